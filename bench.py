@@ -1,0 +1,172 @@
+"""Benchmark: unique formula semantics enumerated per second on one MI355X.
+
+Workload (the medium synthesis problem): 3 atomic propositions, 32 positive
+and 32 negative traces of lengths 8..32, per-proposition bit rates drawn from
+U(0.3, 0.7), labels from a planted formula of cost 11 (seed 1).  The plain
+solve of this problem stops at its minimal cost, which is small, so one
+benchmark step is the whole hot path run exhaustively: encode, seed, and every
+cost level 1..--bound generated, deduplicated and checked (the enumeration
+does not stop at the first separating level).  The specification is uploaded
+once before timing (inputs resident in HBM); each step is one ltlf_run.
+
+value = sum over levels of |U_c| / step time.  Also reported: time to
+formula of the plain solve (upload + enumeration to the minimal cost +
+witness) on the medium problems of seeds 1..4, the roofline of the dominant
+kernel (generation) from HIP events around its launches, and the CPU oracle
+on a bounded sample of the same problem.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(seed: int, bound: int):
+    import oracle
+    import workload
+
+    p = workload.medium(seed)
+    t0 = time.perf_counter()
+    r = oracle.solve(p, cost_bound=bound, exhaust=True)
+    wall = time.perf_counter() - t0
+    uniq = sum(r.level_counts[1: r.levels_done + 1])
+    return {"value": uniq / r.seconds, "unit": "unique semantics/s", "cores": 1, "kind": "oracle",
+            "sample": f"medium seed {seed}, every level to cost {bound} ({uniq} unique CMs, "
+                      f"{r.candidates} candidates), single-threaded C, {r.seconds:.2f} s "
+                      f"enumeration, {wall:.2f} s wall"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--bound", type=int, default=13)
+    ap.add_argument("--workspace-gb", type=float, default=0.0)
+    ap.add_argument("--cpu-bound", type=int, default=9)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ttf", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); independent problems "
+              "shard across GPUs without communication, which this build does not launch.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2504_18943_amd as m
+    import workload
+
+    dev = 0
+    free, total = torch.cuda.mem_get_info(dev)
+    ws = int(args.workspace_gb * (1 << 30)) if args.workspace_gb > 0 else \
+        int(min(free * 0.8, 160 * (1 << 30)))
+    log(f"[bench] workspace {ws / (1 << 30):.1f} GiB of {free / (1 << 30):.1f} GiB free")
+    synth = m.Synthesizer(device=dev, workspace_bytes=ws)
+    p = workload.medium(args.seed)
+    synth.load(p)
+
+    flags = m.FLAG_EXHAUST | m.FLAG_PROFILE
+    for i in range(args.warmup):
+        r = synth.run(args.bound, flags=flags)
+        log(f"[bench] warmup {i}: status {r.status_name} levels {r.levels_done} "
+            f"unique {r.unique_total} {r.enum_ms:.1f} ms")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for i in range(args.steps):
+        r = synth.run(args.bound, flags=flags)
+        results.append(r)
+        log(f"[bench] step {i}: {r.enum_ms:.1f} ms, unique {r.unique_total}, cand {r.candidates}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    last = results[-1]
+    for r in results:
+        assert r.level_counts == last.level_counts, "level counts changed between steps"
+    unique = last.unique_total
+    value = unique / (ms_per_step / 1e3)
+
+    # roofline of the generation kernel: algorithmic bytes = (row bytes + 8)
+    # per candidate (operands amortised; one probe; one verify read or row
+    # write per candidate), over the summed event time of its launches
+    gen_ms = sum(r.gen_ms for r in results) / len(results)
+    launches = last.gen_launches
+    bytes_per_step = last.candidates * (last.row_bytes + 8)
+    achieved = bytes_per_step / (gen_ms / 1e3) / 1e9 if gen_ms > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_generate", "launches_per_step": launches,
+            "avg_launch_ms": round(gen_ms / max(launches, 1), 4),
+            "bytes_per_candidate": last.row_bytes + 8}
+
+    ttf = None
+    if not args.no_ttf:
+        per_seed = {}
+        for s in (1, 2, 3, 4):
+            q = workload.medium(s)
+            times = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                rr = synth.solve(q)  # upload + plain solve + witness
+                times.append((time.perf_counter() - a) * 1e3)
+            per_seed[s] = {"ms": round(statistics.median(times), 3), "min_cost": rr.min_cost,
+                           "formula": rr.formula}
+            log(f"[bench] time-to-formula seed {s}: {per_seed[s]}")
+        ttf = {"median_ms": round(statistics.median(v["ms"] for v in per_seed.values()), 3),
+               "per_seed": per_seed, "includes": "host-to-device upload of the specification"}
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.seed, args.cpu_bound)
+    if cpu:
+        log(f"[bench] cpu baseline {cpu['value']:.0f} unique/s")
+
+    line = {
+        "metric": "unique formula semantics enumerated/sec",
+        "value": round(value, 1),
+        "unit": "unique semantics/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"medium synthesis problem (3 props, 32+32 traces, lengths 8-32, "
+                               f"planted cost 11, seed {args.seed}); every cost level 1..{args.bound} "
+                               f"enumerated, deduplicated and checked",
+                   "seed": args.seed, "cost_bound": args.bound, "row_bytes": last.row_bytes,
+                   "unique_per_level": last.level_counts[1:last.levels_done + 1],
+                   "candidates": last.candidates, "deferred": last.deferred,
+                   "status": last.status_name, "min_cost": last.min_cost},
+        "time_to_formula": ttf,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    synth.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

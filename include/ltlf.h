@@ -1,0 +1,211 @@
+/*
+ * ltlf.h -- C ABI of the MI355X LTLf synthesiser.
+ *
+ * Problem (paper, "Synthesising linear temporal logic formulae from
+ * examples"): given finite example traces over atomic propositions
+ * p_0..p_{m-1}, each labelled positive or negative, find a formula of minimal
+ * cost over p_i, not, and, or, X, F, G, U that holds at position 0 of every
+ * positive trace and fails at position 0 of every negative trace
+ * ("phi separates (P, N)").  Cost is the sum of node costs; with unit costs it
+ * is the formula size.
+ *
+ * Method (paper, "Program synthesis" and "Parallel enumeration of LTLf
+ * formulae on GPUs"): bottom-up enumeration by cost, one level per cost c,
+ * over formula semantics instead of syntax.  Each candidate is represented by
+ * its characteristic matrix (CM): one bit per (trace, position), set iff the
+ * formula holds there.  A CM is kept only if no cheaper or equally cheap
+ * formula with the same CM was kept before (observational equivalence), so
+ * U_c, the kept CMs of level c, are exactly the CMs whose cheapest formula
+ * costs c.
+ *
+ * Semantics (finite traces): X is strong (false at the last position), F, G
+ * and U are reflexive (phi U psi holds at i if psi holds at some j >= i and
+ * phi holds on [i, j)).
+ *
+ * Conventions for every call:
+ *   - the return value is an ltlf_status; nothing else signals errors and no
+ *     C++ exception crosses this boundary;
+ *   - pointers named host_* or documented as host memory are read or written
+ *     only during the call; the caller keeps ownership of every buffer it
+ *     passes;
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream); all
+ *     device work of a call is enqueued on it, and calls that return host
+ *     results synchronise it before returning;
+ *   - a context is used by one host thread at a time.
+ */
+#ifndef LTLF_H
+#define LTLF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LTLF_OK = 0,         /* a separating formula of minimal cost was found */
+    LTLF_NOT_FOUND = 1,  /* no separating formula of cost <= bound */
+    LTLF_CAPACITY = 2,   /* the store filled before the bound; levels_done is exact */
+    LTLF_EINVAL = -1,    /* invalid argument (see each call) */
+    LTLF_ENOMEM = -2,    /* device memory could not be obtained */
+    LTLF_EDEVICE = -3,   /* a HIP runtime call failed */
+    LTLF_EBUFSZ = -4,    /* a caller buffer is too small; the needed size is reported */
+    LTLF_ESTATE = -5     /* call out of order (e.g. run before load) */
+} ltlf_status;
+
+/* Operator indices into ltlf_costs.op_cost. */
+typedef enum {
+    LTLF_NOT = 0,
+    LTLF_X = 1,
+    LTLF_F = 2,
+    LTLF_G = 3,
+    LTLF_AND = 4,
+    LTLF_OR = 5,
+    LTLF_U = 6,
+    LTLF_NUM_OPS = 7
+} ltlf_op;
+
+/* Node costs.  atom_cost >= 1; op_cost[k] >= 1 enables operator k with that
+ * cost, 0 disables it. */
+typedef struct {
+    uint32_t atom_cost;
+    uint32_t op_cost[LTLF_NUM_OPS];
+} ltlf_costs;
+
+/* The specification (P, N), host memory.
+ *   n_props  : 1..32 atomic propositions p_0..p_{n_props-1};
+ *   n_traces : >= 1; the caller's order fixes the trace order inside a CM;
+ *   lengths  : n_traces entries, each >= 1;
+ *   letters  : sum(lengths) entries, trace after trace, position 0 first;
+ *              bit p of an entry is set iff p holds at that position (bits at
+ *              or above n_props must be clear);
+ *   positive : n_traces entries; nonzero = P, zero = N. */
+typedef struct {
+    uint32_t n_props;
+    uint32_t n_traces;
+    const uint32_t *lengths;
+    const uint32_t *letters;
+    const uint8_t *positive;
+} ltlf_spec;
+
+/* Flags for ltlf_run / ltlf_solve. */
+#define LTLF_FLAG_EXHAUST 0x1u /* keep enumerating complete levels up to the
+                                  bound after the first separating level; the
+                                  minimal cost and witness are unchanged */
+#define LTLF_FLAG_PROFILE 0x2u /* time every generation and verification launch
+                                  with HIP events on the run's stream and
+                                  report the sums (gen_ms, verify_ms) */
+#define LTLF_FLAG_DEBUG_WEAK_HASH 0x100u /* test hook: keep 6 bits of every hash,
+                                  so all candidates share a few slots and one
+                                  tag; exercises the verify/defer paths */
+
+/* Result of a run.  level_counts and formula are caller buffers (host). */
+typedef struct {
+    ltlf_status status;       /* OK, NOT_FOUND or CAPACITY */
+    uint32_t min_cost;        /* valid iff status == OK */
+    uint32_t levels_done;     /* highest completely enumerated and stored level */
+    uint32_t overflow_level;  /* level that did not fit the store, 0 if none */
+    uint64_t *level_counts;   /* in: buffer of level_counts_len entries or NULL;
+                                 out: entry c = |U_c| for c <= levels_done, 0 above */
+    uint32_t level_counts_len;
+    char *formula;            /* in: buffer or NULL; out: witness in prefix tokens,
+                                 e.g. "! U p1 p0"; tokens p<k>, !, X, F, G, &, |, U */
+    uint64_t formula_cap;     /* in: capacity of formula in bytes */
+    uint64_t formula_len;     /* out: bytes needed including the NUL */
+    uint64_t candidates;      /* out: candidates generated (after pruning) */
+    uint64_t unique_total;    /* out: sum of |U_c| over stored levels */
+    uint64_t deferred;        /* out: candidates whose check was deferred to the
+                                 verification kernel (statistics) */
+    uint32_t row_bytes;       /* out: bytes of one stored CM (4 * words) */
+    uint32_t gen_launches;    /* out: generation kernel launches */
+    uint32_t verify_launches; /* out: verification kernel launches */
+    uint32_t pad;
+    double enum_ms;           /* out: stream time of the whole run (events) */
+    double gen_ms;            /* out: summed generation kernel time (PROFILE) */
+    double verify_ms;         /* out: summed verification kernel time (PROFILE) */
+} ltlf_result;
+
+typedef struct ltlf_ctx ltlf_ctx;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes is the device
+ * memory the context allocates for itself at the first load (0 = 2 GiB,
+ * values below 64 MiB are raised to 64 MiB); it is ignored once a workspace
+ * is set.  EINVAL: out == NULL or
+ * no such device.  EDEVICE: the device cannot be selected. */
+ltlf_status ltlf_ctx_create(int device, uint64_t hbm_budget_bytes, ltlf_ctx **out);
+
+/* Use caller-owned device memory (e.g. a framework allocation) as the
+ * context's only workspace instead of allocating.  dev_ptr must be 256-byte
+ * aligned device memory on the context's device, valid until the context is
+ * destroyed or another workspace is set; the context never frees it.
+ * EINVAL: null pointer, misalignment, or bytes < 64 MiB. */
+ltlf_status ltlf_ctx_set_workspace(ltlf_ctx *ctx, void *dev_ptr, uint64_t bytes);
+
+/* Limit the store to at most max_rows characteristic matrices (0 = as many
+ * as fit in the workspace).  The level that would need more is finished
+ * check-only: its candidates are still tested for separation, so a minimal
+ * formula of that cost is still found, but the level is not stored and the
+ * run ends there (status CAPACITY unless a separating formula was found).
+ * Takes effect at the next ltlf_run.  EINVAL: ctx == NULL. */
+ltlf_status ltlf_ctx_set_row_limit(ltlf_ctx *ctx, uint64_t max_rows);
+
+/* Destroy a context and free the memory it allocated.  NULL is ignored. */
+void ltlf_ctx_destroy(ltlf_ctx *ctx);
+
+/* Validate a specification and copy it to the device (stream-ordered; the
+ * call synchronises the stream before returning, so host buffers may be
+ * reused at once).  The uploaded specification stays resident for any number
+ * of ltlf_run calls.  EINVAL: ctx/spec/arrays NULL, n_props outside 1..32,
+ * n_traces == 0, a zero length, or a letter with a bit >= n_props. */
+ltlf_status ltlf_load(ltlf_ctx *ctx, const ltlf_spec *spec, void *stream);
+
+/* Enumerate levels c = 1..cost_bound for the loaded specification (encode
+ * atoms and masks, seed, and for each level generate, deduplicate and check
+ * every candidate), then write the witness formula.  Without
+ * LTLF_FLAG_EXHAUST the run stops after the first level that contains a
+ * separating formula (that level is still completed).  Returns res->status
+ * for OK/NOT_FOUND/CAPACITY.  EINVAL: NULL ctx/costs/res, atom_cost == 0,
+ * cost_bound < atom_cost or cost_bound > 1024.  ESTATE: nothing loaded.
+ * EBUFSZ: res->formula non-NULL and too small (formula_len reports the need;
+ * all other fields are valid). */
+ltlf_status ltlf_run(ltlf_ctx *ctx, const ltlf_costs *costs, uint32_t cost_bound, uint32_t flags,
+                     void *stream, ltlf_result *res);
+
+/* ltlf_load followed by ltlf_run. */
+ltlf_status ltlf_solve(ltlf_ctx *ctx, const ltlf_spec *spec, const ltlf_costs *costs,
+                       uint32_t cost_bound, uint32_t flags, void *stream, ltlf_result *res);
+
+/* Export CMs first .. first+count-1 (clipped to |U_cost|) of U_cost from the
+ * last run in the canonical layout: per CM, trace by trace in the caller's
+ * order, positions 0..n_t-1 as consecutive bits, least significant bit first,
+ * packed into uint64 words, tail zero-padded; *words_per_cm =
+ * ceil(sum(lengths) / 64).  The order of CMs within a level is unspecified
+ * but fixed until the next run.  *n_cms receives the number of CMs exported
+ * (or, with host_buf == NULL, that would be exported).  EBUFSZ: cap_words <
+ * n_cms * words_per_cm.  EINVAL: cost 0 or above the last run's levels_done.
+ * ESTATE: no completed run. */
+ltlf_status ltlf_export_level(ltlf_ctx *ctx, uint32_t cost, uint64_t first, uint64_t count,
+                              uint64_t *host_buf, uint64_t cap_words, uint64_t *n_cms,
+                              uint64_t *words_per_cm);
+
+/* Formula (prefix tokens) of the index-th CM of U_cost in the order used by
+ * ltlf_export_level.  *need receives the bytes needed including the NUL.
+ * EBUFSZ: buf too small.  EINVAL: cost or index out of range. */
+ltlf_status ltlf_formula_of(ltlf_ctx *ctx, uint32_t cost, uint64_t index, char *buf, uint64_t cap,
+                            uint64_t *need);
+
+/* Description of the last failure of a call on this context (which step or
+ * HIP call failed and the HIP error string); empty after a successful
+ * ltlf_load/ltlf_run.  The string is owned by the context and valid until
+ * the next call on it.  Never NULL. */
+const char *ltlf_ctx_last_error(const ltlf_ctx *ctx);
+
+/* Static description of a status code; never NULL. */
+const char *ltlf_status_str(ltlf_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LTLF_H */

@@ -1,0 +1,16 @@
+"""MI355X-native LTLf synthesiser: bottom-up enumeration of formula semantics.
+
+The compute path is libltlf.so (HIP kernels for gfx950 behind the C ABI in
+include/ltlf.h); this package only binds it.
+"""
+from .ltlf import (Synthesizer, Result, LtlfError, load_library, ltlf_status_str, ltlf_ctx_create,
+                   ltlf_ctx_last_error,
+                   ltlf_ctx_set_workspace, ltlf_ctx_set_row_limit, ltlf_ctx_destroy, ltlf_load,
+                   ltlf_run, ltlf_solve, ltlf_export_level, ltlf_formula_of, FLAG_EXHAUST, FLAG_PROFILE,
+                   FLAG_WEAK_HASH, UNIT_ALL, STATUS_NAMES, LIB_PATH)
+
+__all__ = ["Synthesizer", "Result", "LtlfError", "load_library", "ltlf_status_str",
+           "ltlf_ctx_create", "ltlf_ctx_last_error", "ltlf_ctx_set_workspace", "ltlf_ctx_set_row_limit",
+           "ltlf_ctx_destroy", "ltlf_load", "ltlf_run", "ltlf_solve", "ltlf_export_level",
+           "ltlf_formula_of", "FLAG_EXHAUST", "FLAG_PROFILE", "FLAG_WEAK_HASH", "UNIT_ALL", "STATUS_NAMES",
+           "LIB_PATH"]

@@ -1,0 +1,701 @@
+// Host driver and C ABI of the LTLf synthesiser (see include/ltlf.h).
+//
+// The driver owns the level loop of the bottom-up enumeration (paper,
+// "Program synthesis": language cache by size, every level built from the
+// cheaper ones) and everything around the kernels: validation, the device
+// memory plan, the per-level block lists, launch chunking, deferral
+// resolution, table growth, and witness reconstruction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ltlf.h"
+#include "ltlf_internal.h"
+
+using namespace ltlf;
+
+namespace {
+
+constexpr uint64_t kMinWorkspace = 64ull << 20;
+constexpr uint64_t kDefaultBudget = 2ull << 30;
+constexpr uint32_t kMaxBound = 1024;
+constexpr uint32_t kMaxTokens = kMaxBound + 1;
+constexpr uint64_t kStagingBytes = 8ull << 20;
+constexpr uint64_t kMinTableSlots = 1ull << 12;
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+inline uint64_t pow2_ceil(uint64_t x) {
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+inline uint64_t pow2_floor(uint64_t x) {
+    uint64_t p = 1;
+    while ((p << 1) <= x && (p << 1) != 0) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+struct ltlf_ctx {
+    int device = 0;
+    uint64_t budget = kDefaultBudget;
+    char* ws = nullptr;
+    uint64_t ws_bytes = 0;
+    bool own_ws = false;
+
+    // loaded specification
+    bool loaded = false;
+    uint32_t n_props = 0, n_traces = 0;
+    uint64_t n_pos = 0;   // sum of lengths
+    uint64_t n_bits = 0;  // sum of (length + 1)
+    uint32_t Wp = 0;
+
+    // device regions
+    uint32_t *d_letters = nullptr, *d_lengths = nullptr, *d_pos_off = nullptr, *d_seg_off = nullptr;
+    uint8_t* d_positive = nullptr;
+    uint32_t* d_canon = nullptr;
+    uint32_t *d_V = nullptr, *d_S = nullptr, *d_P0 = nullptr, *d_atoms = nullptr;
+    unsigned long long* d_ctr = nullptr;
+    uint32_t* d_tokens = nullptr;
+    uint64_t* d_stage = nullptr;
+    Store st{};
+    uint64_t table_max = 0;  // slots available
+    uint64_t plan_cap = 0;   // rows that fit the workspace
+    uint64_t row_limit = 0;  // caller's limit (0 = none)
+
+    // host mirrors
+    unsigned long long* h_ctr = nullptr;  // pinned
+    uint32_t* h_tokens = nullptr;         // pinned
+
+    // last run
+    bool ran = false;
+    uint32_t levels_done = 0;
+    std::vector<uint64_t> lstart, lcount;
+
+    // description of the last failure (empty after a successful call)
+    std::string err;
+};
+
+namespace {
+
+// Failure helpers: every error path records what failed in ctx->err.
+ltlf_status fail(ltlf_ctx* c, ltlf_status s, const char* what, hipError_t e = hipSuccess) {
+    if (c) {
+        c->err = what;
+        if (e != hipSuccess) {
+            c->err += ": ";
+            c->err += hipGetErrorString(e);
+        }
+    }
+    return s;
+}
+#define TRY_HIP(x)                                                   \
+    do {                                                             \
+        const hipError_t e_ = (x);                                   \
+        if (e_ != hipSuccess) return fail(c, LTLF_EDEVICE, #x, e_);  \
+    } while (0)
+#define TRY(x)                                \
+    do {                                      \
+        ltlf_status s_ = (x);                 \
+        if (s_ != LTLF_OK) return s_;         \
+    } while (0)
+
+
+// Carves the workspace.  Fixed regions first, then deferral lists, then the
+// row store and the table, which take what is left.
+ltlf_status plan_memory_impl(ltlf_ctx* c);
+ltlf_status plan_memory(ltlf_ctx* c) {
+    const ltlf_status s = plan_memory_impl(c);
+    if (s != LTLF_OK) return fail(c, s, "workspace too small for this specification");
+    return s;
+}
+ltlf_status plan_memory_impl(ltlf_ctx* c) {
+    const uint64_t T = c->n_traces, Wp = c->Wp;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t o = align_up(off, 256);
+        off = o + bytes;
+        return c->ws + o;
+    };
+    c->d_letters = reinterpret_cast<uint32_t*>(take(4 * c->n_pos));
+    c->d_lengths = reinterpret_cast<uint32_t*>(take(4 * T));
+    c->d_pos_off = reinterpret_cast<uint32_t*>(take(4 * (T + 1)));
+    c->d_seg_off = reinterpret_cast<uint32_t*>(take(4 * (T + 1)));
+    c->d_positive = reinterpret_cast<uint8_t*>(take(T));
+    c->d_canon = reinterpret_cast<uint32_t*>(take(4 * c->n_pos));
+    c->d_V = reinterpret_cast<uint32_t*>(take(4 * Wp));
+    c->d_S = reinterpret_cast<uint32_t*>(take(4 * Wp));
+    c->d_P0 = reinterpret_cast<uint32_t*>(take(4 * Wp));
+    c->d_atoms = reinterpret_cast<uint32_t*>(take(4 * Wp * c->n_props));
+    c->d_ctr = reinterpret_cast<unsigned long long*>(take(8 * C_NUM));
+    c->d_tokens = reinterpret_cast<uint32_t*>(take(4 * (1 + kMaxTokens + 3 * (kMaxTokens + 1))));
+    c->d_stage = reinterpret_cast<uint64_t*>(take(kStagingBytes));
+    off = align_up(off, 256);
+    if (off >= c->ws_bytes) return LTLF_ENOMEM;
+    uint64_t rest = c->ws_bytes - off;
+
+    uint64_t d0 = std::min<uint64_t>(std::max<uint64_t>(rest / 64 / 16, 1ull << 16), 1ull << 26);
+    uint64_t d1 = std::max<uint64_t>(d0 / 16, 4096);
+    if ((d0 + d1) * 16 + 4096 >= rest) return LTLF_ENOMEM;
+    c->st.def0 = reinterpret_cast<uint4*>(take(16 * d0));
+    c->st.def1 = reinterpret_cast<uint4*>(take(16 * d1));
+    c->st.def0_cap = d0;
+    c->st.def1_cap = d1;
+    off = align_up(off, 256);
+    if (off >= c->ws_bytes) return LTLF_ENOMEM;
+    rest = c->ws_bytes - off;
+
+    const uint64_t per_row = 4 * Wp + 16 + 8;
+    uint64_t cap0 = rest / (per_row + 16);
+    uint64_t slots = pow2_floor(std::max<uint64_t>(2 * cap0, 2));
+    while (slots > 2 && slots * 8 > rest) slots >>= 1;
+    uint64_t cap = std::min<uint64_t>((rest - slots * 8 - 3 * 256) / per_row, slots / 2);
+    cap = std::min<uint64_t>(cap, 0xFFFFFFF0ull);
+    if (cap < c->n_props + 16 || slots < kMinTableSlots) return LTLF_ENOMEM;
+    c->st.table = reinterpret_cast<uint64_t*>(take(8 * slots));
+    c->st.rows = reinterpret_cast<uint32_t*>(take(4 * Wp * cap));
+    c->st.meta = reinterpret_cast<uint4*>(take(16 * cap));
+    c->st.rhash = reinterpret_cast<uint64_t*>(take(8 * cap));
+    if (off > c->ws_bytes) return LTLF_ENOMEM;
+    c->table_max = slots;
+    c->plan_cap = cap;
+    c->st.cap = cap;
+    c->st.V = c->d_V;
+    c->st.S = c->d_S;
+    c->st.P0 = c->d_P0;
+    c->st.atoms = c->d_atoms;
+    c->st.ctr = c->d_ctr;
+    c->st.Wp = c->Wp;
+    c->st.n_props = c->n_props;
+    c->st.hmask = ~0ull;
+    return LTLF_OK;
+}
+
+ltlf_status ensure_workspace(ltlf_ctx* c) {
+    if (c->ws) return LTLF_OK;
+    TRY_HIP(hipSetDevice(c->device));
+    void* p = nullptr;
+    if (hipMalloc(&p, c->budget) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, LTLF_ENOMEM, "hipMalloc of the workspace failed");
+    }
+    c->ws = static_cast<char*>(p);
+    c->ws_bytes = c->budget;
+    c->own_ws = true;
+    return LTLF_OK;
+}
+
+const char* op_token(uint32_t op) {
+    switch (op) {
+    case OP_NOT: return "!";
+    case OP_X: return "X";
+    case OP_F: return "F";
+    case OP_G: return "G";
+    case OP_AND: return "&";
+    case OP_OR: return "|";
+    case OP_U: return "U";
+    default: return "?";
+    }
+}
+
+// Runs the formula kernel from a root derivation and renders prefix tokens.
+ltlf_status render_formula(ltlf_ctx* c, uint32_t op, uint32_t a, uint32_t b, hipStream_t s,
+                           std::string& out) {
+    TRY_HIP(launch_formula(c->st.meta, op, a, b, kMaxTokens, c->d_tokens, s));
+    TRY_HIP(hipMemcpyAsync(c->h_tokens, c->d_tokens, 4 * (1 + kMaxTokens), hipMemcpyDeviceToHost, s));
+    TRY_HIP(hipStreamSynchronize(s));
+    const uint32_t n = c->h_tokens[0];
+    if (n > kMaxTokens) return fail(c, LTLF_EDEVICE, "witness formula longer than the token buffer");
+    out.clear();
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t t = c->h_tokens[1 + i];
+        const uint32_t top = t >> 24;
+        if (i) out.push_back(' ');
+        if (top == OP_ATOM) {
+            out += "p" + std::to_string(t & 0xFFFFFFu);
+        } else {
+            out += op_token(top);
+        }
+    }
+    return LTLF_OK;
+}
+
+struct LevelPlan {
+    std::vector<Seg> segs;
+    std::vector<uint64_t> cand_per_tile;
+    uint64_t cand_ub = 0;
+};
+
+// Blocks of level c: atoms, unary operators over U_{c-k}, and for every pair
+// of levels i <= j the binary operators whose cost closes the sum to c.  The
+// larger operand level goes to the lanes; a pair (a, b) yields a&b, a|b,
+// aUb and bUa, so each unordered pair of representatives is visited once.
+LevelPlan plan_level(const ltlf_ctx* c, const ltlf_costs* k, uint32_t lev) {
+    LevelPlan p;
+    auto cnt = [&](uint32_t i) -> uint64_t { return i < c->lcount.size() ? c->lcount[i] : 0; };
+    if (lev == k->atom_cost) {
+        Seg g{};
+        g.kind = SEG_ATOM;
+        g.nb = c->n_props;
+        g.tiles = 1;
+        p.segs.push_back(g);
+        p.cand_per_tile.push_back(c->n_props);
+    }
+    // unary: group operators by source level
+    const uint32_t umask[4] = {M_NOT, M_X, M_F, M_G};
+    for (uint32_t src = 1; src < lev; ++src) {
+        uint32_t mask = 0;
+        for (int o = 0; o < 4; ++o)
+            if (k->op_cost[o] && k->op_cost[o] + src == lev) mask |= umask[o];
+        if (!mask || cnt(src) == 0) continue;
+        Seg g{};
+        g.kind = SEG_UNARY;
+        g.opmask = mask;
+        g.b0 = c->lstart[src];
+        g.nb = cnt(src);
+        g.tiles = (g.nb + kLanes - 1) / kLanes;
+        p.segs.push_back(g);
+        p.cand_per_tile.push_back((uint64_t)kLanes * __builtin_popcount(mask));
+    }
+    // binary
+    for (uint32_t i = 1; i < lev; ++i) {
+        for (uint32_t j = i; i + j < lev; ++j) {
+            uint32_t mask = 0;
+            if (k->op_cost[LTLF_AND] && i + j + k->op_cost[LTLF_AND] == lev) mask |= M_AND;
+            if (k->op_cost[LTLF_OR] && i + j + k->op_cost[LTLF_OR] == lev) mask |= M_OR;
+            if (k->op_cost[LTLF_U] && i + j + k->op_cost[LTLF_U] == lev) mask |= M_UAB | M_UBA;
+            if (!mask || cnt(i) == 0 || cnt(j) == 0) continue;
+            Seg g{};
+            g.kind = SEG_PAIR;
+            g.opmask = mask;
+            if (i == j) {
+                const uint64_t n = cnt(i);
+                if (n < 2) continue;
+                g.tri = 1;
+                g.a0 = g.b0 = c->lstart[i];
+                g.na = g.nb = n;
+                const uint64_t K = (n + kLanes - 1) / kLanes;
+                const uint64_t ta = (n + kTileA - 1) / kTileA;
+                g.tiles = 8ull * (K - 1) * K + ta;
+            } else {
+                // lanes take the larger level
+                uint32_t la = i, lb = j;
+                if (cnt(i) > cnt(j)) std::swap(la, lb);
+                g.a0 = c->lstart[la];
+                g.na = cnt(la);
+                g.b0 = c->lstart[lb];
+                g.nb = cnt(lb);
+                g.tiles = ((g.na + kTileA - 1) / kTileA) * ((g.nb + kLanes - 1) / kLanes);
+            }
+            p.segs.push_back(g);
+            p.cand_per_tile.push_back((uint64_t)kLanes * kTileA * __builtin_popcount(mask));
+        }
+    }
+    for (size_t s = 0; s < p.segs.size(); ++s) p.cand_ub += p.segs[s].tiles * p.cand_per_tile[s];
+    return p;
+}
+
+// Grows the table (clear + re-insert every stored row) so that it keeps at
+// least two slots per row after `extra` more rows.
+ltlf_status ensure_table(ltlf_ctx* c, uint64_t rows, uint64_t extra, hipStream_t s) {
+    const uint64_t need = std::min<uint64_t>(pow2_ceil(std::max<uint64_t>(2 * (rows + extra), kMinTableSlots)),
+                                             c->table_max);
+    if (need <= c->st.tmask + 1) return LTLF_OK;
+    c->st.tmask = need - 1;
+    TRY_HIP(launch_fill_u64(c->st.table, need, ~0ull, s));
+    TRY_HIP(launch_rehash(c->st, rows, s));
+    return LTLF_OK;
+}
+
+ltlf_status read_counters(ltlf_ctx* c, hipStream_t s) {
+    TRY_HIP(hipMemcpyAsync(c->h_ctr, c->d_ctr, 8 * C_NUM, hipMemcpyDeviceToHost, s));
+    TRY_HIP(hipStreamSynchronize(s));
+    return LTLF_OK;
+}
+
+// Events around generation/verification launches: mark() records one event;
+// collect() adds the gaps (gen = mark0..mark1, verify = mark1..mark2, per
+// launch triple) after the stream has been synchronised.
+struct Profiler {
+    ltlf_ctx* c = nullptr;
+    std::vector<hipEvent_t> ev;
+    size_t used = 0;
+    ltlf_status mark(hipStream_t s) {
+        if (used == ev.size()) {
+            hipEvent_t e;
+            TRY_HIP(hipEventCreate(&e));
+            ev.push_back(e);
+        }
+        TRY_HIP(hipEventRecord(ev[used++], s));
+        return LTLF_OK;
+    }
+    ltlf_status collect(double& gen_ms, double& ver_ms) {
+        for (size_t i = 0; i + 2 < used; i += 3) {
+            float a = 0.f, b = 0.f;
+            TRY_HIP(hipEventElapsedTime(&a, ev[i], ev[i + 1]));
+            TRY_HIP(hipEventElapsedTime(&b, ev[i + 1], ev[i + 2]));
+            gen_ms += a;
+            ver_ms += b;
+        }
+        used = 0;
+        return LTLF_OK;
+    }
+    ~Profiler() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+ltlf_status validate_spec(const ltlf_spec* sp) {
+    if (!sp || !sp->lengths || !sp->letters || !sp->positive) return LTLF_EINVAL;
+    if (sp->n_props < 1 || sp->n_props > 32 || sp->n_traces < 1) return LTLF_EINVAL;
+    uint64_t total = 0;
+    for (uint32_t t = 0; t < sp->n_traces; ++t) {
+        if (sp->lengths[t] < 1) return LTLF_EINVAL;
+        total += sp->lengths[t];
+    }
+    const uint32_t bad = sp->n_props == 32 ? 0u : ~((1u << sp->n_props) - 1u);
+    for (uint64_t i = 0; i < total; ++i)
+        if (sp->letters[i] & bad) return LTLF_EINVAL;
+    return LTLF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ltlf_status_str(ltlf_status s) {
+    switch (s) {
+    case LTLF_OK: return "ok";
+    case LTLF_NOT_FOUND: return "no separating formula within the cost bound";
+    case LTLF_CAPACITY: return "store full before the cost bound";
+    case LTLF_EINVAL: return "invalid argument";
+    case LTLF_ENOMEM: return "out of device memory";
+    case LTLF_EDEVICE: return "HIP runtime error";
+    case LTLF_EBUFSZ: return "buffer too small";
+    case LTLF_ESTATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+ltlf_status ltlf_ctx_create(int device, uint64_t hbm_budget_bytes, ltlf_ctx** out) {
+    if (!out) return LTLF_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return LTLF_EDEVICE;
+    if (device < 0 || device >= n) return LTLF_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return LTLF_EDEVICE;
+    ltlf_ctx* c = new (std::nothrow) ltlf_ctx();
+    if (!c) return LTLF_ENOMEM;
+    c->device = device;
+    c->budget = hbm_budget_bytes ? std::max<uint64_t>(hbm_budget_bytes, kMinWorkspace) : kDefaultBudget;
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_ctr), 8 * C_NUM, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->h_tokens), 4 * (1 + kMaxTokens), hipHostMallocDefault) !=
+            hipSuccess) {
+        if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+        delete c;
+        return LTLF_EDEVICE;
+    }
+    *out = c;
+    return LTLF_OK;
+}
+
+ltlf_status ltlf_ctx_set_workspace(ltlf_ctx* c, void* dev_ptr, uint64_t bytes) {
+    if (!c || !dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255u) || bytes < kMinWorkspace)
+        return LTLF_EINVAL;
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    c->ws = static_cast<char*>(dev_ptr);
+    c->ws_bytes = bytes;
+    c->own_ws = false;
+    c->loaded = false;
+    c->ran = false;
+    return LTLF_OK;
+}
+
+const char* ltlf_ctx_last_error(const ltlf_ctx* c) {
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+ltlf_status ltlf_ctx_set_row_limit(ltlf_ctx* c, uint64_t max_rows) {
+    if (!c) return LTLF_EINVAL;
+    c->row_limit = max_rows;
+    return LTLF_OK;
+}
+
+void ltlf_ctx_destroy(ltlf_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+    if (c->h_tokens) (void)hipHostFree(c->h_tokens);
+    delete c;
+}
+
+ltlf_status ltlf_load(ltlf_ctx* c, const ltlf_spec* sp, void* stream) {
+    if (!c) return LTLF_EINVAL;
+    c->err.clear();
+    TRY(validate_spec(sp));
+    TRY_HIP(hipSetDevice(c->device));
+    TRY(ensure_workspace(c));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint32_t T = sp->n_traces;
+    std::vector<uint32_t> pos_off(T + 1), seg_off(T + 1);
+    for (uint32_t t = 0; t < T; ++t) {
+        pos_off[t + 1] = pos_off[t] + sp->lengths[t];
+        seg_off[t + 1] = seg_off[t] + sp->lengths[t] + 1;
+    }
+    c->loaded = false;
+    c->ran = false;
+    c->n_props = sp->n_props;
+    c->n_traces = T;
+    c->n_pos = pos_off[T];
+    c->n_bits = seg_off[T];
+    c->Wp = (uint32_t)align_up((c->n_bits + 31) / 32, 4);
+    TRY(plan_memory(c));
+    // canonical bit g (trace t, position k) -> packed bit of that position
+    std::vector<uint32_t> canon(c->n_pos);
+    for (uint32_t t = 0; t < T; ++t)
+        for (uint32_t k = 0; k < sp->lengths[t]; ++k)
+            canon[pos_off[t] + k] = seg_off[t] + (sp->lengths[t] - 1 - k);
+    TRY_HIP(hipMemcpyAsync(c->d_letters, sp->letters, 4 * c->n_pos, hipMemcpyHostToDevice, s));
+    TRY_HIP(hipMemcpyAsync(c->d_lengths, sp->lengths, 4ull * T, hipMemcpyHostToDevice, s));
+    TRY_HIP(hipMemcpyAsync(c->d_pos_off, pos_off.data(), 4ull * (T + 1), hipMemcpyHostToDevice, s));
+    TRY_HIP(hipMemcpyAsync(c->d_seg_off, seg_off.data(), 4ull * (T + 1), hipMemcpyHostToDevice, s));
+    TRY_HIP(hipMemcpyAsync(c->d_positive, sp->positive, T, hipMemcpyHostToDevice, s));
+    TRY_HIP(hipMemcpyAsync(c->d_canon, canon.data(), 4 * c->n_pos, hipMemcpyHostToDevice, s));
+    TRY_HIP(hipStreamSynchronize(s));
+    c->loaded = true;
+    return LTLF_OK;
+}
+
+ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t flags, void* stream,
+                     ltlf_result* res) {
+    if (!c || !k || !res) return LTLF_EINVAL;
+    c->err.clear();
+    if (k->atom_cost == 0 || bound < k->atom_cost || bound > kMaxBound) return LTLF_EINVAL;
+    if (!c->loaded) return LTLF_ESTATE;
+    TRY_HIP(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool exhaust = (flags & LTLF_FLAG_EXHAUST) != 0;
+
+    res->status = LTLF_NOT_FOUND;
+    res->min_cost = 0;
+    res->levels_done = 0;
+    res->overflow_level = 0;
+    res->formula_len = 0;
+    res->candidates = 0;
+    res->unique_total = 0;
+    res->deferred = 0;
+    res->row_bytes = 4 * c->Wp;
+    res->gen_launches = 0;
+    res->verify_launches = 0;
+    res->enum_ms = 0.0;
+    res->gen_ms = 0.0;
+    res->verify_ms = 0.0;
+    const bool profile = (flags & LTLF_FLAG_PROFILE) != 0;
+    Profiler prof;
+    prof.c = c;
+    c->ran = false;
+    c->lstart.assign(bound + 1, 0);
+    c->lcount.assign(bound + 1, 0);
+    c->st.cap = c->row_limit ? std::min(c->plan_cap, c->row_limit) : c->plan_cap;
+    c->st.hmask = (flags & LTLF_FLAG_DEBUG_WEAK_HASH) ? 0x3Full : ~0ull;
+
+    hipEvent_t e0, e1;
+    TRY_HIP(hipEventCreate(&e0));
+    TRY_HIP(hipEventCreate(&e1));
+    struct EventGuard {
+        hipEvent_t a, b;
+        ~EventGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+    TRY_HIP(hipEventRecord(e0, s));
+
+    // a1: encode atoms and masks; reset counters and the initial table
+    TRY_HIP(launch_encode(c->d_letters, c->d_lengths, c->d_pos_off, c->d_seg_off, c->d_positive,
+                          c->n_traces, c->n_props, c->Wp, c->d_V, c->d_S, c->d_P0, c->d_atoms, s));
+    TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(c->d_ctr), C_NUM, 0, s));
+    const uint64_t slots0 = std::min<uint64_t>(pow2_ceil(std::max<uint64_t>(4ull * c->n_props, kMinTableSlots)),
+                                               c->table_max);
+    c->st.tmask = slots0 - 1;
+    TRY_HIP(launch_fill_u64(c->st.table, slots0, ~0ull, s));
+
+    uint64_t rows = 0;
+    ltlf_status status = LTLF_NOT_FOUND;
+    uint32_t wit_op = 0, wit_a = 0, wit_b = 0;
+    uint64_t candidates = 0;
+
+    for (uint32_t lev = 1; lev <= bound; ++lev) {
+        c->lstart[lev] = rows;
+        LevelPlan p = plan_level(c, k, lev);
+        if (p.segs.empty()) {
+            res->levels_done = lev;
+            continue;
+        }
+        TRY(ensure_table(c, rows, std::min<uint64_t>(p.cand_ub, c->st.cap - rows), s));
+        // launch in groups of at most kMaxSegs segments, each split into
+        // chunks whose candidates fit the deferral list
+        for (size_t g0 = 0; g0 < p.segs.size(); g0 += kMaxSegs) {
+            const size_t g1 = std::min(p.segs.size(), g0 + kMaxSegs);
+            SegTable t{};
+            t.n = (uint32_t)(g1 - g0);
+            t.first[0] = 0;
+            for (size_t q = g0; q < g1; ++q) {
+                t.seg[q - g0] = p.segs[q];
+                t.first[q - g0 + 1] = t.first[q - g0] + p.segs[q].tiles;
+            }
+            uint64_t tile = 0;
+            const uint64_t total = t.first[t.n];
+            while (tile < total) {
+                uint64_t budget = c->st.def0_cap, end = tile;
+                uint32_t si = 0;
+                while (end < total) {
+                    while (t.first[si + 1] <= end) ++si;
+                    const uint64_t per = p.cand_per_tile[g0 + si];
+                    const uint64_t seg_end = t.first[si + 1];
+                    const uint64_t fit = budget / per;
+                    if (fit == 0) break;
+                    const uint64_t take = std::min<uint64_t>(fit, seg_end - end);
+                    end += take;
+                    budget -= take * per;
+                }
+                if (end == tile) return fail(c, LTLF_EDEVICE, "a tile exceeds the deferral list");
+                t.tile_begin = tile;
+                t.tile_end = end;
+                if (profile) TRY(prof.mark(s));
+                TRY_HIP(launch_generate(c->st, t, s));
+                if (profile) TRY(prof.mark(s));
+                TRY_HIP(launch_verify_deferred(c->st, s));
+                if (profile) TRY(prof.mark(s));
+                ++res->gen_launches;
+                ++res->verify_launches;
+                TRY_HIP(launch_between(c->d_ctr, s));
+                tile = end;
+            }
+        }
+        TRY(read_counters(c, s));
+        if (profile) TRY(prof.collect(res->gen_ms, res->verify_ms));
+        // rare: deferred candidates that were new after all.  Every round
+        // inserts or resolves at least one record (a record is deferred again
+        // only after meeting a row that another record of the same round
+        // inserted), so the loop ends within n0 rounds.
+        const uint64_t n0 = c->h_ctr[C_DEF1];
+        for (uint64_t round = 0; c->h_ctr[C_DEF1] > 0 && !c->h_ctr[C_DEF_OVF]; ++round) {
+            if (round > n0 + 16) return fail(c, LTLF_EDEVICE, "re-insertion rounds made no progress");
+            const uint64_t n = c->h_ctr[C_DEF1];
+            TRY_HIP(launch_reinsert(c->st, n, s));
+            TRY_HIP(launch_set_counter(c->d_ctr, C_DEF1, 0, s));
+            TRY_HIP(launch_verify_deferred(c->st, s));
+            TRY_HIP(launch_between(c->d_ctr, s));
+            TRY(read_counters(c, s));
+        }
+        if (c->h_ctr[C_DEF_OVF]) return fail(c, LTLF_EDEVICE, "deferral list overflow");
+        const uint64_t now = std::min<uint64_t>(c->h_ctr[C_ROWS], c->st.cap);
+        c->lcount[lev] = now - rows;
+        rows = now;
+        candidates = c->h_ctr[C_CAND];
+        const bool overflow = c->h_ctr[C_OVERFLOW] != 0;
+        if (c->h_ctr[C_FOUND] && status != LTLF_OK) {
+            status = LTLF_OK;
+            res->min_cost = lev;
+            wit_op = (uint32_t)c->h_ctr[C_WIT_OP];
+            wit_a = (uint32_t)c->h_ctr[C_WIT_A];
+            wit_b = (uint32_t)c->h_ctr[C_WIT_B];
+        }
+        if (overflow) {
+            if (status != LTLF_OK) status = LTLF_CAPACITY;
+            res->overflow_level = lev;
+            c->lcount[lev] = 0;
+            break;
+        }
+        res->levels_done = lev;
+        if (status == LTLF_OK && !exhaust) break;
+    }
+    TRY_HIP(hipEventRecord(e1, s));
+    TRY_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+    res->enum_ms = ms;
+    res->status = status;
+    res->candidates = candidates;
+    res->deferred = c->h_ctr[C_DEFERRED];
+    c->levels_done = res->levels_done;
+    uint64_t uniq = 0;
+    for (uint32_t lev = 1; lev <= res->levels_done; ++lev) uniq += c->lcount[lev];
+    res->unique_total = uniq;
+    if (res->level_counts) {
+        for (uint32_t i = 0; i < res->level_counts_len; ++i)
+            res->level_counts[i] = (i <= res->levels_done && i < c->lcount.size()) ? c->lcount[i] : 0;
+    }
+    c->ran = true;
+    if (status == LTLF_OK) {
+        std::string f;
+        TRY(render_formula(c, wit_op, wit_a, wit_b, s, f));
+        res->formula_len = f.size() + 1;
+        if (res->formula) {
+            if (res->formula_cap < f.size() + 1) return LTLF_EBUFSZ;
+            std::memcpy(res->formula, f.c_str(), f.size() + 1);
+        }
+    } else if (res->formula && res->formula_cap) {
+        res->formula[0] = 0;
+        res->formula_len = 1;
+    }
+    return status;
+}
+
+ltlf_status ltlf_solve(ltlf_ctx* c, const ltlf_spec* sp, const ltlf_costs* k, uint32_t bound,
+                       uint32_t flags, void* stream, ltlf_result* res) {
+    TRY(ltlf_load(c, sp, stream));
+    return ltlf_run(c, k, bound, flags, stream, res);
+}
+
+ltlf_status ltlf_export_level(ltlf_ctx* c, uint32_t cost, uint64_t first, uint64_t count,
+                              uint64_t* host_buf, uint64_t cap_words, uint64_t* n_cms,
+                              uint64_t* words_per_cm) {
+    if (!c || !n_cms || !words_per_cm) return LTLF_EINVAL;
+    if (!c->ran) return LTLF_ESTATE;
+    if (cost == 0 || cost > c->levels_done) return LTLF_EINVAL;
+    const uint64_t cw = (c->n_pos + 63) / 64;
+    const uint64_t total = c->lcount[cost];
+    const uint64_t lo = std::min(first, total);
+    const uint64_t n = std::min(count, total - lo);
+    *n_cms = n;
+    *words_per_cm = cw;
+    if (!host_buf) return LTLF_OK;
+    if (cap_words < n * cw) return LTLF_EBUFSZ;
+    TRY_HIP(hipSetDevice(c->device));
+    const uint64_t per = std::max<uint64_t>(1, kStagingBytes / 8 / cw);
+    for (uint64_t q = 0; q < n; q += per) {
+        const uint64_t m = std::min<uint64_t>(per, n - q);
+        TRY_HIP(launch_export(c->st.rows, c->Wp, c->lstart[cost] + lo + q, m, c->d_canon, c->n_pos,
+                              c->d_stage, nullptr));
+        TRY_HIP(hipMemcpy(host_buf + q * cw, c->d_stage, 8 * m * cw, hipMemcpyDeviceToHost));
+    }
+    return LTLF_OK;
+}
+
+ltlf_status ltlf_formula_of(ltlf_ctx* c, uint32_t cost, uint64_t index, char* buf, uint64_t cap,
+                            uint64_t* need) {
+    if (!c || !need) return LTLF_EINVAL;
+    if (!c->ran) return LTLF_ESTATE;
+    if (cost == 0 || cost > c->levels_done || index >= c->lcount[cost]) return LTLF_EINVAL;
+    TRY_HIP(hipSetDevice(c->device));
+    uint4 m;
+    TRY_HIP(hipMemcpy(&m, c->st.meta + c->lstart[cost] + index, sizeof(uint4), hipMemcpyDeviceToHost));
+    std::string f;
+    TRY(render_formula(c, m.x, m.y, m.z, nullptr, f));
+    *need = f.size() + 1;
+    if (!buf || cap < f.size() + 1) return LTLF_EBUFSZ;
+    std::memcpy(buf, f.c_str(), f.size() + 1);
+    return LTLF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,303 @@
+"""Python binding of the C ABI in include/ltlf.h (argument marshalling only).
+
+The functions named ``ltlf_*`` mirror the C entry points one to one.  Every
+step of the synthesis runs in libltlf.so; nothing here computes on the data.
+PyTorch supplies device memory (the workspace tensor) and the stream.
+:class:`Synthesizer` bundles a context, a torch workspace and the current
+stream for convenience.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libltlf.so")
+
+OK, NOT_FOUND, CAPACITY = 0, 1, 2
+EINVAL, ENOMEM, EDEVICE, EBUFSZ, ESTATE = -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "OK", 1: "NOT_FOUND", 2: "CAPACITY", -1: "EINVAL", -2: "ENOMEM",
+                -3: "EDEVICE", -4: "EBUFSZ", -5: "ESTATE"}
+FLAG_EXHAUST = 0x1
+FLAG_PROFILE = 0x2
+FLAG_WEAK_HASH = 0x100  # test hook: 6-bit hashes, every probe meets an equal tag
+
+OP_NAMES = ("!", "X", "F", "G", "&", "|", "U")  # index = ltlf_op
+
+
+class LtlfError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        msg = f"{where}: {STATUS_NAMES.get(status, status)}"
+        super().__init__(msg + (f" ({detail})" if detail else ""))
+        self.status = status
+
+
+class ltlf_spec(ctypes.Structure):
+    _fields_ = [("n_props", ctypes.c_uint32), ("n_traces", ctypes.c_uint32),
+                ("lengths", ctypes.POINTER(ctypes.c_uint32)),
+                ("letters", ctypes.POINTER(ctypes.c_uint32)),
+                ("positive", ctypes.POINTER(ctypes.c_uint8))]
+
+
+class ltlf_costs(ctypes.Structure):
+    _fields_ = [("atom_cost", ctypes.c_uint32), ("op_cost", ctypes.c_uint32 * 7)]
+
+
+class ltlf_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("min_cost", ctypes.c_uint32),
+                ("levels_done", ctypes.c_uint32), ("overflow_level", ctypes.c_uint32),
+                ("level_counts", ctypes.POINTER(ctypes.c_uint64)),
+                ("level_counts_len", ctypes.c_uint32),
+                ("formula", ctypes.c_char_p), ("formula_cap", ctypes.c_uint64),
+                ("formula_len", ctypes.c_uint64), ("candidates", ctypes.c_uint64),
+                ("unique_total", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
+                ("row_bytes", ctypes.c_uint32), ("gen_launches", ctypes.c_uint32),
+                ("verify_launches", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("enum_ms", ctypes.c_double), ("gen_ms", ctypes.c_double),
+                ("verify_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Loads libltlf.so from the package directory; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libltlf.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    L.ltlf_status_str.restype = ctypes.c_char_p
+    L.ltlf_status_str.argtypes = [i32]
+    L.ltlf_ctx_last_error.restype = ctypes.c_char_p
+    L.ltlf_ctx_last_error.argtypes = [vp]
+    L.ltlf_ctx_create.restype = i32
+    L.ltlf_ctx_create.argtypes = [i32, u64, ctypes.POINTER(vp)]
+    L.ltlf_ctx_set_workspace.restype = i32
+    L.ltlf_ctx_set_workspace.argtypes = [vp, vp, u64]
+    L.ltlf_ctx_set_row_limit.restype = i32
+    L.ltlf_ctx_set_row_limit.argtypes = [vp, u64]
+    L.ltlf_ctx_destroy.restype = None
+    L.ltlf_ctx_destroy.argtypes = [vp]
+    L.ltlf_load.restype = i32
+    L.ltlf_load.argtypes = [vp, ctypes.POINTER(ltlf_spec), vp]
+    L.ltlf_run.restype = i32
+    L.ltlf_run.argtypes = [vp, ctypes.POINTER(ltlf_costs), u32, u32, vp, ctypes.POINTER(ltlf_result)]
+    L.ltlf_solve.restype = i32
+    L.ltlf_solve.argtypes = [vp, ctypes.POINTER(ltlf_spec), ctypes.POINTER(ltlf_costs), u32, u32, vp,
+                             ctypes.POINTER(ltlf_result)]
+    L.ltlf_export_level.restype = i32
+    L.ltlf_export_level.argtypes = [vp, u32, u64, u64, vp, u64, ctypes.POINTER(u64),
+                                    ctypes.POINTER(u64)]
+    L.ltlf_formula_of.restype = i32
+    L.ltlf_formula_of.argtypes = [vp, u32, u64, ctypes.c_char_p, u64, ctypes.POINTER(u64)]
+    _lib = L
+    return L
+
+
+# ---------------------------------------------------------- C entry points --
+def ltlf_status_str(status: int) -> str:
+    return load_library().ltlf_status_str(status).decode()
+
+
+def ltlf_ctx_last_error(ctx) -> str:
+    return load_library().ltlf_ctx_last_error(ctx).decode()
+
+
+def ltlf_ctx_create(device: int, hbm_budget_bytes: int):
+    h = ctypes.c_void_p()
+    st = load_library().ltlf_ctx_create(device, hbm_budget_bytes, ctypes.byref(h))
+    return st, h
+
+
+def ltlf_ctx_set_workspace(ctx, dev_ptr: int, nbytes: int) -> int:
+    return load_library().ltlf_ctx_set_workspace(ctx, ctypes.c_void_p(dev_ptr), nbytes)
+
+
+def ltlf_ctx_set_row_limit(ctx, max_rows: int) -> int:
+    return load_library().ltlf_ctx_set_row_limit(ctx, max_rows)
+
+
+def ltlf_ctx_destroy(ctx) -> None:
+    load_library().ltlf_ctx_destroy(ctx)
+
+
+def _spec(n_props, lengths, letters, positive):
+    lengths = np.ascontiguousarray(lengths, dtype=np.uint32)
+    letters = np.ascontiguousarray(letters, dtype=np.uint32)
+    positive = np.ascontiguousarray(positive, dtype=np.uint8)
+    sp = ltlf_spec(n_props, len(lengths),
+                   lengths.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                   letters.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                   positive.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    return sp, (lengths, letters, positive)
+
+
+def _costs(op_cost: Sequence[int], atom_cost: int):
+    c = ltlf_costs()
+    c.atom_cost = atom_cost
+    for i, v in enumerate(op_cost):
+        c.op_cost[i] = v
+    return c
+
+
+def ltlf_load(ctx, n_props, lengths, letters, positive, stream: int = 0) -> int:
+    sp, keep = _spec(n_props, lengths, letters, positive)
+    return load_library().ltlf_load(ctx, ctypes.byref(sp), ctypes.c_void_p(stream))
+
+
+def ltlf_run(ctx, op_cost, atom_cost, cost_bound, flags, stream, res: ltlf_result) -> int:
+    c = _costs(op_cost, atom_cost)
+    return load_library().ltlf_run(ctx, ctypes.byref(c), cost_bound, flags, ctypes.c_void_p(stream),
+                                   ctypes.byref(res))
+
+
+def ltlf_solve(ctx, n_props, lengths, letters, positive, op_cost, atom_cost, cost_bound, flags,
+               stream, res: ltlf_result) -> int:
+    sp, keep = _spec(n_props, lengths, letters, positive)
+    c = _costs(op_cost, atom_cost)
+    return load_library().ltlf_solve(ctx, ctypes.byref(sp), ctypes.byref(c), cost_bound, flags,
+                                     ctypes.c_void_p(stream), ctypes.byref(res))
+
+
+def ltlf_export_level(ctx, cost: int, first: int = 0, count: int = (1 << 64) - 1):
+    L = load_library()
+    n, cw = ctypes.c_uint64(), ctypes.c_uint64()
+    st = L.ltlf_export_level(ctx, cost, first, count, None, 0, ctypes.byref(n), ctypes.byref(cw))
+    if st != OK:
+        return st, None
+    out = np.zeros((n.value, cw.value), dtype=np.uint64)
+    if n.value:
+        st = L.ltlf_export_level(ctx, cost, first, count, ctypes.c_void_p(out.ctypes.data), out.size,
+                                 ctypes.byref(n), ctypes.byref(cw))
+    return st, out
+
+
+def ltlf_formula_of(ctx, cost: int, index: int):
+    L = load_library()
+    need = ctypes.c_uint64()
+    buf = ctypes.create_string_buffer(4096)
+    st = L.ltlf_formula_of(ctx, cost, index, buf, len(buf), ctypes.byref(need))
+    if st == EBUFSZ:
+        buf = ctypes.create_string_buffer(int(need.value))
+        st = L.ltlf_formula_of(ctx, cost, index, buf, len(buf), ctypes.byref(need))
+    return st, (buf.value.decode() if st == OK else None)
+
+
+# --------------------------------------------------------------- convenience --
+@dataclass
+class Result:
+    status: int
+    min_cost: int
+    levels_done: int
+    overflow_level: int
+    level_counts: List[int]
+    formula: str
+    candidates: int
+    unique_total: int
+    enum_ms: float
+    deferred: int = 0
+    row_bytes: int = 0
+    gen_launches: int = 0
+    verify_launches: int = 0
+    gen_ms: float = 0.0
+    verify_ms: float = 0.0
+
+    @property
+    def status_name(self) -> str:
+        return STATUS_NAMES.get(self.status, str(self.status))
+
+
+UNIT_ALL = (1, 1, 1, 1, 1, 1, 1)
+
+
+class Synthesizer:
+    """A context on one device with a torch-owned workspace.
+
+    workspace_bytes: size of the torch uint8 tensor handed to the library as
+    its only device memory.
+    """
+
+    def __init__(self, device: int = 0, workspace_bytes: int = 1 << 30):
+        import torch
+
+        self._torch = torch
+        self.device = device
+        st, self._ctx = ltlf_ctx_create(device, 0)
+        if st != OK:
+            raise LtlfError(st, "ltlf_ctx_create")
+        self.workspace = torch.empty(int(workspace_bytes), dtype=torch.uint8,
+                                     device=f"cuda:{device}")
+        st = ltlf_ctx_set_workspace(self._ctx, self.workspace.data_ptr(), self.workspace.numel())
+        if st != OK:
+            raise LtlfError(st, "ltlf_ctx_set_workspace")
+        self._bound = 0
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            ltlf_ctx_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self) -> int:
+        return self._torch.cuda.current_stream(self.device).cuda_stream
+
+    def set_row_limit(self, max_rows: int) -> None:
+        st = ltlf_ctx_set_row_limit(self._ctx, max_rows)
+        if st != OK:
+            raise LtlfError(st, "ltlf_ctx_set_row_limit")
+
+    def load(self, problem) -> None:
+        lengths, letters, positive = problem.arrays()
+        st = ltlf_load(self._ctx, problem.n_props, lengths, letters, positive, self._stream())
+        if st != OK:
+            raise LtlfError(st, "ltlf_load", ltlf_ctx_last_error(self._ctx))
+
+    def run(self, cost_bound: int, op_cost=UNIT_ALL, atom_cost: int = 1, flags: int = 0) -> Result:
+        counts = (ctypes.c_uint64 * (cost_bound + 1))()
+        fbuf = ctypes.create_string_buffer(8192)
+        res = ltlf_result()
+        res.level_counts = counts
+        res.level_counts_len = cost_bound + 1
+        res.formula = ctypes.cast(fbuf, ctypes.c_char_p)
+        res.formula_cap = len(fbuf)
+        st = ltlf_run(self._ctx, op_cost, atom_cost, cost_bound, flags, self._stream(), res)
+        if st < 0:
+            raise LtlfError(st, "ltlf_run", ltlf_ctx_last_error(self._ctx))
+        self._bound = cost_bound
+        return Result(status=st, min_cost=res.min_cost, levels_done=res.levels_done,
+                      overflow_level=res.overflow_level, level_counts=list(counts),
+                      formula=fbuf.value.decode(), candidates=res.candidates,
+                      unique_total=res.unique_total, enum_ms=res.enum_ms, deferred=res.deferred,
+                      row_bytes=res.row_bytes, gen_launches=res.gen_launches,
+                      verify_launches=res.verify_launches, gen_ms=res.gen_ms,
+                      verify_ms=res.verify_ms)
+
+    def solve(self, problem, cost_bound: Optional[int] = None, op_cost=UNIT_ALL, atom_cost: int = 1,
+              flags: int = 0) -> Result:
+        self.load(problem)
+        return self.run(int(cost_bound if cost_bound is not None else problem.cost_bound),
+                        op_cost=op_cost, atom_cost=atom_cost, flags=flags)
+
+    def export_level(self, cost: int, first: int = 0, count: int = (1 << 64) - 1) -> np.ndarray:
+        st, out = ltlf_export_level(self._ctx, cost, first, count)
+        if st != OK:
+            raise LtlfError(st, "ltlf_export_level")
+        return out
+
+    def formula_of(self, cost: int, index: int) -> str:
+        st, f = ltlf_formula_of(self._ctx, cost, index)
+        if st != OK:
+            raise LtlfError(st, "ltlf_formula_of")
+        return f

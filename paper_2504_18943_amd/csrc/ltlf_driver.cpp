@@ -68,6 +68,7 @@ struct ltlf_ctx {
     uint64_t table_max = 0;  // slots available
     uint64_t plan_cap = 0;   // rows that fit the workspace
     uint64_t row_limit = 0;  // caller's limit (0 = none)
+    uint64_t lds_limit = 0;  // largest dynamic LDS per workgroup on the device
 
     // host mirrors
     unsigned long long* h_ctr = nullptr;  // pinned
@@ -393,6 +394,12 @@ ltlf_status ltlf_ctx_create(int device, uint64_t hbm_budget_bytes, ltlf_ctx** ou
     ltlf_ctx* c = new (std::nothrow) ltlf_ctx();
     if (!c) return LTLF_ENOMEM;
     c->device = device;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) {
+        delete c;
+        return LTLF_EDEVICE;
+    }
+    c->lds_limit = lds > 1024 ? (uint64_t)lds - 1024 : 0;  // room for static LDS
     c->budget = hbm_budget_bytes ? std::max<uint64_t>(hbm_budget_bytes, kMinWorkspace) : kDefaultBudget;
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_ctr), 8 * C_NUM, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->h_tokens), 4 * (1 + kMaxTokens), hipHostMallocDefault) !=
@@ -571,7 +578,7 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
                 t.tile_begin = tile;
                 t.tile_end = end;
                 if (profile) TRY(prof.mark(s));
-                TRY_HIP(launch_generate(c->st, t, s));
+                TRY_HIP(launch_generate(c->st, t, c->lds_limit, s));
                 if (profile) TRY(prof.mark(s));
                 TRY_HIP(launch_verify_deferred(c->st, s));
                 if (profile) TRY(prof.mark(s));

@@ -101,7 +101,10 @@ hipError_t launch_encode(const uint32_t* letters, const uint32_t* lengths, const
                          uint32_t n_props, uint32_t Wp, uint32_t* V, uint32_t* S, uint32_t* P0,
                          uint32_t* atoms, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st);
-hipError_t launch_generate(const Store& s, const SegTable& t, hipStream_t st);
+// Dynamic LDS bytes of the LDS-staged generation kernel for rows of Wp words;
+// rows needing more than lds_limit use the generic kernel.
+uint64_t lds_bytes(uint32_t Wp);
+hipError_t launch_generate(const Store& s, const SegTable& t, uint64_t lds_limit, hipStream_t st);
 hipError_t launch_verify_deferred(const Store& s, hipStream_t st);
 hipError_t launch_reinsert(const Store& s, uint64_t n, hipStream_t st);
 // Sets C_DEF0 = 0 and C_SNAP = C_ROWS; must run between any launch that

@@ -186,21 +186,35 @@ __device__ __forceinline__ void stream_cm(const Store& s, uint32_t op, uint32_t 
     }
 }
 
-__device__ __forceinline__ uint64_t cm_hash(const Store& s, uint32_t op, uint32_t L, uint32_t R) {
+// An emitter streams one candidate's CM as 16-byte vectors: e(fn) calls
+// fn(w, r) for word index w = 0, 4, 8, ... until fn returns false.  The
+// generic emitter reads both operands from the row store; the register
+// emitters below read them from VGPRs and LDS.
+struct GlobalEmit {
+    const Store& s;
+    uint32_t op, L, R;
+    template <class Fn>
+    __device__ __forceinline__ void operator()(Fn&& fn) const {
+        stream_cm(s, op, L, R, fn);
+    }
+};
+
+template <class Emit>
+__device__ __forceinline__ uint64_t emit_hash(const Store& s, const Emit& e) {
     Hash h;
-    stream_cm(s, op, L, R, [&](uint32_t, uint4 r) {
+    e([&](uint32_t, uint4 r) {
         h.add4(r);
         return true;
     });
     return h.fin() & s.hmask;
 }
 
-__device__ __forceinline__ bool cm_equal_row(const Store& s, uint32_t op, uint32_t L, uint32_t R,
-                                             uint64_t row) {
-    const uint32_t* M = s.rows + row * s.Wp;
+template <class Emit>
+__device__ __forceinline__ bool emit_equal_row(const Store& s, uint64_t row, const Emit& e) {
+    const uint4* M = reinterpret_cast<const uint4*>(s.rows + row * s.Wp);
     bool eq = true;
-    stream_cm(s, op, L, R, [&](uint32_t w, uint4 r) {
-        const uint4 m = *reinterpret_cast<const uint4*>(M + w);
+    e([&](uint32_t w, uint4 r) {
+        const uint4 m = M[w >> 2];
         eq = (r.x == m.x) && (r.y == m.y) && (r.z == m.z) && (r.w == m.w);
         return eq;
     });
@@ -209,9 +223,13 @@ __device__ __forceinline__ bool cm_equal_row(const Store& s, uint32_t op, uint32
 
 // Spec check (paper: phi separates (P, N) iff it holds at position 0 of every
 // positive trace and of no negative one): ((cm ^ P0) & S) == 0 in every word.
-__device__ __forceinline__ uint32_t check_vec(const Store& s, uint32_t w, uint4 r) {
-    const uint4 p = *reinterpret_cast<const uint4*>(s.P0 + w);
-    const uint4 q = *reinterpret_cast<const uint4*>(s.S + w);
+struct Masks {
+    const uint4* S;
+    const uint4* P;
+};
+__device__ __forceinline__ uint32_t check_vec(const Masks& m, uint32_t w, uint4 r) {
+    const uint4 p = m.P[w >> 2];
+    const uint4 q = m.S[w >> 2];
     return ((r.x ^ p.x) & q.x) | ((r.y ^ p.y) & q.y) | ((r.z ^ p.z) & q.z) | ((r.w ^ p.w) & q.w);
 }
 
@@ -223,23 +241,15 @@ __device__ __forceinline__ void report_found(const Store& s, uint32_t op, uint32
     }
 }
 
-__device__ __forceinline__ void check_only(const Store& s, uint32_t op, uint32_t L, uint32_t R) {
+template <class Emit>
+__device__ __forceinline__ void emit_check_only(const Store& s, const Masks& m, uint32_t op,
+                                                uint32_t L, uint32_t R, const Emit& e) {
     uint32_t acc = 0;
-    stream_cm(s, op, L, R, [&](uint32_t w, uint4 r) {
-        acc |= check_vec(s, w, r);
+    e([&](uint32_t w, uint4 r) {
+        acc |= check_vec(m, w, r);
         return true;
     });
     if (acc == 0) report_found(s, op, L, R);
-}
-
-__device__ __forceinline__ void defer(const Store& s, uint32_t op, uint32_t L, uint32_t R,
-                                      uint64_t pos) {
-    const unsigned long long d = wave_alloc(&s.ctr[C_DEF0]);
-    if (d >= s.def0_cap) {
-        atomicExch(&s.ctr[C_DEF_OVF], 1ull);
-        return;
-    }
-    s.def0[d] = make_uint4(op | ((uint32_t)(pos >> 32) << 4), L, R, (uint32_t)pos);
 }
 
 __device__ __forceinline__ uint32_t tag_of(uint64_t h) {
@@ -247,60 +257,157 @@ __device__ __forceinline__ uint32_t tag_of(uint64_t h) {
     return t == 0xFFFFFFFFu ? 0xFFFFFFFEu : t;  // a reserved slot never reads as EMPTY
 }
 
-// Inserts candidate op(L, R) with hash h, probing from `pos`.  Rows with
-// index >= snap were allocated by the running launch.
-__device__ void insert_candidate(const Store& s, uint32_t op, uint32_t L, uint32_t R, uint64_t h,
-                                 uint64_t pos, uint64_t snap) {
+// Outcome of probing one candidate.
+enum : uint32_t { P_SKIP = 0, P_DUP = 1, P_DEFER = 2, P_WON = 3, P_FULL = 4 };
+
+// Probes candidate e (hash h) from `pos`, whose slot value the caller has
+// already loaded (cur0, so that several first probes can be in flight), until
+// an equal stored row is found (DUP), a matching slot of the running launch is
+// met (DEFER; pos = that slot), or an empty slot is reserved (WON; pos = that
+// slot).  FULL: no free slot in the whole table.  Rows with index >= snap
+// were allocated by the running launch and are not read.
+template <class Emit>
+__device__ uint32_t probe_reserve(const Store& s, uint64_t h, uint64_t& pos, uint64_t cur0,
+                                  uint64_t snap, const Emit& e) {
     const uint32_t tag = tag_of(h);
     const uint64_t hi = (uint64_t)tag << 32;
+    uint64_t cur = cur0;
     for (uint64_t steps = 0;; ++steps) {
-        if (steps > s.tmask) {  // table full: cannot happen below the load limit
-            atomicExch(&s.ctr[C_OVERFLOW], 1ull);
-            check_only(s, op, L, R);
-            return;
-        }
-        uint64_t cur = slot_load(&s.table[pos]);
+        if (steps > s.tmask) return P_FULL;
+        if (steps) cur = slot_load(&s.table[pos]);
         if (cur == kEmpty) {
             const uint64_t old = slot_cas(&s.table[pos], kEmpty, hi | kPending);
-            if (old == kEmpty) {
-                const unsigned long long r = wave_alloc(&s.ctr[C_ROWS]);
-                if (r >= s.cap) {
-                    atomicExch(&s.ctr[C_OVERFLOW], 1ull);
-                    check_only(s, op, L, R);
-                    return;
-                }
-                uint32_t* M = s.rows + r * s.Wp;
-                uint32_t acc = 0;
-                stream_cm(s, op, L, R, [&](uint32_t w, uint4 v) {
-                    *reinterpret_cast<uint4*>(M + w) = v;
-                    acc |= check_vec(s, w, v);
-                    return true;
-                });
-                s.meta[r] = make_uint4(op, L, R, 0);
-                s.rhash[r] = h;
-                slot_store(&s.table[pos], hi | (uint32_t)r);
-                if (acc == 0) report_found(s, op, L, R);
-                return;
-            }
+            if (old == kEmpty) return P_WON;
             cur = old;
         }
         const uint32_t cidx = (uint32_t)cur;
         if ((uint32_t)(cur >> 32) == tag) {
-            if (cidx == kPending || cidx >= snap) {
-                defer(s, op, L, R, pos);
-                return;
-            }
-            if (cm_equal_row(s, op, L, R, cidx)) return;  // duplicate
+            if (cidx == kPending || cidx >= snap) return P_DEFER;
+            if (emit_equal_row(s, cidx, e)) return P_DUP;
         }
         pos = (pos + 1) & s.tmask;
     }
 }
 
+// Writes a candidate whose slot `pos` it reserved into row r (or, past the
+// row capacity, only checks it), publishes the slot and runs the spec check.
+template <class Emit>
+__device__ __forceinline__ void write_row(const Store& s, const Masks& m, uint32_t op, uint32_t L,
+                                          uint32_t R, uint64_t h, uint64_t pos, uint64_t r,
+                                          const Emit& e) {
+    if (r >= s.cap) {  // the slot stays reserved; the level will not be stored
+        atomicExch(&s.ctr[C_OVERFLOW], 1ull);
+        emit_check_only(s, m, op, L, R, e);
+        return;
+    }
+    uint4* M = reinterpret_cast<uint4*>(s.rows + r * s.Wp);
+    uint32_t acc = 0;
+    e([&](uint32_t w, uint4 v) {
+        M[w >> 2] = v;
+        acc |= check_vec(m, w, v);
+        return true;
+    });
+    s.meta[r] = make_uint4(op, L, R, 0);
+    s.rhash[r] = h;
+    slot_store(&s.table[pos], ((uint64_t)tag_of(h) << 32) | (uint32_t)r);
+    if (acc == 0) report_found(s, op, L, R);
+}
+
+__device__ __forceinline__ void write_defer(const Store& s, unsigned long long d, uint32_t op,
+                                            uint32_t L, uint32_t R, uint64_t pos) {
+    if (d >= s.def0_cap) {
+        atomicExch(&s.ctr[C_DEF_OVF], 1ull);
+        return;
+    }
+    s.def0[d] = make_uint4(op | ((uint32_t)(pos >> 32) << 4), L, R, (uint32_t)pos);
+}
+
+// One candidate end to end, with per-wave counter aggregation (generic path).
+template <class Emit>
+__device__ void insert_emit(const Store& s, const Masks& m, uint32_t op, uint32_t L, uint32_t R,
+                            uint64_t h, uint64_t pos, uint64_t cur0, uint64_t snap, const Emit& e) {
+    const uint32_t o = probe_reserve(s, h, pos, cur0, snap, e);
+    if (o == P_WON) {
+        write_row(s, m, op, L, R, h, pos, wave_alloc(&s.ctr[C_ROWS]), e);
+    } else if (o == P_DEFER) {
+        write_defer(s, wave_alloc(&s.ctr[C_DEF0]), op, L, R, pos);
+    } else if (o == P_FULL) {
+        atomicExch(&s.ctr[C_OVERFLOW], 1ull);
+        emit_check_only(s, m, op, L, R, e);
+    }
+}
+
+__device__ __forceinline__ Masks global_masks(const Store& s) {
+    return Masks{reinterpret_cast<const uint4*>(s.S), reinterpret_cast<const uint4*>(s.P0)};
+}
+
+__device__ __forceinline__ void check_only(const Store& s, uint32_t op, uint32_t L, uint32_t R) {
+    emit_check_only(s, global_masks(s), op, L, R, GlobalEmit{s, op, L, R});
+}
+
 __device__ __forceinline__ void process(const Store& s, uint32_t op, uint32_t L, uint32_t R,
                                         uint64_t snap) {
-    const uint64_t h = cm_hash(s, op, L, R);
-    insert_candidate(s, op, L, R, h, h & s.tmask, snap);
+    const GlobalEmit e{s, op, L, R};
+    const uint64_t h = emit_hash(s, e);
+    const uint64_t pos = h & s.tmask;
+    insert_emit(s, global_masks(s), op, L, R, h, pos, slot_load(&s.table[pos]), snap, e);
 }
+
+__device__ __forceinline__ bool cm_equal_row(const Store& s, uint32_t op, uint32_t L, uint32_t R,
+                                             uint64_t row) {
+    return emit_equal_row(s, row, GlobalEmit{s, op, L, R});
+}
+
+__device__ __forceinline__ uint64_t cm_hash(const Store& s, uint32_t op, uint32_t L, uint32_t R) {
+    return emit_hash(s, GlobalEmit{s, op, L, R});
+}
+
+// ------------------------------------------------------------ LDS emitters --
+// Operators selected at run time (the selector is wave-uniform in the
+// generation kernels, so the switch costs scalar branches only).
+__device__ __forceinline__ uint4 unary_any(uint32_t op, uint4 a, uint4 v, uint32_t& st) {
+    switch (op) {
+    case OP_NOT: return op_vec<OP_NOT>(a, a, v, st);
+    case OP_X: return op_vec<OP_X>(a, a, v, st);
+    case OP_F: return op_vec<OP_F>(a, a, v, st);
+    default: return op_vec<OP_G>(a, a, v, st);
+    }
+}
+__device__ __forceinline__ uint4 binary_any(uint32_t op, uint4 a, uint4 b, uint32_t& st) {
+    switch (op) {
+    case OP_AND: return op_vec<OP_AND>(a, b, b, st);
+    case OP_OR: return op_vec<OP_OR>(a, b, b, st);
+    default: return op_vec<OP_U>(a, b, b, st);
+    }
+}
+
+// Unary operator `op` over a row in LDS (v), with V in LDS.
+struct LdsUnaryEmit {
+    const uint4* v;
+    const uint4* V;
+    uint32_t nq, op;
+    template <class Fn>
+    __device__ __forceinline__ void operator()(Fn&& fn) const {
+        uint32_t st = 0;
+        for (uint32_t q = 0; q < nq; ++q) {
+            if (!fn(4u * q, unary_any(op, v[q], V[q], st))) return;
+        }
+    }
+};
+
+// Binary operator `op` with left operand l and right operand r (LDS rows).
+struct LdsPairEmit {
+    const uint4* l;
+    const uint4* r;
+    uint32_t nq, op;
+    template <class Fn>
+    __device__ __forceinline__ void operator()(Fn&& fn) const {
+        uint32_t st = 0;
+        for (uint32_t q = 0; q < nq; ++q) {
+            if (!fn(4u * q, binary_any(op, l[q], r[q], st))) return;
+        }
+    }
+};
 
 // ------------------------------------------------------------ tile mapping --
 __device__ __forceinline__ void tri_tile(uint64_t lt, uint64_t& ta, uint64_t& tb) {
@@ -371,11 +478,223 @@ __global__ __launch_bounds__(kLanes) void k_generate(Store s, SegTable t) {
     if (__lane_id() == 0 && c) atomicAdd(&s.ctr[C_CAND], c);
 }
 
+// Wave-wide allocation of rows and deferral records: every active lane
+// brings how many rows (nrow) and records (ndef) it needs (each <= 4); one
+// atomic per counter and wave hands out consecutive indices.  No barrier, so
+// waves never wait for each other's probe chains.
+__device__ __forceinline__ void wave_alloc2(const Store& s, uint32_t nrow, uint32_t ndef,
+                                            unsigned long long& rbase,
+                                            unsigned long long& dbase) {
+    const uint32_t lane = __lane_id();
+    const uint32_t mine = nrow | (ndef << 16);
+    uint32_t incl = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(incl, d, 64);
+        if (lane >= (uint32_t)d) incl += t;
+    }
+    const uint32_t total = __shfl(incl, 63, 64);
+    unsigned long long rb = 0, db = 0;
+    if (lane == 0) {
+        if (total & 0xFFFFu) rb = atomicAdd(&s.ctr[C_ROWS], (unsigned long long)(total & 0xFFFFu));
+        if (total >> 16) db = atomicAdd(&s.ctr[C_DEF0], (unsigned long long)(total >> 16));
+    }
+    rb = __shfl(rb, 0, 64);
+    db = __shfl(db, 0, 64);
+    const uint32_t excl = incl - mine;
+    rbase = rb + (excl & 0xFFFFu);
+    dbase = db + (excl >> 16);
+}
+
+__device__ __forceinline__ uint32_t diff4(uint4 a, uint4 b) {
+    return (a.x ^ b.x) | (a.y ^ b.y) | (a.z ^ b.z) | (a.w ^ b.w);
+}
+
+// Per-candidate state of one iteration.
+struct Cand {
+    uint64_t h, pos, cur;
+    uint32_t out;
+};
+
+// Hash pass of one candidate: records the hash and issues the first probe,
+// unless the candidate is disabled or its CM equals one of its operands
+// (A, or B if given) -- a stored, cheaper CM, so a sure duplicate.  P_WON
+// here only marks "still to probe".
+template <class Emit>
+__device__ __forceinline__ void cand_begin(const Store& s, Cand& c, bool enabled, bool check_eq,
+                                           const uint4* A, const uint4* B, const Emit& e) {
+    c.out = P_SKIP;
+    if (!enabled) return;
+    Hash hs;
+    uint32_t ea = 0, eb = 0;
+    e([&](uint32_t w, uint4 r) {
+        hs.add4(r);
+        ea |= diff4(r, A[w >> 2]);
+        eb |= diff4(r, B[w >> 2]);
+        return true;
+    });
+    if (check_eq && (ea == 0 || eb == 0)) return;
+    c.h = hs.fin() & s.hmask;
+    c.pos = c.h & s.tmask;
+    c.cur = slot_load(&s.table[c.pos]);
+    c.out = P_WON;
+}
+
+template <class Emit>
+__device__ __forceinline__ void cand_probe(const Store& s, Cand& c, uint64_t snap, const Emit& e) {
+    if (c.out == P_WON) c.out = probe_reserve(s, c.h, c.pos, c.cur, snap, e);
+}
+
+template <class Emit>
+__device__ __forceinline__ void cand_finish(const Store& s, const Masks& m, const Cand& c,
+                                            uint32_t op, uint32_t L, uint32_t R,
+                                            unsigned long long& rb, unsigned long long& db,
+                                            const Emit& e) {
+    if (c.out == P_WON) {
+        write_row(s, m, op, L, R, c.h, c.pos, rb++, e);
+    } else if (c.out == P_DEFER) {
+        write_defer(s, db++, op, L, R, c.pos);
+    } else if (c.out == P_FULL) {
+        atomicExch(&s.ctr[C_OVERFLOW], 1ull);
+        emit_check_only(s, m, op, L, R, e);
+    }
+}
+
+__host__ __device__ __forceinline__ uint32_t lds_stride(uint32_t nq) { return nq | 1u; }
+
+// Generation with operands staged in LDS, for rows that fit (see
+// lds_bytes()).  Pair tiles: the workgroup stages its 16 left operands (read
+// by whole waves at one address: broadcast) and each lane its right operand
+// (rows padded to an odd number of 16-byte vectors, so the 8 lanes served per
+// LDS cycle hit disjoint banks); the masks go to LDS too.  For every pair,
+// each enabled operator (a and b, a or b, a U b, b U a) is streamed once to
+// hash it and to test it against both operands, the first probes of all
+// operators are issued before any is waited on, and rows and deferral records
+// are allocated with one atomic per counter, wave and pair.  Unary tiles do
+// the same for not, X, F, G over the lane's operand.
+__global__ __launch_bounds__(kLanes) void k_generate_lds(Store s, SegTable t) {
+    extern __shared__ uint4 dyn[];
+    const uint32_t NQ = s.Wp / 4, SB = lds_stride(NQ);
+    uint4* sh_b = dyn;
+    uint4* sh_a = sh_b + kLanes * SB;
+    uint4* sh_v = sh_a + kTileA * NQ;
+    uint4* sh_s = sh_v + NQ;
+    uint4* sh_p = sh_s + NQ;
+    const uint64_t tile = t.tile_begin + blockIdx.x;
+    if (tile >= t.tile_end) return;
+    const uint64_t snap = s.ctr[C_SNAP];
+    uint32_t si = 0;
+    while (si + 1 < t.n && t.first[si + 1] <= tile) ++si;
+    const Seg& g = t.seg[si];
+    const uint64_t lt = tile - t.first[si];
+    const uint32_t tid = threadIdx.x;
+    const uint4* rows4 = reinterpret_cast<const uint4*>(s.rows);
+    for (uint32_t q = tid; q < NQ; q += kLanes) {
+        sh_v[q] = reinterpret_cast<const uint4*>(s.V)[q];
+        sh_s[q] = reinterpret_cast<const uint4*>(s.S)[q];
+        sh_p[q] = reinterpret_cast<const uint4*>(s.P0)[q];
+    }
+    const Masks m{sh_s, sh_p};
+    uint4* mine = sh_b + tid * SB;
+    uint32_t count = 0;
+
+    if (g.kind == SEG_ATOM) {
+        __syncthreads();
+        if (tid < g.nb) {
+            process(s, OP_ATOM, tid, 0, snap);
+            ++count;
+        }
+    } else if (g.kind == SEG_UNARY) {
+        const uint64_t vl = lt * kLanes + tid;
+        const bool ok = vl < g.nb;
+        const uint32_t vi = (uint32_t)(g.b0 + (ok ? vl : 0));
+        for (uint32_t q = 0; q < NQ; ++q) mine[q] = ok ? rows4[(uint64_t)vi * NQ + q] : make_uint4(0, 0, 0, 0);
+        __syncthreads();
+        const uint32_t vop = ok ? s.meta[vi].x : OP_ATOM;
+        // not not a, F F a, G G a are cheaper formulas' CMs: skipped.  A result
+        // equal to a (possible for X, F, G) is a sure duplicate.
+        constexpr uint32_t ops[4] = {OP_NOT, OP_X, OP_F, OP_G};
+        constexpr uint32_t bits[4] = {M_NOT, M_X, M_F, M_G};
+        Cand c[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool en = ok && (g.opmask & bits[j]) && (j == 1 || vop != ops[j]);
+            cand_begin(s, c[j], en, j != 0, mine, mine, LdsUnaryEmit{mine, sh_v, NQ, ops[j]});
+            count += en;
+        }
+        uint32_t nrow = 0, ndef = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            cand_probe(s, c[j], snap, LdsUnaryEmit{mine, sh_v, NQ, ops[j]});
+            nrow += c[j].out == P_WON;
+            ndef += c[j].out == P_DEFER;
+        }
+        unsigned long long rb, db;
+        wave_alloc2(s, nrow, ndef, rb, db);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            cand_finish(s, m, c[j], ops[j], vi, 0, rb, db, LdsUnaryEmit{mine, sh_v, NQ, ops[j]});
+    } else {
+        uint64_t ta, tb;
+        if (g.tri) {
+            tri_tile(lt, ta, tb);
+        } else {
+            const uint64_t tiles_b = (g.nb + kLanes - 1) / kLanes;
+            ta = lt / tiles_b;
+            tb = lt % tiles_b;
+        }
+        for (uint32_t idx = tid; idx < kTileA * NQ; idx += kLanes) {
+            const uint64_t al = ta * kTileA + idx / NQ;
+            sh_a[idx] = al < g.na ? rows4[(g.a0 + al) * NQ + idx % NQ] : make_uint4(0, 0, 0, 0);
+        }
+        const uint64_t bl = tb * kLanes + tid;
+        const bool valid = bl < g.nb;
+        const uint32_t bi = (uint32_t)(g.b0 + (valid ? bl : 0));
+        for (uint32_t q = 0; q < NQ; ++q) mine[q] = valid ? rows4[(uint64_t)bi * NQ + q] : make_uint4(0, 0, 0, 0);
+        __syncthreads();
+        // candidate j: a&b, a|b, a U b, b U a
+        constexpr uint32_t ops[4] = {OP_AND, OP_OR, OP_U, OP_U};
+        constexpr uint32_t bits[4] = {M_AND, M_OR, M_UAB, M_UBA};
+        for (uint32_t i = 0; i < kTileA; ++i) {
+            const uint64_t al = ta * kTileA + i;
+            if (al >= g.na) break;  // uniform across the block
+            const bool ok = valid && !(g.tri && al >= bl);  // pairs a < b only
+            const uint32_t ai = (uint32_t)(g.a0 + al);
+            const uint4* arow = sh_a + i * NQ;
+            Cand c[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool en = ok && (g.opmask & bits[j]);
+                const LdsPairEmit e{j == 3 ? mine : arow, j == 3 ? arow : mine, NQ, ops[j]};
+                cand_begin(s, c[j], en, true, arow, mine, e);
+                count += en;
+            }
+            uint32_t nrow = 0, ndef = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                cand_probe(s, c[j], snap, LdsPairEmit{j == 3 ? mine : arow, j == 3 ? arow : mine, NQ, ops[j]});
+                nrow += c[j].out == P_WON;
+                ndef += c[j].out == P_DEFER;
+            }
+            unsigned long long rb, db;
+            wave_alloc2(s, nrow, ndef, rb, db);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                cand_finish(s, m, c[j], ops[j], j == 3 ? bi : ai, j == 3 ? ai : bi, rb, db,
+                            LdsPairEmit{j == 3 ? mine : arow, j == 3 ? arow : mine, NQ, ops[j]});
+        }
+    }
+    unsigned long long cc = count;
+    for (int off = 32; off > 0; off >>= 1) cc += __shfl_down(cc, off);
+    if (__lane_id() == 0 && cc) atomicAdd(&s.ctr[C_CAND], cc);
+}
+
 // Verifies deferred candidates against the entries they met (now visible).
 // Candidates that turn out to be new go to list 1 for re-insertion.
 __global__ __launch_bounds__(kLanes) void k_verify_deferred(Store s) {
     const uint64_t n = s.ctr[C_DEF0];
     const uint64_t lim = n < s.def0_cap ? n : s.def0_cap;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && lim) atomicAdd(&s.ctr[C_DEFERRED], (unsigned long long)lim);
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < lim;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const uint4 rec = s.def0[i];
@@ -383,7 +702,6 @@ __global__ __launch_bounds__(kLanes) void k_verify_deferred(Store s) {
         uint64_t pos = ((uint64_t)(rec.x >> 4) << 32) | rec.w;
         const uint64_t h = cm_hash(s, op, rec.y, rec.z);
         const uint32_t tag = tag_of(h);
-        atomicAdd(&s.ctr[C_DEFERRED], 1ull);
         for (uint64_t steps = 0;; ++steps) {
             if (steps > s.tmask) {
                 atomicExch(&s.ctr[C_OVERFLOW], 1ull);
@@ -580,10 +898,29 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st) 
     return hipGetLastError();
 }
 
-hipError_t launch_generate(const Store& s, const SegTable& t, hipStream_t st) {
+uint64_t lds_bytes(uint32_t Wp) {
+    const uint32_t nq = Wp / 4;
+    return 16ull * (kLanes * lds_stride(nq) + kTileA * nq + 3ull * nq);
+}
+
+hipError_t launch_generate(const Store& s, const SegTable& t, uint64_t lds_limit, hipStream_t st) {
     const uint64_t n = t.tile_end - t.tile_begin;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_generate, dim3((uint32_t)n), dim3(kLanes), 0, st, s, t);
+    const dim3 grid((uint32_t)n), block(kLanes);
+    const uint64_t lds = lds_bytes(s.Wp);
+    if (lds <= lds_limit) {
+        static uint64_t raised = 0;  // largest dynamic LDS size enabled so far
+        if (lds > 65536 && lds > raised) {
+            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_generate_lds),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)lds);
+            if (e != hipSuccess) return e;
+            raised = lds;
+        }
+        hipLaunchKernelGGL(k_generate_lds, grid, block, (uint32_t)lds, st, s, t);
+    } else {
+        hipLaunchKernelGGL(k_generate, grid, block, 0, st, s, t);
+    }
     return hipGetLastError();
 }
 

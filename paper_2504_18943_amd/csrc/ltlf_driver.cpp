@@ -34,11 +34,6 @@ inline uint64_t pow2_ceil(uint64_t x) {
     while (p < x) p <<= 1;
     return p;
 }
-inline uint64_t pow2_floor(uint64_t x) {
-    uint64_t p = 1;
-    while ((p << 1) <= x && (p << 1) != 0) p <<= 1;
-    return p;
-}
 
 }  // namespace
 
@@ -152,17 +147,15 @@ ltlf_status plan_memory_impl(ltlf_ctx* c) {
     if (off >= c->ws_bytes) return LTLF_ENOMEM;
     rest = c->ws_bytes - off;
 
-    const uint64_t per_row = 4 * Wp + 16 + 8;
-    uint64_t cap0 = rest / (per_row + 16);
-    uint64_t slots = pow2_floor(std::max<uint64_t>(2 * cap0, 2));
-    while (slots > 2 && slots * 8 > rest) slots >>= 1;
-    uint64_t cap = std::min<uint64_t>((rest - slots * 8 - 3 * 256) / per_row, slots / 2);
-    cap = std::min<uint64_t>(cap, 0xFFFFFFF0ull);
+    // two table slots (16 bytes) per row; the table holds at most 2^32 slots
+    const uint64_t per_row = 4 * Wp + 16;
+    uint64_t cap = (rest - 3 * 256) / (per_row + 16);
+    cap = std::min<uint64_t>(cap, (1ull << 31) - 16);
+    const uint64_t slots = 2 * cap;
     if (cap < c->n_props + 16 || slots < kMinTableSlots) return LTLF_ENOMEM;
     c->st.table = reinterpret_cast<uint64_t*>(take(8 * slots));
     c->st.rows = reinterpret_cast<uint32_t*>(take(4 * Wp * cap));
     c->st.meta = reinterpret_cast<uint4*>(take(16 * cap));
-    c->st.rhash = reinterpret_cast<uint64_t*>(take(8 * cap));
     if (off > c->ws_bytes) return LTLF_ENOMEM;
     c->table_max = slots;
     c->plan_cap = cap;
@@ -295,7 +288,8 @@ LevelPlan plan_level(const ltlf_ctx* c, const ltlf_costs* k, uint32_t lev) {
                 g.tiles = ((g.na + kTileA - 1) / kTileA) * ((g.nb + kLanes - 1) / kLanes);
             }
             p.segs.push_back(g);
-            p.cand_per_tile.push_back((uint64_t)kLanes * kTileA * __builtin_popcount(mask));
+            p.cand_per_tile.push_back((uint64_t)kLanes * std::min<uint64_t>(kTileA, g.na) *
+                                      __builtin_popcount(mask));
         }
     }
     for (size_t s = 0; s < p.segs.size(); ++s) p.cand_ub += p.segs[s].tiles * p.cand_per_tile[s];
@@ -305,10 +299,11 @@ LevelPlan plan_level(const ltlf_ctx* c, const ltlf_costs* k, uint32_t lev) {
 // Grows the table (clear + re-insert every stored row) so that it keeps at
 // least two slots per row after `extra` more rows.
 ltlf_status ensure_table(ltlf_ctx* c, uint64_t rows, uint64_t extra, hipStream_t s) {
-    const uint64_t need = std::min<uint64_t>(pow2_ceil(std::max<uint64_t>(2 * (rows + extra), kMinTableSlots)),
-                                             c->table_max);
-    if (need <= c->st.tmask + 1) return LTLF_OK;
-    c->st.tmask = need - 1;
+    const uint64_t want = std::max<uint64_t>(2 * (rows + extra), kMinTableSlots);
+    if (want <= c->st.tsize || c->st.tsize == c->table_max) return LTLF_OK;
+    // grow by at least 2x: a growth re-inserts every stored row
+    const uint64_t need = std::min<uint64_t>(std::max<uint64_t>(want, 2 * c->st.tsize), c->table_max);
+    c->st.tsize = need;
     TRY_HIP(launch_fill_u64(c->st.table, need, ~0ull, s));
     TRY_HIP(launch_rehash(c->st, rows, s));
     return LTLF_OK;
@@ -532,7 +527,7 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
     TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(c->d_ctr), C_NUM, 0, s));
     const uint64_t slots0 = std::min<uint64_t>(pow2_ceil(std::max<uint64_t>(4ull * c->n_props, kMinTableSlots)),
                                                c->table_max);
-    c->st.tmask = slots0 - 1;
+    c->st.tsize = slots0;
     TRY_HIP(launch_fill_u64(c->st.table, slots0, ~0ull, s));
 
     uint64_t rows = 0;
@@ -547,7 +542,21 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
             res->levels_done = lev;
             continue;
         }
-        TRY(ensure_table(c, rows, std::min<uint64_t>(p.cand_ub, c->st.cap - rows), s));
+        // Size the table for this level from the growth of the previous
+        // levels (1.5x margin, never above the candidate bound); the guard
+        // below keeps >= 2 slots per row that can exist after the next chunk
+        // whatever the estimate, growing the table between chunks if needed.
+        // rows_ub is an upper bound on the rows stored so far (kept without
+        // a sync).
+        {
+            uint64_t est = p.cand_ub;
+            if (lev >= 3 && c->lcount[lev - 1] && c->lcount[lev - 2]) {
+                const double ratio = (double)c->lcount[lev - 1] / (double)c->lcount[lev - 2];
+                est = std::min<uint64_t>(est, (uint64_t)(1.5 * ratio * (double)c->lcount[lev - 1]) + 4096);
+            }
+            TRY(ensure_table(c, rows, std::min<uint64_t>(est, c->st.cap - rows), s));
+        }
+        uint64_t rows_ub = rows;
         // launch in groups of at most kMaxSegs segments, each split into
         // chunks whose candidates fit the deferral list
         for (size_t g0 = 0; g0 < p.segs.size(); g0 += kMaxSegs) {
@@ -575,6 +584,13 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
                     budget -= take * per;
                 }
                 if (end == tile) return fail(c, LTLF_EDEVICE, "a tile exceeds the deferral list");
+                const uint64_t chunk = c->st.def0_cap - budget;  // candidates, upper bound
+                if (2 * (rows_ub + chunk) > c->st.tsize) {
+                    TRY(read_counters(c, s));
+                    rows_ub = std::min<uint64_t>(c->h_ctr[C_ROWS], c->st.cap);
+                    TRY(ensure_table(c, rows_ub, std::min<uint64_t>(chunk, c->st.cap - rows_ub), s));
+                }
+                rows_ub = std::min<uint64_t>(rows_ub + chunk, c->st.cap);
                 t.tile_begin = tile;
                 t.tile_end = end;
                 if (profile) TRY(prof.mark(s));
@@ -598,6 +614,8 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
         for (uint64_t round = 0; c->h_ctr[C_DEF1] > 0 && !c->h_ctr[C_DEF_OVF]; ++round) {
             if (round > n0 + 16) return fail(c, LTLF_EDEVICE, "re-insertion rounds made no progress");
             const uint64_t n = c->h_ctr[C_DEF1];
+            const uint64_t now_rows = std::min<uint64_t>(c->h_ctr[C_ROWS], c->st.cap);
+            TRY(ensure_table(c, now_rows, std::min<uint64_t>(n, c->st.cap - now_rows), s));
             TRY_HIP(launch_reinsert(c->st, n, s));
             TRY_HIP(launch_set_counter(c->d_ctr, C_DEF1, 0, s));
             TRY_HIP(launch_verify_deferred(c->st, s));
@@ -698,7 +716,7 @@ ltlf_status ltlf_formula_of(ltlf_ctx* c, uint32_t cost, uint64_t index, char* bu
     uint4 m;
     TRY_HIP(hipMemcpy(&m, c->st.meta + c->lstart[cost] + index, sizeof(uint4), hipMemcpyDeviceToHost));
     std::string f;
-    TRY(render_formula(c, m.x, m.y, m.z, nullptr, f));
+    TRY(render_formula(c, m.x & 7u, m.y, m.z, nullptr, f));
     *need = f.size() + 1;
     if (!buf || cap < f.size() + 1) return LTLF_EBUFSZ;
     std::memcpy(buf, f.c_str(), f.size() + 1);

@@ -81,10 +81,9 @@ struct Store {
     const uint32_t* P0;     // position-0 mask of positive traces
     const uint32_t* atoms;  // n_props rows of Wp words
     uint32_t* rows;         // cap rows of Wp words
-    uint4* meta;            // per row {op, a, b, 0}
-    uint64_t* rhash;        // per row 64-bit hash
-    uint64_t* table;        // open addressing, 2^k slots
-    uint64_t tmask;         // slots - 1
+    uint4* meta;            // per row {op | tag << 3, a, b, low 32 hash bits}
+    uint64_t* table;        // open addressing, tsize slots
+    uint64_t tsize;         // slots in use (<= 2^32)
     unsigned long long* ctr;  // C_NUM counters
     uint4* def0;            // deferral list written by generation kernels
     uint4* def1;            // records that still need inserting

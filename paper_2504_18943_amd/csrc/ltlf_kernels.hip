@@ -252,9 +252,20 @@ __device__ __forceinline__ void emit_check_only(const Store& s, const Masks& m, 
     if (acc == 0) report_found(s, op, L, R);
 }
 
-__device__ __forceinline__ uint32_t tag_of(uint64_t h) {
-    const uint32_t t = (uint32_t)(h >> 32);
-    return t == 0xFFFFFFFFu ? 0xFFFFFFFEu : t;  // a reserved slot never reads as EMPTY
+// Slot tag: the top 29 bits of the hash (never all ones, so a reserved slot
+// never reads as EMPTY).  The derivation record keeps the tag next to the
+// operator code and the low 32 hash bits beside it, so the table can be
+// rebuilt from the records alone (table size <= 2^32 slots).
+__device__ __forceinline__ uint32_t tag_of(uint64_t h) { return (uint32_t)(h >> 35); }
+
+// Home slot of hash h: the low 32 hash bits scaled to the table size
+// (multiply-shift, so the table need not be a power of two); probing walks
+// forward and wraps.
+__device__ __forceinline__ uint64_t slot_of(const Store& s, uint64_t h) {
+    return (uint64_t)__umulhi((uint32_t)h, (uint32_t)s.tsize) | 0ull;
+}
+__device__ __forceinline__ uint64_t slot_next(const Store& s, uint64_t pos) {
+    return pos + 1 == s.tsize ? 0 : pos + 1;
 }
 
 // Outcome of probing one candidate.
@@ -264,18 +275,21 @@ enum : uint32_t { P_SKIP = 0, P_DUP = 1, P_DEFER = 2, P_WON = 3, P_FULL = 4 };
 // already loaded (cur0, so that several first probes can be in flight), until
 // an equal stored row is found (DUP), a matching slot of the running launch is
 // met (DEFER; pos = that slot), or an empty slot is reserved (WON; pos = that
-// slot).  FULL: no free slot in the whole table.  Rows with index >= snap
-// were allocated by the running launch and are not read.
+// slot).  FULL: no free slot in the whole table, or the store has already
+// overflowed (full_store: no more slots are reserved; the caller only checks
+// the candidate).  Rows with index >= snap were allocated by the running
+// launch and are not read.
 template <class Emit>
 __device__ uint32_t probe_reserve(const Store& s, uint64_t h, uint64_t& pos, uint64_t cur0,
-                                  uint64_t snap, const Emit& e) {
+                                  uint64_t snap, bool full_store, const Emit& e) {
     const uint32_t tag = tag_of(h);
     const uint64_t hi = (uint64_t)tag << 32;
     uint64_t cur = cur0;
     for (uint64_t steps = 0;; ++steps) {
-        if (steps > s.tmask) return P_FULL;
+        if (steps > s.tsize) return P_FULL;
         if (steps) cur = slot_load(&s.table[pos]);
         if (cur == kEmpty) {
+            if (full_store) return P_FULL;
             const uint64_t old = slot_cas(&s.table[pos], kEmpty, hi | kPending);
             if (old == kEmpty) return P_WON;
             cur = old;
@@ -285,7 +299,7 @@ __device__ uint32_t probe_reserve(const Store& s, uint64_t h, uint64_t& pos, uin
             if (cidx == kPending || cidx >= snap) return P_DEFER;
             if (emit_equal_row(s, cidx, e)) return P_DUP;
         }
-        pos = (pos + 1) & s.tmask;
+        pos = slot_next(s, pos);
     }
 }
 
@@ -307,8 +321,7 @@ __device__ __forceinline__ void write_row(const Store& s, const Masks& m, uint32
         acc |= check_vec(m, w, v);
         return true;
     });
-    s.meta[r] = make_uint4(op, L, R, 0);
-    s.rhash[r] = h;
+    s.meta[r] = make_uint4(op | (tag_of(h) << 3), L, R, (uint32_t)h);
     slot_store(&s.table[pos], ((uint64_t)tag_of(h) << 32) | (uint32_t)r);
     if (acc == 0) report_found(s, op, L, R);
 }
@@ -326,7 +339,7 @@ __device__ __forceinline__ void write_defer(const Store& s, unsigned long long d
 template <class Emit>
 __device__ void insert_emit(const Store& s, const Masks& m, uint32_t op, uint32_t L, uint32_t R,
                             uint64_t h, uint64_t pos, uint64_t cur0, uint64_t snap, const Emit& e) {
-    const uint32_t o = probe_reserve(s, h, pos, cur0, snap, e);
+    const uint32_t o = probe_reserve(s, h, pos, cur0, snap, s.ctr[C_OVERFLOW] != 0, e);
     if (o == P_WON) {
         write_row(s, m, op, L, R, h, pos, wave_alloc(&s.ctr[C_ROWS]), e);
     } else if (o == P_DEFER) {
@@ -349,7 +362,7 @@ __device__ __forceinline__ void process(const Store& s, uint32_t op, uint32_t L,
                                         uint64_t snap) {
     const GlobalEmit e{s, op, L, R};
     const uint64_t h = emit_hash(s, e);
-    const uint64_t pos = h & s.tmask;
+    const uint64_t pos = slot_of(s, h);
     insert_emit(s, global_masks(s), op, L, R, h, pos, slot_load(&s.table[pos]), snap, e);
 }
 
@@ -440,7 +453,7 @@ __global__ __launch_bounds__(kLanes) void k_generate(Store s, SegTable t) {
         const uint64_t vl = lt * kLanes + tid;
         if (vl < g.nb) {
             const uint32_t v = (uint32_t)(g.b0 + vl);
-            const uint32_t vop = s.meta[v].x;
+            const uint32_t vop = s.meta[v].x & 7u;
             // not not a = a, F F a = F a, G G a = G a: those candidates are
             // cheaper formulas' CMs and are skipped without changing any set.
             if ((g.opmask & M_NOT) && vop != OP_NOT) { process(s, OP_NOT, v, 0, snap); ++count; }
@@ -535,14 +548,15 @@ __device__ __forceinline__ void cand_begin(const Store& s, Cand& c, bool enabled
     });
     if (check_eq && (ea == 0 || eb == 0)) return;
     c.h = hs.fin() & s.hmask;
-    c.pos = c.h & s.tmask;
+    c.pos = slot_of(s, c.h);
     c.cur = slot_load(&s.table[c.pos]);
     c.out = P_WON;
 }
 
 template <class Emit>
-__device__ __forceinline__ void cand_probe(const Store& s, Cand& c, uint64_t snap, const Emit& e) {
-    if (c.out == P_WON) c.out = probe_reserve(s, c.h, c.pos, c.cur, snap, e);
+__device__ __forceinline__ void cand_probe(const Store& s, Cand& c, uint64_t snap, bool full_store,
+                                           const Emit& e) {
+    if (c.out == P_WON) c.out = probe_reserve(s, c.h, c.pos, c.cur, snap, full_store, e);
 }
 
 template <class Emit>
@@ -572,6 +586,7 @@ __host__ __device__ __forceinline__ uint32_t lds_stride(uint32_t nq) { return nq
 // operators are issued before any is waited on, and rows and deferral records
 // are allocated with one atomic per counter, wave and pair.  Unary tiles do
 // the same for not, X, F, G over the lane's operand.
+template <int BATCH>
 __global__ __launch_bounds__(kLanes) void k_generate_lds(Store s, SegTable t) {
     extern __shared__ uint4 dyn[];
     const uint32_t NQ = s.Wp / 4, SB = lds_stride(NQ);
@@ -583,6 +598,7 @@ __global__ __launch_bounds__(kLanes) void k_generate_lds(Store s, SegTable t) {
     const uint64_t tile = t.tile_begin + blockIdx.x;
     if (tile >= t.tile_end) return;
     const uint64_t snap = s.ctr[C_SNAP];
+    const bool full_store = s.ctr[C_OVERFLOW] != 0;
     uint32_t si = 0;
     while (si + 1 < t.n && t.first[si + 1] <= tile) ++si;
     const Seg& g = t.seg[si];
@@ -610,30 +626,35 @@ __global__ __launch_bounds__(kLanes) void k_generate_lds(Store s, SegTable t) {
         const uint32_t vi = (uint32_t)(g.b0 + (ok ? vl : 0));
         for (uint32_t q = 0; q < NQ; ++q) mine[q] = ok ? rows4[(uint64_t)vi * NQ + q] : make_uint4(0, 0, 0, 0);
         __syncthreads();
-        const uint32_t vop = ok ? s.meta[vi].x : OP_ATOM;
+        const uint32_t vop = ok ? (s.meta[vi].x & 7u) : OP_ATOM;
         // not not a, F F a, G G a are cheaper formulas' CMs: skipped.  A result
         // equal to a (possible for X, F, G) is a sure duplicate.
         constexpr uint32_t ops[4] = {OP_NOT, OP_X, OP_F, OP_G};
         constexpr uint32_t bits[4] = {M_NOT, M_X, M_F, M_G};
-        Cand c[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const bool en = ok && (g.opmask & bits[j]) && (j == 1 || vop != ops[j]);
-            cand_begin(s, c[j], en, j != 0, mine, mine, LdsUnaryEmit{mine, sh_v, NQ, ops[j]});
-            count += en;
+        for (int j0 = 0; j0 < 4; j0 += BATCH) {
+            Cand c[BATCH];
+#pragma unroll
+            for (int jj = 0; jj < BATCH; ++jj) {
+                const int j = j0 + jj;
+                const bool en = ok && (g.opmask & bits[j]) && (j == 1 || vop != ops[j]);
+                cand_begin(s, c[jj], en, j != 0, mine, mine, LdsUnaryEmit{mine, sh_v, NQ, ops[j]});
+                count += en;
+            }
+            uint32_t nrow = 0, ndef = 0;
+#pragma unroll
+            for (int jj = 0; jj < BATCH; ++jj) {
+                cand_probe(s, c[jj], snap, full_store, LdsUnaryEmit{mine, sh_v, NQ, ops[j0 + jj]});
+                nrow += c[jj].out == P_WON;
+                ndef += c[jj].out == P_DEFER;
+            }
+            unsigned long long rb, db;
+            wave_alloc2(s, nrow, ndef, rb, db);
+#pragma unroll
+            for (int jj = 0; jj < BATCH; ++jj)
+                cand_finish(s, m, c[jj], ops[j0 + jj], vi, 0, rb, db,
+                            LdsUnaryEmit{mine, sh_v, NQ, ops[j0 + jj]});
         }
-        uint32_t nrow = 0, ndef = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            cand_probe(s, c[j], snap, LdsUnaryEmit{mine, sh_v, NQ, ops[j]});
-            nrow += c[j].out == P_WON;
-            ndef += c[j].out == P_DEFER;
-        }
-        unsigned long long rb, db;
-        wave_alloc2(s, nrow, ndef, rb, db);
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            cand_finish(s, m, c[j], ops[j], vi, 0, rb, db, LdsUnaryEmit{mine, sh_v, NQ, ops[j]});
     } else {
         uint64_t ta, tb;
         if (g.tri) {
@@ -661,27 +682,35 @@ __global__ __launch_bounds__(kLanes) void k_generate_lds(Store s, SegTable t) {
             const bool ok = valid && !(g.tri && al >= bl);  // pairs a < b only
             const uint32_t ai = (uint32_t)(g.a0 + al);
             const uint4* arow = sh_a + i * NQ;
-            Cand c[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const bool en = ok && (g.opmask & bits[j]);
-                const LdsPairEmit e{j == 3 ? mine : arow, j == 3 ? arow : mine, NQ, ops[j]};
-                cand_begin(s, c[j], en, true, arow, mine, e);
-                count += en;
+            for (int j0 = 0; j0 < 4; j0 += BATCH) {
+                Cand c[BATCH];
+#pragma unroll
+                for (int jj = 0; jj < BATCH; ++jj) {
+                    const int j = j0 + jj;
+                    const bool en = ok && (g.opmask & bits[j]);
+                    const LdsPairEmit e{j == 3 ? mine : arow, j == 3 ? arow : mine, NQ, ops[j]};
+                    cand_begin(s, c[jj], en, true, arow, mine, e);
+                    count += en;
+                }
+                uint32_t nrow = 0, ndef = 0;
+#pragma unroll
+                for (int jj = 0; jj < BATCH; ++jj) {
+                    const int j = j0 + jj;
+                    cand_probe(s, c[jj], snap, full_store,
+                               LdsPairEmit{j == 3 ? mine : arow, j == 3 ? arow : mine, NQ, ops[j]});
+                    nrow += c[jj].out == P_WON;
+                    ndef += c[jj].out == P_DEFER;
+                }
+                unsigned long long rb, db;
+                wave_alloc2(s, nrow, ndef, rb, db);
+#pragma unroll
+                for (int jj = 0; jj < BATCH; ++jj) {
+                    const int j = j0 + jj;
+                    cand_finish(s, m, c[jj], ops[j], j == 3 ? bi : ai, j == 3 ? ai : bi, rb, db,
+                                LdsPairEmit{j == 3 ? mine : arow, j == 3 ? arow : mine, NQ, ops[j]});
+                }
             }
-            uint32_t nrow = 0, ndef = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                cand_probe(s, c[j], snap, LdsPairEmit{j == 3 ? mine : arow, j == 3 ? arow : mine, NQ, ops[j]});
-                nrow += c[j].out == P_WON;
-                ndef += c[j].out == P_DEFER;
-            }
-            unsigned long long rb, db;
-            wave_alloc2(s, nrow, ndef, rb, db);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                cand_finish(s, m, c[j], ops[j], j == 3 ? bi : ai, j == 3 ? ai : bi, rb, db,
-                            LdsPairEmit{j == 3 ? mine : arow, j == 3 ? arow : mine, NQ, ops[j]});
         }
     }
     unsigned long long cc = count;
@@ -703,7 +732,7 @@ __global__ __launch_bounds__(kLanes) void k_verify_deferred(Store s) {
         const uint64_t h = cm_hash(s, op, rec.y, rec.z);
         const uint32_t tag = tag_of(h);
         for (uint64_t steps = 0;; ++steps) {
-            if (steps > s.tmask) {
+            if (steps > s.tsize) {
                 atomicExch(&s.ctr[C_OVERFLOW], 1ull);
                 check_only(s, op, rec.y, rec.z);
                 break;
@@ -723,7 +752,7 @@ __global__ __launch_bounds__(kLanes) void k_verify_deferred(Store s) {
                 }
                 if (cm_equal_row(s, op, rec.y, rec.z, cidx)) break;
             }
-            pos = (pos + 1) & s.tmask;
+            pos = slot_next(s, pos);
         }
     }
 }
@@ -760,15 +789,15 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
 __global__ __launch_bounds__(kLanes) void k_rehash(Store s, uint64_t n_rows) {
     const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_rows) return;
-    const uint64_t h = s.rhash[r];
-    const uint64_t want = ((uint64_t)tag_of(h) << 32) | (uint32_t)r;
-    uint64_t pos = h & s.tmask;
+    const uint4 mt = s.meta[r];
+    const uint64_t want = ((uint64_t)(mt.x >> 3) << 32) | (uint32_t)r;
+    uint64_t pos = (uint64_t)__umulhi(mt.w, (uint32_t)s.tsize);
     for (uint64_t steps = 0; slot_cas(&s.table[pos], kEmpty, want) != kEmpty; ++steps) {
-        if (steps > s.tmask) {
+        if (steps > s.tsize) {
             atomicExch(&s.ctr[C_OVERFLOW], 1ull);
             return;
         }
-        pos = (pos + 1) & s.tmask;
+        pos = slot_next(s, pos);
     }
 }
 
@@ -864,13 +893,13 @@ __global__ void k_formula(const uint4* meta, uint32_t root_op, uint32_t root_a, 
         if (op == OP_ATOM) continue;
         if (op >= OP_AND) {  // right child below the left child on the stack
             const uint4 rb = meta[b];
-            stk[3 * sp] = rb.x;
+            stk[3 * sp] = rb.x & 7u;
             stk[3 * sp + 1] = rb.y;
             stk[3 * sp + 2] = rb.z;
             ++sp;
         }
         const uint4 ra = meta[a];
-        stk[3 * sp] = ra.x;
+        stk[3 * sp] = ra.x & 7u;
         stk[3 * sp + 1] = ra.y;
         stk[3 * sp + 2] = ra.z;
         ++sp;
@@ -898,6 +927,13 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st) 
     return hipGetLastError();
 }
 
+// Candidates a lane keeps in flight in the LDS-staged kernel (1, 2 or 4 of a
+// pair's or operand's operators between allocation points).
+#ifndef LTLF_BATCH
+#define LTLF_BATCH 4
+#endif
+constexpr int kBatch = LTLF_BATCH;
+
 uint64_t lds_bytes(uint32_t Wp) {
     const uint32_t nq = Wp / 4;
     return 16ull * (kLanes * lds_stride(nq) + kTileA * nq + 3ull * nq);
@@ -911,13 +947,13 @@ hipError_t launch_generate(const Store& s, const SegTable& t, uint64_t lds_limit
     if (lds <= lds_limit) {
         static uint64_t raised = 0;  // largest dynamic LDS size enabled so far
         if (lds > 65536 && lds > raised) {
-            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_generate_lds),
+            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_generate_lds<kBatch>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                                      (int)lds);
             if (e != hipSuccess) return e;
             raised = lds;
         }
-        hipLaunchKernelGGL(k_generate_lds, grid, block, (uint32_t)lds, st, s, t);
+        hipLaunchKernelGGL(k_generate_lds<kBatch>, grid, block, (uint32_t)lds, st, s, t);
     } else {
         hipLaunchKernelGGL(k_generate, grid, block, 0, st, s, t);
     }

@@ -35,6 +35,27 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
+def profiled_traffic(kernel_prefix: str, workload_tag: str):
+    """HBM bytes per launch of the dominant kernel from a committed rocprofv3
+    summary (profiles/*.txt), if that summary was taken on the current kernel
+    source (same sha256) and workload; else None."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2504_18943_amd", "csrc", "ltlf_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
+        fields = {}
+        for line in open(path):
+            if ":" in line:
+                key, _, val = line.partition(":")
+                fields[key.strip()] = val.strip()
+        if (fields.get("kernel_source_sha256") == sha and workload_tag in fields.get("command", "")
+                and fields.get("dominant_kernel", "").startswith(kernel_prefix)
+                and "traffic_bytes_per_launch" in fields):
+            return float(fields["traffic_bytes_per_launch"]), os.path.basename(path)
+    return None, None
+
+
 def cpu_baseline(seed: int, bound: int):
     import oracle
     import workload
@@ -126,9 +147,14 @@ def main() -> int:
     launches = last.gen_launches
     bytes_per_step = last.candidates * (last.row_bytes + 8)
     achieved = bytes_per_step / (gen_ms / 1e3) / 1e9 if gen_ms > 0 else 0.0
+    traffic, prof_file = profiled_traffic("ltlf::k_generate", f"--bound {args.bound} ")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_generate", "launches_per_step": launches,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": round(traffic) if traffic else None,
+            "traffic_unit": "HBM bytes per launch (2 x FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_source": prof_file,
+            "algorithmic_bytes_per_launch": round(bytes_per_step / max(launches, 1)),
+            "kernel": "generation (k_generate*)", "launches_per_step": launches,
             "avg_launch_ms": round(gen_ms / max(launches, 1), 4),
             "bytes_per_candidate": last.row_bytes + 8}
 

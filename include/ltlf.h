@@ -96,6 +96,14 @@ typedef struct {
 #define LTLF_FLAG_PROFILE 0x2u /* time every generation and verification launch
                                   with HIP events on the run's stream and
                                   report the sums (gen_ms, verify_ms) */
+#define LTLF_FLAG_KERNEL_LANE 0x4u /* generation with one candidate per lane where
+                                  its operand tile fits the LDS (the default
+                                  choice wherever it fits) */
+#define LTLF_FLAG_KERNEL_GROUP 0x8u /* generation with one candidate per group
+                                  of lanes (one 16-byte chunk per lane) where
+                                  rows have 2..64 chunks; else the default.
+                                  Results never depend on the kernel: these
+                                  two flags exist for testing and tuning */
 #define LTLF_FLAG_DEBUG_WEAK_HASH 0x100u /* test hook: keep 6 bits of every hash,
                                   so all candidates share a few slots and one
                                   tag; exercises the verify/defer paths */
@@ -124,6 +132,9 @@ typedef struct {
     double enum_ms;           /* out: stream time of the whole run (events) */
     double gen_ms;            /* out: summed generation kernel time (PROFILE) */
     double verify_ms;         /* out: summed verification kernel time (PROFILE) */
+    uint64_t dead_rows;       /* out: row indices taken but left unused (lost
+                                 slot claims, allocation tails); each level is
+                                 compacted at its end (statistics) */
 } ltlf_result;
 
 typedef struct ltlf_ctx ltlf_ctx;

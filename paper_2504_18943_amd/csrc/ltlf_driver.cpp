@@ -230,9 +230,10 @@ struct LevelPlan {
 // of levels i <= j the binary operators whose cost closes the sum to c.  The
 // larger operand level goes to the lanes; a pair (a, b) yields a&b, a|b,
 // aUb and bUa, so each unordered pair of representatives is visited once.
-LevelPlan plan_level(const ltlf_ctx* c, const ltlf_costs* k, uint32_t lev) {
+LevelPlan plan_level(const ltlf_ctx* c, const ltlf_costs* k, uint32_t lev, const TileShape& ts) {
     LevelPlan p;
     auto cnt = [&](uint32_t i) -> uint64_t { return i < c->lcount.size() ? c->lcount[i] : 0; };
+    auto ceil_div = [](uint64_t a, uint64_t b) { return (a + b - 1) / b; };
     if (lev == k->atom_cost) {
         Seg g{};
         g.kind = SEG_ATOM;
@@ -253,9 +254,9 @@ LevelPlan plan_level(const ltlf_ctx* c, const ltlf_costs* k, uint32_t lev) {
         g.opmask = mask;
         g.b0 = c->lstart[src];
         g.nb = cnt(src);
-        g.tiles = (g.nb + kLanes - 1) / kLanes;
+        g.tiles = ceil_div(g.nb, ts.tu);
         p.segs.push_back(g);
-        p.cand_per_tile.push_back((uint64_t)kLanes * __builtin_popcount(mask));
+        p.cand_per_tile.push_back((uint64_t)std::min<uint64_t>(ts.tu, g.nb) * __builtin_popcount(mask));
     }
     // binary
     for (uint32_t i = 1; i < lev; ++i) {
@@ -274,21 +275,25 @@ LevelPlan plan_level(const ltlf_ctx* c, const ltlf_costs* k, uint32_t lev) {
                 g.tri = 1;
                 g.a0 = g.b0 = c->lstart[i];
                 g.na = g.nb = n;
-                const uint64_t K = (n + kLanes - 1) / kLanes;
-                const uint64_t ta = (n + kTileA - 1) / kTileA;
-                g.tiles = 8ull * (K - 1) * K + ta;
+                if (ts.square_tri) {
+                    const uint64_t T = ceil_div(n, ts.ta);
+                    g.tiles = T * (T + 1) / 2;
+                } else {
+                    const uint64_t K = ceil_div(n, ts.tb);
+                    g.tiles = 8ull * (K - 1) * K + ceil_div(n, ts.ta);
+                }
             } else {
-                // lanes take the larger level
+                // lanes (the right operand) take the larger level
                 uint32_t la = i, lb = j;
                 if (cnt(i) > cnt(j)) std::swap(la, lb);
                 g.a0 = c->lstart[la];
                 g.na = cnt(la);
                 g.b0 = c->lstart[lb];
                 g.nb = cnt(lb);
-                g.tiles = ((g.na + kTileA - 1) / kTileA) * ((g.nb + kLanes - 1) / kLanes);
+                g.tiles = ceil_div(g.na, ts.ta) * ceil_div(g.nb, ts.tb);
             }
             p.segs.push_back(g);
-            p.cand_per_tile.push_back((uint64_t)kLanes * std::min<uint64_t>(kTileA, g.na) *
+            p.cand_per_tile.push_back(std::min<uint64_t>(ts.ta, g.na) * std::min<uint64_t>(ts.tb, g.nb) *
                                       __builtin_popcount(mask));
         }
     }
@@ -500,14 +505,19 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
     res->enum_ms = 0.0;
     res->gen_ms = 0.0;
     res->verify_ms = 0.0;
+    res->dead_rows = 0;
     const bool profile = (flags & LTLF_FLAG_PROFILE) != 0;
     Profiler prof;
     prof.c = c;
     c->ran = false;
     c->lstart.assign(bound + 1, 0);
     c->lcount.assign(bound + 1, 0);
-    c->st.cap = c->row_limit ? std::min(c->plan_cap, c->row_limit) : c->plan_cap;
+    c->st.cap = c->plan_cap;  // the row limit is applied to live rows per level
     c->st.hmask = (flags & LTLF_FLAG_DEBUG_WEAK_HASH) ? 0x3Full : ~0ull;
+    const uint32_t pref = (flags & LTLF_FLAG_KERNEL_GROUP) ? KERNEL_GROUP
+                          : (flags & LTLF_FLAG_KERNEL_LANE) ? KERNEL_LANE : KERNEL_AUTO;
+    const TileShape shape = tile_shape(c->Wp, c->lds_limit, pref);
+    c->st.kernel = shape.kind;
 
     hipEvent_t e0, e1;
     TRY_HIP(hipEventCreate(&e0));
@@ -537,7 +547,7 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
 
     for (uint32_t lev = 1; lev <= bound; ++lev) {
         c->lstart[lev] = rows;
-        LevelPlan p = plan_level(c, k, lev);
+        LevelPlan p = plan_level(c, k, lev, shape);
         if (p.segs.empty()) {
             res->levels_done = lev;
             continue;
@@ -557,8 +567,9 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
             TRY(ensure_table(c, rows, std::min<uint64_t>(est, c->st.cap - rows), s));
         }
         uint64_t rows_ub = rows;
-        // launch in groups of at most kMaxSegs segments, each split into
-        // chunks whose candidates fit the deferral list
+        TRY_HIP(launch_set_counter(c->d_ctr, C_DEAD, 0, s));
+        const bool persistent = shape.kind == KERNEL_GROUP;
+        // launch in groups of at most kMaxSegs segments
         for (size_t g0 = 0; g0 < p.segs.size(); g0 += kMaxSegs) {
             const size_t g1 = std::min(p.segs.size(), g0 + kMaxSegs);
             SegTable t{};
@@ -568,8 +579,65 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
                 t.seg[q - g0] = p.segs[q];
                 t.first[q - g0 + 1] = t.first[q - g0] + p.segs[q].tiles;
             }
-            uint64_t tile = 0;
             const uint64_t total = t.first[t.n];
+            if (persistent) {
+                // persistent group kernel: resident blocks pull tiles from a
+                // cursor and stop while the deferral list or the table could
+                // not take every candidate of the tiles in flight (one per
+                // block, plus each wave's allocation chunk); the host empties
+                // the list, grows the table if needed, and launches again
+                uint64_t per_tile = 0;
+                for (size_t q = g0; q < g1; ++q) per_tile = std::max(per_tile, p.cand_per_tile[q]);
+                const uint64_t per_block = per_tile + (kLanes / 64) * kAllocChunk;
+                uint64_t blocks = 0;
+                TRY_HIP(generate_blocks(c->st, total, blocks));
+                blocks = std::max<uint64_t>(1, std::min<uint64_t>(blocks, c->st.def0_cap / (2 * per_block)));
+                const uint64_t margin = blocks * per_block;
+                t.tile_begin = 0;
+                t.tile_end = total;
+                t.def_margin = margin;
+                t.row_margin = margin;
+                TRY_HIP(launch_set_counter(c->d_ctr, C_TILE, 0, s));
+                uint64_t taken = 0, ctr_rows = rows_ub;
+                for (;;) {
+                    if (2 * (ctr_rows + margin) > c->st.tsize && c->st.tsize < c->table_max) {
+                        // room for the margin, and for the rest of the group at
+                        // the yield seen so far
+                        uint64_t extra = margin;
+                        if (taken > 0 && ctr_rows > rows)
+                            extra = std::max<uint64_t>(
+                                extra, (uint64_t)(1.25 * (double)(ctr_rows - rows) / (double)taken *
+                                                  (double)(total - taken)));
+                        const uint64_t stored = std::min<uint64_t>(ctr_rows, c->st.cap);
+                        TRY(ensure_table(c, stored, extra + (ctr_rows - stored), s));
+                    }
+                    t.row_budget = c->st.tsize < c->table_max ? c->st.tsize / 2 : ~0ull;
+                    if (profile) TRY(prof.mark(s));
+                    TRY_HIP(launch_generate(c->st, t, blocks, s));
+                    if (profile) TRY(prof.mark(s));
+                    TRY_HIP(launch_verify_deferred(c->st, s));
+                    if (profile) TRY(prof.mark(s));
+                    ++res->gen_launches;
+                    ++res->verify_launches;
+                    TRY_HIP(launch_between(c->d_ctr, s));
+                    TRY(read_counters(c, s));
+                    const uint64_t now_taken = std::min<uint64_t>(c->h_ctr[C_TILE], total);
+                    ctr_rows = c->h_ctr[C_ROWS];
+                    if (now_taken >= total) break;
+                    if (now_taken == taken) {  // not expected: the table was sized for the margin
+                        if (c->st.tsize >= c->table_max)
+                            return fail(c, LTLF_EDEVICE, "generation made no progress");
+                        const uint64_t stored = std::min<uint64_t>(ctr_rows, c->st.cap);
+                        TRY(ensure_table(c, stored, c->st.tsize, s));
+                    }
+                    taken = now_taken;
+                }
+                rows_ub = std::min<uint64_t>(ctr_rows, c->st.cap);
+                continue;
+            }
+            // one block per tile: split into launches whose candidates fit
+            // the deferral list
+            uint64_t tile = 0;
             while (tile < total) {
                 uint64_t budget = c->st.def0_cap, end = tile;
                 uint32_t si = 0;
@@ -594,7 +662,7 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
                 t.tile_begin = tile;
                 t.tile_end = end;
                 if (profile) TRY(prof.mark(s));
-                TRY_HIP(launch_generate(c->st, t, c->lds_limit, s));
+                TRY_HIP(launch_generate(c->st, t, 0, s));
                 if (profile) TRY(prof.mark(s));
                 TRY_HIP(launch_verify_deferred(c->st, s));
                 if (profile) TRY(prof.mark(s));
@@ -624,10 +692,31 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
         }
         if (c->h_ctr[C_DEF_OVF]) return fail(c, LTLF_EDEVICE, "deferral list overflow");
         const uint64_t now = std::min<uint64_t>(c->h_ctr[C_ROWS], c->st.cap);
-        c->lcount[lev] = now - rows;
-        rows = now;
+        const uint64_t dead = c->h_ctr[C_DEAD];
+        res->dead_rows += dead;
+        if (dead > now - rows) return fail(c, LTLF_EDEVICE, "dead row count exceeds the level");
+        const uint64_t live_end = now - dead;
         candidates = c->h_ctr[C_CAND];
-        const bool overflow = c->h_ctr[C_OVERFLOW] != 0;
+        // the caller's row limit counts live rows only (unused allocation
+        // tails do not count against it)
+        const bool overflow = c->h_ctr[C_OVERFLOW] != 0 || (c->row_limit && live_end > c->row_limit);
+        if (!overflow && dead) {
+            // move the live rows above live_end into the holes below it, in
+            // rounds of at most `lcap` (the deferral list is free now)
+            const uint64_t lcap = 2 * c->st.def0_cap;
+            uint32_t* holes = reinterpret_cast<uint32_t*>(c->st.def0);
+            for (uint64_t done = 0; done < dead; done += lcap) {
+                TRY_HIP(launch_set_counter(c->d_ctr, C_NH, 0, s));
+                TRY_HIP(launch_set_counter(c->d_ctr, C_NM, 0, s));
+                TRY_HIP(launch_compact(c->st, rows, live_end, now, holes, holes + lcap, lcap, s));
+            }
+            // the next level allocates from the compacted end, and its first
+            // launch treats exactly the rows below it as written before it
+            TRY_HIP(launch_set_counter(c->d_ctr, C_ROWS, live_end, s));
+            TRY_HIP(launch_set_counter(c->d_ctr, C_SNAP, live_end, s));
+        }
+        c->lcount[lev] = live_end - rows;
+        rows = live_end;
         if (c->h_ctr[C_FOUND] && status != LTLF_OK) {
             status = LTLF_OK;
             res->min_cost = lev;

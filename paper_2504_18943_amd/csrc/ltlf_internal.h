@@ -46,7 +46,11 @@ enum : uint32_t {
     C_DEFERRED = 10,  // total deferrals (statistics)
     C_VERIFY = 11,    // verification reads (statistics)
     C_SNAP = 12,      // row count when the running inserting launch started
-    C_NUM = 16,
+    C_TILE = 13,      // group kernel: tile cursor, kept over the launches of one segment table
+    C_DEAD = 14,      // rows of the level left unused (retired chunk tails)
+    C_NH = 15,        // compaction: holes found
+    C_NM = 16,        // compaction: rows to move
+    C_NUM = 24,
 };
 
 enum : uint32_t { SEG_ATOM = 0, SEG_UNARY = 1, SEG_PAIR = 2 };
@@ -54,6 +58,7 @@ enum : uint32_t { SEG_ATOM = 0, SEG_UNARY = 1, SEG_PAIR = 2 };
 constexpr uint32_t kLanes = 256;   // workgroup size; lane operand tile
 constexpr uint32_t kTileA = 16;    // loop operands per pair tile
 constexpr uint32_t kMaxSegs = 40;  // segments per launch
+constexpr uint32_t kAllocChunk = 64;  // rows / records a wave takes per atomic (group kernel)
 
 struct Seg {
     uint32_t kind;    // SEG_*
@@ -70,6 +75,10 @@ struct SegTable {
     uint32_t pad;
     uint64_t tile_begin;  // first tile (inclusive) handled by this launch
     uint64_t tile_end;    // last tile (exclusive)
+    // persistent group kernel only (tiles [0, tile_end) from the C_TILE
+    // cursor): a block takes a tile only while C_DEF0 + def_margin <= the
+    // deferral capacity and C_ROWS + row_margin <= row_budget
+    uint64_t def_margin, row_margin, row_budget;
     uint64_t first[kMaxSegs + 1];  // prefix sums of tiles
     Seg seg[kMaxSegs];
 };
@@ -92,6 +101,8 @@ struct Store {
     uint64_t hmask;         // hash mask (all ones; fewer bits force collisions in tests)
     uint32_t Wp;            // words per row (multiple of 4)
     uint32_t n_props;
+    uint32_t kernel;        // KERNEL_* generation kernel of the run
+    uint32_t pad;
 };
 
 // Launchers (defined in ltlf_kernels.hip).
@@ -100,10 +111,24 @@ hipError_t launch_encode(const uint32_t* letters, const uint32_t* lengths, const
                          uint32_t n_props, uint32_t Wp, uint32_t* V, uint32_t* S, uint32_t* P0,
                          uint32_t* atoms, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st);
-// Dynamic LDS bytes of the LDS-staged generation kernel for rows of Wp words;
-// rows needing more than lds_limit use the generic kernel.
+// Generation kernel chosen for rows of Wp words, and its tile shape: pair
+// tiles of ta left x tb right operands, unary tiles of tu operands; triangular
+// (same-level) pair segments use square tiles if square_tri, else columns of
+// 16(k+1) left tiles per right tile k.
+enum : uint32_t { KERNEL_GENERIC = 0, KERNEL_LANE = 1, KERNEL_GROUP = 2, KERNEL_AUTO = 3 };
+struct TileShape {
+    uint32_t kind, ta, tb, tu, square_tri;
+};
+// Generation kernel and tile for rows of Wp words.  pref: KERNEL_LANE or
+// KERNEL_GROUP asks for that kernel where it fits, anything else is the
+// default (lane kernel where its tile fits the LDS, else the group kernel,
+// else the generic one).
+TileShape tile_shape(uint32_t Wp, uint64_t lds_limit, uint32_t pref);
 uint64_t lds_bytes(uint32_t Wp);
-hipError_t launch_generate(const Store& s, const SegTable& t, uint64_t lds_limit, hipStream_t st);
+// Grid of the generation launch: the tile count, or for the persistent group
+// kernel the resident block count (at most the tile count).
+hipError_t generate_blocks(const Store& s, uint64_t n_tiles, uint64_t& blocks);
+hipError_t launch_generate(const Store& s, const SegTable& t, uint64_t blocks, hipStream_t st);
 hipError_t launch_verify_deferred(const Store& s, hipStream_t st);
 hipError_t launch_reinsert(const Store& s, uint64_t n, hipStream_t st);
 // Sets C_DEF0 = 0 and C_SNAP = C_ROWS; must run between any launch that
@@ -112,6 +137,11 @@ hipError_t launch_between(unsigned long long* ctr, hipStream_t st);
 hipError_t launch_set_counter(unsigned long long* ctr, uint32_t which, unsigned long long v,
                               hipStream_t st);
 hipError_t launch_rehash(const Store& s, uint64_t n_rows, hipStream_t st);
+// Level compaction over [lo, hi) (one round): lists up to `cap` holes below
+// new_end and live rows above it (C_NH, C_NM must be zero), then moves rows
+// and repoints their table slots.
+hipError_t launch_compact(const Store& s, uint64_t lo, uint64_t new_end, uint64_t hi, uint32_t* holes,
+                          uint32_t* movers, uint64_t cap, hipStream_t st);
 hipError_t launch_export(const uint32_t* rows, uint32_t Wp, uint64_t first, uint64_t n,
                          const uint32_t* canon_bit, uint64_t n_bits, uint64_t* out, hipStream_t st);
 // tokens must hold 1 + max_tokens + 3 * (max_tokens + 1) words (list + stack).

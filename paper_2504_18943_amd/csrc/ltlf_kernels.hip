@@ -49,6 +49,10 @@ namespace ltlf {
 
 static constexpr uint64_t kEmpty = ~0ull;
 static constexpr uint32_t kPending = 0xFFFFFFFFu;
+// Derivation record of a row index that was allocated but never used (y),
+// and operator code of an unused deferral record.
+static constexpr uint32_t kDead = 0xFFFFFFFFu;
+static constexpr uint32_t kNoRecord = 0xFu;
 
 // ----------------------------------------------------------- table atomics --
 __device__ __forceinline__ uint64_t slot_load(uint64_t* p) {
@@ -76,31 +80,32 @@ __device__ __forceinline__ unsigned long long wave_alloc(unsigned long long* ctr
 }
 
 // ----------------------------------------------------------------- hashing --
-// Per word: three full-rate ops per state word (xor, rotate, add/xor), then
-// a 64-bit finaliser.  Only speed depends on the quality: every match is
-// verified against the full row.
+// Hash of a CM: the XOR over its 16-byte chunks k of chunk_hash(k, chunk),
+// then a 64-bit finaliser.  Chunks are independent, so a group of lanes that
+// holds one chunk each combines its parts with shuffles, and every kernel
+// (one lane per candidate or one group per candidate) gets the same value.
+// Only speed depends on the quality: every match is verified against the
+// full row.
+__device__ __forceinline__ uint64_t chunk_hash(uint32_t k, uint4 r) {
+    const uint64_t a = ((uint64_t)r.y << 32) | r.x;
+    const uint64_t b = ((uint64_t)r.w << 32) | r.z;
+    uint64_t h = (a ^ ((uint64_t)(k + 1) * 0x9E3779B97F4A7C15ull)) * 0xbf58476d1ce4e5b9ull;
+    h ^= (b + (h >> 31)) * 0x94d049bb133111ebull;
+    return h ^ (h >> 29);
+}
+__device__ __forceinline__ uint64_t hash_fin(uint64_t k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
 struct Hash {
-    uint32_t x = 0x243F6A88u, y = 0x85A308D3u;
-    __device__ __forceinline__ void add(uint32_t w) {
-        const uint32_t a = w ^ x;
-        x = ((a << 11) | (a >> 21)) + y;
-        y = ((y << 7) | (y >> 25)) ^ a;
-    }
-    __device__ __forceinline__ void add4(uint4 r) {
-        add(r.x);
-        add(r.y);
-        add(r.z);
-        add(r.w);
-    }
-    __device__ __forceinline__ uint64_t fin() const {
-        uint64_t k = ((uint64_t)x << 32) | y;
-        k ^= k >> 33;
-        k *= 0xff51afd7ed558ccdull;
-        k ^= k >> 33;
-        k *= 0xc4ceb9fe1a85ec53ull;
-        k ^= k >> 33;
-        return k;
-    }
+    uint64_t acc = 0;
+    uint32_t k = 0;
+    __device__ __forceinline__ void add4(uint4 r) { acc ^= chunk_hash(k++, r); }
+    __device__ __forceinline__ uint64_t fin() const { return hash_fin(acc); }
 };
 
 // --------------------------------------------------------------- operators --
@@ -148,6 +153,15 @@ __device__ __forceinline__ uint4 op_vec(uint4 a, uint4 b, uint4 v, uint32_t& st)
     return r;
 }
 
+// *p if c, else zero.  Written as a branch: the select form `c ? p[i] : z`
+// with a zero local becomes a select between p and a stack copy of z, i.e.
+// flat (generic) loads even for LDS and global pointers.
+__device__ __forceinline__ uint4 load_if(bool c, const uint4* p) {
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (c) v = *p;
+    return v;
+}
+
 __device__ __forceinline__ bool is_binary(uint32_t op) { return op >= OP_AND; }
 
 __device__ __forceinline__ const uint32_t* operand(const Store& s, uint32_t op, uint32_t idx) {
@@ -163,7 +177,7 @@ __device__ __forceinline__ void stream_op(const Store& s, const uint32_t* A, con
     const uint4 zero = make_uint4(0, 0, 0, 0);
     for (uint32_t w = 0; w < s.Wp; w += 4) {
         const uint4 a = *reinterpret_cast<const uint4*>(A + w);
-        const uint4 b = is_binary(OP) ? *reinterpret_cast<const uint4*>(B + w) : zero;
+        const uint4 b = load_if(is_binary(OP), reinterpret_cast<const uint4*>(B + w));
         const uint4 v = *reinterpret_cast<const uint4*>(s.V + w);
         if (!fn(w, op_vec<OP>(a, b, v, st))) return;
     }
@@ -519,9 +533,78 @@ __device__ __forceinline__ void wave_alloc2(const Store& s, uint32_t nrow, uint3
     dbase = db + (excl >> 16);
 }
 
+// Per-wave allocator used by the persistent group kernel: row indices and
+// deferral records are taken from the global counters kAllocChunk at a time,
+// so one same-address atomic serves ~kAllocChunk rows (same-address atomics
+// serialise).  A request that does not fit the wave's current chunk takes
+// its rest and a new chunk, so the only unused indices are the tails the
+// waves hold when the launch ends.  Those are retired: rows get a dead
+// derivation record (y = kDead) and are counted in C_DEAD (removed at the end
+// of the level), records get the empty operator code.
+struct WaveAlloc {
+    unsigned long long rnext = 0, rend = 0, dnext = 0, dend = 0;
+};
+
+__device__ __forceinline__ void retire_rows(const Store& s, unsigned long long lo,
+                                            unsigned long long hi) {
+    const unsigned long long top = hi < s.cap ? hi : s.cap;
+    if (lo >= top) return;
+    for (unsigned long long r = lo + __lane_id(); r < top; r += 64) s.meta[r] = make_uint4(0, kDead, 0, 0);
+    if (__lane_id() == 0) atomicAdd(&s.ctr[C_DEAD], top - lo);
+}
+
+__device__ __forceinline__ void retire_records(const Store& s, unsigned long long lo,
+                                               unsigned long long hi) {
+    const unsigned long long top = hi < s.def0_cap ? hi : s.def0_cap;
+    for (unsigned long long r = lo + __lane_id(); r < top; r += 64) s.def0[r] = make_uint4(kNoRecord, 0, 0, 0);
+}
+
+// Wave-uniform: `total` indices are needed, this lane's first is `excl`
+// (each lane takes at most one).  Returns the lane's index.
+__device__ __forceinline__ unsigned long long chunk_take(unsigned long long* ctr, unsigned long long& next,
+                                                         unsigned long long& end, uint32_t total,
+                                                         uint32_t excl) {
+    if (total == 0) return 0;
+    const unsigned long long rem = end - next;
+    if (total <= rem) {
+        const unsigned long long mine = next + excl;
+        next += total;
+        return mine;
+    }
+    const uint32_t need = total - (uint32_t)rem;
+    const uint32_t ch = need > kAllocChunk ? need : kAllocChunk;
+    unsigned long long b = 0;
+    if (__lane_id() == 0) b = atomicAdd(ctr, (unsigned long long)ch);
+    b = __shfl(b, 0, 64);
+    const unsigned long long mine = excl < rem ? next + excl : b + (excl - rem);
+    next = b + need;
+    end = b + ch;
+    return mine;
+}
+
+// Wave-wide (every lane calls it): lane needs nrow rows and ndef records
+// (each 0 or 1); returns its indices.
+__device__ __forceinline__ void wave_take(const Store& s, WaveAlloc& wa, uint32_t nrow,
+                                          uint32_t ndef, unsigned long long& rbase,
+                                          unsigned long long& dbase) {
+    const uint32_t lane = __lane_id();
+    const uint32_t mine = nrow | (ndef << 16);
+    uint32_t incl = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(incl, d, 64);
+        if (lane >= (uint32_t)d) incl += t;
+    }
+    const uint32_t total = __shfl(incl, 63, 64);
+    const uint32_t excl = incl - mine;
+    rbase = chunk_take(&s.ctr[C_ROWS], wa.rnext, wa.rend, total & 0xFFFFu, excl & 0xFFFFu);
+    dbase = chunk_take(&s.ctr[C_DEF0], wa.dnext, wa.dend, total >> 16, excl >> 16);
+}
+
 __device__ __forceinline__ uint32_t diff4(uint4 a, uint4 b) {
     return (a.x ^ b.x) | (a.y ^ b.y) | (a.z ^ b.z) | (a.w ^ b.w);
 }
+
 
 // Per-candidate state of one iteration.
 struct Cand {
@@ -718,6 +801,365 @@ __global__ __launch_bounds__(kLanes) void k_generate_lds(Store s, SegTable t) {
     if (__lane_id() == 0 && cc) atomicAdd(&s.ctr[C_CAND], cc);
 }
 
+// ------------------------------------------------ one lane group per candidate --
+// Rows of 2..64 chunks are handled by groups of G lanes (G = the next power of
+// two >= chunks, at least 4): lane k of a group holds chunk k of the operands
+// and of the candidate.  Carries of the multi-word adds (F, G, U) cross chunk
+// boundaries by carry-lookahead over ballots; the hash, the operand-equality
+// test and the spec check are combined across the group; lanes 0..3 own the
+// table work of the (up to) four candidates of the group's work item, and the
+// whole group verifies and writes rows, so every row access is one coalesced
+// 16*NQ-byte transfer.
+
+constexpr uint32_t kGA = 32;  // left operands per pair tile
+constexpr uint32_t kGB = 32;  // right operands per pair tile (kGA == kGB: square triangles)
+constexpr uint32_t kGU = 64;  // operands per unary tile
+
+// 128-bit add of two chunks with carry-in; *cout receives the carry out.
+__device__ __forceinline__ uint4 add128(uint4 x, uint4 y, uint32_t cin, uint32_t& cout) {
+    uint32_t c = cin;
+    uint4 r;
+    r.x = addc(x.x, y.x, c);
+    r.y = addc(x.y, y.y, c);
+    r.z = addc(x.z, y.z, c);
+    r.w = addc(x.w, y.w, c);
+    cout = c;
+    return r;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t group_bits(uint64_t wave_mask, uint32_t base) {
+    if constexpr (G == 64) return wave_mask;
+    else return (wave_mask >> base) & ((1ull << G) - 1);
+}
+
+// True iff `flag` is clear on every lane of the caller's group (wave-wide
+// ballot: every lane of the wave must call it).
+template <int G>
+__device__ __forceinline__ bool group_none(bool flag, uint32_t base) {
+    return group_bits<G>(__ballot(flag), base) == 0;
+}
+
+// Full multi-chunk sum X + Y for the caller's chunk k of a group: the carry
+// into chunk k is 1 iff a lower chunk generates a carry and every chunk in
+// between propagates it.  With generate bits g and propagate bits p (one per
+// chunk), the carries into all chunks are ((g|p) + g) ^ (g|p) ^ g.
+template <int G>
+__device__ __forceinline__ uint4 group_add(uint4 x, uint4 y, uint32_t base, uint32_t k) {
+    uint32_t co = 0;
+    const uint4 s0 = add128(x, y, 0, co);
+    const bool gen = co != 0;
+    const bool prop = !gen && (s0.x & s0.y & s0.z & s0.w) == 0xFFFFFFFFu;
+    const uint64_t g = group_bits<G>(__ballot(gen), base);
+    const uint64_t p = group_bits<G>(__ballot(prop), base);
+    const uint64_t a = g | p;
+    const uint32_t cin = (uint32_t)((((a + g) ^ a ^ g) >> k) & 1u);
+    uint32_t dummy;
+    return add128(x, y, cin, dummy);
+}
+
+// XOR of a 64-bit value over the caller's group.
+template <int G>
+__device__ __forceinline__ uint64_t group_xor(uint64_t v) {
+#pragma unroll
+    for (int m = 1; m < G; m <<= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
+        const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
+        v ^= ((uint64_t)hi << 32) | lo;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint4 select4(int j, uint4 r0, uint4 r1, uint4 r2, uint4 r3) {
+    return j == 0 ? r0 : j == 1 ? r1 : j == 2 ? r2 : r3;
+}
+
+enum : uint32_t { S_DONE = 0, S_PROBE = 1, S_DUP = 2, S_DEFER = 3, S_WON = 4, S_FULL = 5 };
+
+// Table work of the four candidates of one work item.  Owner lane j (k == j)
+// holds candidate j's state; results r0..r3 are this lane's chunks of the
+// four candidates.  Every lane of the wave must call it (ballots, shuffles).
+template <int G>
+__device__ __forceinline__ void group_insert(const Store& s, WaveAlloc& wa, uint32_t NQ,
+                                             uint32_t base, uint32_t k,
+                                             uint64_t snap, bool full_store, bool active,
+                                             uint64_t h, uint32_t op, uint32_t L, uint32_t R,
+                                             bool sep, uint4 r0, uint4 r1, uint4 r2, uint4 r3) {
+    const uint4* rows4 = reinterpret_cast<const uint4*>(s.rows);
+    const uint32_t tag = tag_of(h);
+    uint32_t st = active ? S_PROBE : S_DONE;
+    uint64_t pos = 0, cur = 0, steps = 0;
+    if (active) {
+        pos = slot_of(s, h);
+        cur = slot_load(&s.table[pos]);
+    }
+    while (__ballot(st == S_PROBE) != 0) {
+        bool need_v = false;
+        uint32_t vrow = 0;
+        if (st == S_PROBE) {
+            if (steps++ >= s.tsize) st = S_FULL;
+            if (st == S_PROBE && cur == kEmpty) {
+                if (full_store) {
+                    st = S_FULL;
+                } else {
+                    const uint64_t old = slot_cas(&s.table[pos], kEmpty, ((uint64_t)tag << 32) | kPending);
+                    if (old == kEmpty) st = S_WON;
+                    else cur = old;
+                }
+            }
+            if (st == S_PROBE) {
+                const uint32_t cidx = (uint32_t)cur;
+                if ((uint32_t)(cur >> 32) == tag) {
+                    if (cidx == kPending || cidx >= snap) st = S_DEFER;
+                    else {
+                        need_v = true;
+                        vrow = cidx;
+                    }
+                } else {
+                    pos = slot_next(s, pos);
+                    cur = slot_load(&s.table[pos]);
+                }
+            }
+        }
+        // verify the owners' rows with the whole group (coalesced reads)
+        const uint64_t nvm = group_bits<G>(__ballot(need_v), base);
+        uint4 m[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t vr = __shfl(vrow, (int)(base + j), 64);
+            m[j] = load_if(((nvm >> j) & 1u) && k < NQ, &rows4[(uint64_t)vr * NQ + k]);
+        }
+        bool eq_mine = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool differ = ((nvm >> j) & 1u) && k < NQ && diff4(m[j], select4(j, r0, r1, r2, r3)) != 0;
+            const bool eq = group_none<G>(differ, base);
+            if (k == (uint32_t)j) eq_mine = eq;
+        }
+        if (need_v) {
+            if (eq_mine) st = S_DUP;
+            else {
+                pos = slot_next(s, pos);
+                cur = slot_load(&s.table[pos]);
+            }
+        }
+    }
+    unsigned long long rb, db;
+    wave_take(s, wa, st == S_WON ? 1u : 0u, st == S_DEFER ? 1u : 0u, rb, db);
+    const uint64_t wonm = group_bits<G>(__ballot(st == S_WON), base);
+    // past the capacity the broadcast index is 0xFFFFFFFF (>= cap): nothing is written
+    const uint32_t myrow = st == S_WON && rb < s.cap ? (uint32_t)rb : 0xFFFFFFFFu;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t rj = __shfl(myrow, (int)(base + j), 64);
+        if (((wonm >> j) & 1u) && rj < s.cap && k < NQ)
+            reinterpret_cast<uint4*>(s.rows)[(uint64_t)rj * NQ + k] = select4(j, r0, r1, r2, r3);
+    }
+    if (st == S_WON) {
+        if (rb >= s.cap) {  // the slot stays reserved; the level will not be stored
+            atomicExch(&s.ctr[C_OVERFLOW], 1ull);
+        } else {
+            s.meta[rb] = make_uint4(op | (tag << 3), L, R, (uint32_t)h);
+            slot_store(&s.table[pos], ((uint64_t)tag << 32) | (uint32_t)rb);
+        }
+        if (sep) report_found(s, op, L, R);
+    } else if (st == S_DEFER) {
+        write_defer(s, db, op, L, R, pos);
+    } else if (st == S_FULL) {
+        atomicExch(&s.ctr[C_OVERFLOW], 1ull);
+        if (sep) report_found(s, op, L, R);
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(kLanes) void k_generate_grp(Store s, SegTable t) {
+    constexpr uint32_t NG = kLanes / G;  // groups per block
+    extern __shared__ uint4 dyn[];
+    __shared__ unsigned long long sh_tile;
+    const uint32_t NQ = s.Wp / 4;
+    uint4* sh_a = dyn;                  // kGA rows (pair tiles)
+    uint4* sh_b = sh_a + kGA * NQ;      // kGB rows (pair tiles) or kGU rows (unary tiles)
+    uint4* sh_v = sh_b + kGU * NQ;
+    uint4* sh_s = sh_v + NQ;
+    uint4* sh_p = sh_s + NQ;
+    const uint64_t snap = s.ctr[C_SNAP];
+    const bool full_store = s.ctr[C_OVERFLOW] != 0;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = __lane_id();
+    const uint32_t k = lane % G, base = lane - k, grp = tid / G;
+    const uint4* rows4 = reinterpret_cast<const uint4*>(s.rows);
+    for (uint32_t q = tid; q < NQ; q += kLanes) {
+        sh_v[q] = reinterpret_cast<const uint4*>(s.V)[q];
+        sh_s[q] = reinterpret_cast<const uint4*>(s.S)[q];
+        sh_p[q] = reinterpret_cast<const uint4*>(s.P0)[q];
+    }
+    WaveAlloc wa;
+    uint32_t count = 0;
+    // persistent: the block takes tiles from a cursor that persists across
+    // launches, while the deferral list and the table can take every
+    // candidate of the tiles that may still be in flight (one per block)
+    for (;;) {
+    if (tid == 0) {
+        unsigned long long tl = ~0ull;
+        const unsigned long long d = __hip_atomic_load(&s.ctr[C_DEF0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long r = __hip_atomic_load(&s.ctr[C_ROWS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (d + t.def_margin <= s.def0_cap && (full_store || r + t.row_margin <= t.row_budget))
+            tl = atomicAdd(&s.ctr[C_TILE], 1ull);
+        sh_tile = tl;
+    }
+    __syncthreads();
+    const uint64_t tile = sh_tile;
+    __syncthreads();
+    if (tile >= t.tile_end) break;
+    uint32_t si = 0;
+    while (si + 1 < t.n && t.first[si + 1] <= tile) ++si;
+    const Seg& g = t.seg[si];
+    const uint64_t lt = tile - t.first[si];
+
+    if (g.kind == SEG_ATOM) {
+        __syncthreads();
+        if (tid < g.nb) {
+            process(s, OP_ATOM, tid, 0, snap);
+            ++count;
+        }
+    } else if (g.kind == SEG_UNARY) {
+        const uint64_t v0 = lt * kGU;
+        for (uint32_t idx = tid; idx < kGU * NQ; idx += kLanes) {
+            const uint64_t vl = v0 + idx / NQ;
+            sh_b[idx] = load_if(vl < g.nb, &rows4[(g.b0 + vl) * NQ + idx % NQ]);
+        }
+        __syncthreads();
+        const uint4 V = load_if(k < NQ, &sh_v[k]);
+        const uint4 S = load_if(k < NQ, &sh_s[k]);
+        const uint4 P = load_if(k < NQ, &sh_p[k]);
+        for (uint32_t iv = grp; iv < kGU; iv += NG) {
+            const uint64_t vl = v0 + iv;
+            const bool valid = vl < g.nb;
+            const uint32_t vi = (uint32_t)(g.b0 + (valid ? vl : 0));
+            const uint4 a = load_if(valid && k < NQ, &sh_b[iv * NQ + k]);
+            const uint32_t vop = valid ? (s.meta[vi].x & 7u) : OP_ATOM;
+            // not not a, F F a, G G a are cheaper formulas' CMs: skipped
+            const bool dn = valid && (g.opmask & M_NOT) && vop != OP_NOT;
+            const bool dx = valid && (g.opmask & M_X);
+            const bool df = valid && (g.opmask & M_F) && vop != OP_F;
+            const bool dg = valid && (g.opmask & M_G) && vop != OP_G;
+            // not
+            const uint4 rn = make_uint4(~a.x & V.x, ~a.y & V.y, ~a.z & V.z, ~a.w & V.w);
+            // X: the bit entering this chunk is the top bit of the chunk below
+            uint32_t up = __shfl_up(a.w >> 31, 1, 64);
+            if (k == 0) up = 0;
+            const uint4 rx = make_uint4(((a.x << 1) | up) & V.x, ((a.y << 1) | (a.x >> 31)) & V.y,
+                                        ((a.z << 1) | (a.y >> 31)) & V.z, ((a.w << 1) | (a.z >> 31)) & V.w);
+            // F: a | (V & carries of a + V)
+            const uint4 sf = group_add<G>(a, V, base, k);
+            const uint4 rf = make_uint4(a.x | (V.x & (sf.x ^ a.x ^ V.x)), a.y | (V.y & (sf.y ^ a.y ^ V.y)),
+                                        a.z | (V.z & (sf.z ^ a.z ^ V.z)), a.w | (V.w & (sf.w ^ a.w ^ V.w)));
+            // G: V & ~F(V & ~a)
+            const uint4 x = make_uint4(V.x & ~a.x, V.y & ~a.y, V.z & ~a.z, V.w & ~a.w);
+            const uint4 sg = group_add<G>(x, V, base, k);
+            const uint4 rg = make_uint4(V.x & ~(x.x | (V.x & (sg.x ^ x.x ^ V.x))),
+                                        V.y & ~(x.y | (V.y & (sg.y ^ x.y ^ V.y))),
+                                        V.z & ~(x.z | (V.z & (sg.z ^ x.z ^ V.z))),
+                                        V.w & ~(x.w | (V.w & (sg.w ^ x.w ^ V.w))));
+            const bool in = k < NQ;
+            const uint64_t hn = hash_fin(group_xor<G>(in ? chunk_hash(k, rn) : 0));
+            const uint64_t hx = hash_fin(group_xor<G>(in ? chunk_hash(k, rx) : 0));
+            const uint64_t hf = hash_fin(group_xor<G>(in ? chunk_hash(k, rf) : 0));
+            const uint64_t hg = hash_fin(group_xor<G>(in ? chunk_hash(k, rg) : 0));
+            const bool ex = group_none<G>(in && diff4(rx, a) != 0, base);
+            const bool ef = group_none<G>(in && diff4(rf, a) != 0, base);
+            const bool eg = group_none<G>(in && diff4(rg, a) != 0, base);
+            const bool sn = group_none<G>(in && ((rn.x ^ P.x) & S.x | (rn.y ^ P.y) & S.y | (rn.z ^ P.z) & S.z | (rn.w ^ P.w) & S.w) != 0, base);
+            const bool sx = group_none<G>(in && ((rx.x ^ P.x) & S.x | (rx.y ^ P.y) & S.y | (rx.z ^ P.z) & S.z | (rx.w ^ P.w) & S.w) != 0, base);
+            const bool sf2 = group_none<G>(in && ((rf.x ^ P.x) & S.x | (rf.y ^ P.y) & S.y | (rf.z ^ P.z) & S.z | (rf.w ^ P.w) & S.w) != 0, base);
+            const bool sg2 = group_none<G>(in && ((rg.x ^ P.x) & S.x | (rg.y ^ P.y) & S.y | (rg.z ^ P.z) & S.z | (rg.w ^ P.w) & S.w) != 0, base);
+            // owner lane j takes candidate j: not, X, F, G
+            const uint32_t opj = k == 0 ? OP_NOT : k == 1 ? OP_X : k == 2 ? OP_F : OP_G;
+            const bool act = k == 0 ? dn : k == 1 ? (dx && !ex) : k == 2 ? (df && !ef) : k == 3 ? (dg && !eg) : false;
+            const uint64_t hj = (k == 0 ? hn : k == 1 ? hx : k == 2 ? hf : hg) & s.hmask;
+            const bool sepj = k == 0 ? sn : k == 1 ? sx : k == 2 ? sf2 : sg2;
+            group_insert<G>(s, wa, NQ, base, k, snap, full_store, act && k < 4, hj, opj, vi, 0, sepj,
+                            rn, rx, rf, rg);
+            if (k == 0) count += (uint32_t)dn + dx + df + dg;
+        }
+    } else {
+        uint64_t ta, tb;
+        if (g.tri) {  // square tiles, upper triangle ta <= tb, column by column
+            tb = (uint64_t)((sqrt(8.0 * (double)lt + 1.0) - 1.0) * 0.5);
+            while ((tb + 1) * (tb + 2) / 2 <= lt) ++tb;
+            while (tb > 0 && tb * (tb + 1) / 2 > lt) --tb;
+            ta = lt - tb * (tb + 1) / 2;
+        } else {
+            const uint64_t tiles_b = (g.nb + kGB - 1) / kGB;
+            ta = lt / tiles_b;
+            tb = lt % tiles_b;
+        }
+        for (uint32_t idx = tid; idx < (kGA + kGB) * NQ; idx += kLanes) {
+            if (idx < kGA * NQ) {
+                const uint64_t al = ta * kGA + idx / NQ;
+                sh_a[idx] = load_if(al < g.na, &rows4[(g.a0 + al) * NQ + idx % NQ]);
+            } else {
+                const uint32_t j = idx - kGA * NQ;
+                const uint64_t bl = tb * kGB + j / NQ;
+                sh_b[j] = load_if(bl < g.nb, &rows4[(g.b0 + bl) * NQ + j % NQ]);
+            }
+        }
+        __syncthreads();
+        const uint4 S = load_if(k < NQ, &sh_s[k]);
+        const uint4 P = load_if(k < NQ, &sh_p[k]);
+        const bool mA = (g.opmask & M_AND) != 0, mO = (g.opmask & M_OR) != 0;  // uniform
+        const bool mU = (g.opmask & M_UAB) != 0, mV = (g.opmask & M_UBA) != 0;
+        for (uint32_t it = grp; it < kGA * kGB; it += NG) {
+            const uint32_t ia = it / kGB, ib = it % kGB;
+            const uint64_t al = ta * kGA + ia, bl = tb * kGB + ib;
+            const bool valid = al < g.na && bl < g.nb && (!g.tri || al < bl);
+            const uint32_t ai = (uint32_t)(g.a0 + (valid ? al : 0));
+            const uint32_t bi = (uint32_t)(g.b0 + (valid ? bl : 0));
+            const bool in = valid && k < NQ;
+            const uint4 a = load_if(in, &sh_a[ia * NQ + k]);
+            const uint4 b = load_if(in, &sh_b[ib * NQ + k]);
+            const uint4 o = make_uint4(a.x | b.x, a.y | b.y, a.z | b.z, a.w | b.w);
+            const uint4 rA = make_uint4(a.x & b.x, a.y & b.y, a.z & b.z, a.w & b.w);
+            // a U b = b | (a & carries of b + (a|b)); b U a symmetric
+            const uint4 s1 = group_add<G>(b, o, base, k);
+            const uint4 rU = make_uint4(b.x | (a.x & (s1.x ^ b.x ^ o.x)), b.y | (a.y & (s1.y ^ b.y ^ o.y)),
+                                        b.z | (a.z & (s1.z ^ b.z ^ o.z)), b.w | (a.w & (s1.w ^ b.w ^ o.w)));
+            const uint4 s2 = group_add<G>(a, o, base, k);
+            const uint4 rV = make_uint4(a.x | (b.x & (s2.x ^ a.x ^ o.x)), a.y | (b.y & (s2.y ^ a.y ^ o.y)),
+                                        a.z | (b.z & (s2.z ^ a.z ^ o.z)), a.w | (b.w & (s2.w ^ a.w ^ o.w)));
+            const uint64_t hA = hash_fin(group_xor<G>(in ? chunk_hash(k, rA) : 0));
+            const uint64_t hO = hash_fin(group_xor<G>(in ? chunk_hash(k, o) : 0));
+            const uint64_t hU = hash_fin(group_xor<G>(in ? chunk_hash(k, rU) : 0));
+            const uint64_t hV = hash_fin(group_xor<G>(in ? chunk_hash(k, rV) : 0));
+            // a result equal to an operand is a stored, cheaper CM
+            const bool eA = group_none<G>(in && diff4(rA, a) != 0, base) || group_none<G>(in && diff4(rA, b) != 0, base);
+            const bool eO = group_none<G>(in && diff4(o, a) != 0, base) || group_none<G>(in && diff4(o, b) != 0, base);
+            const bool eU = group_none<G>(in && diff4(rU, a) != 0, base) || group_none<G>(in && diff4(rU, b) != 0, base);
+            const bool eV = group_none<G>(in && diff4(rV, a) != 0, base) || group_none<G>(in && diff4(rV, b) != 0, base);
+            const bool sA = group_none<G>(in && ((rA.x ^ P.x) & S.x | (rA.y ^ P.y) & S.y | (rA.z ^ P.z) & S.z | (rA.w ^ P.w) & S.w) != 0, base);
+            const bool sO = group_none<G>(in && ((o.x ^ P.x) & S.x | (o.y ^ P.y) & S.y | (o.z ^ P.z) & S.z | (o.w ^ P.w) & S.w) != 0, base);
+            const bool sU = group_none<G>(in && ((rU.x ^ P.x) & S.x | (rU.y ^ P.y) & S.y | (rU.z ^ P.z) & S.z | (rU.w ^ P.w) & S.w) != 0, base);
+            const bool sV = group_none<G>(in && ((rV.x ^ P.x) & S.x | (rV.y ^ P.y) & S.y | (rV.z ^ P.z) & S.z | (rV.w ^ P.w) & S.w) != 0, base);
+            // owner lane j takes candidate j: a&b, a|b, a U b, b U a
+            const uint32_t opj = k == 0 ? OP_AND : k == 1 ? OP_OR : OP_U;
+            const uint32_t Lj = k == 3 ? bi : ai, Rj = k == 3 ? ai : bi;
+            const bool act = valid && (k == 0 ? (mA && !eA) : k == 1 ? (mO && !eO) : k == 2 ? (mU && !eU) :
+                                       k == 3 ? (mV && !eV) : false);
+            const uint64_t hj = (k == 0 ? hA : k == 1 ? hO : k == 2 ? hU : hV) & s.hmask;
+            const bool sepj = k == 0 ? sA : k == 1 ? sO : k == 2 ? sU : sV;
+            group_insert<G>(s, wa, NQ, base, k, snap, full_store, act, hj, opj, Lj, Rj, sepj, rA, o, rU, rV);
+            if (k == 0 && valid) count += (uint32_t)mA + mO + mU + mV;
+        }
+    }
+    __syncthreads();  // the next tile reuses the LDS tiles
+    }
+    retire_rows(s, wa.rnext, wa.rend);
+    retire_records(s, wa.dnext, wa.dend);
+    unsigned long long cc = count;
+    for (int off = 32; off > 0; off >>= 1) cc += __shfl_down(cc, off);
+    if (__lane_id() == 0 && cc) atomicAdd(&s.ctr[C_CAND], cc);
+}
+
 // Verifies deferred candidates against the entries they met (now visible).
 // Candidates that turn out to be new go to list 1 for re-insertion.
 __global__ __launch_bounds__(kLanes) void k_verify_deferred(Store s) {
@@ -728,6 +1170,7 @@ __global__ __launch_bounds__(kLanes) void k_verify_deferred(Store s) {
          i += (uint64_t)gridDim.x * blockDim.x) {
         const uint4 rec = s.def0[i];
         const uint32_t op = rec.x & 15u;
+        if (op == kNoRecord) continue;
         uint64_t pos = ((uint64_t)(rec.x >> 4) << 32) | rec.w;
         const uint64_t h = cm_hash(s, op, rec.y, rec.z);
         const uint32_t tag = tag_of(h);
@@ -753,6 +1196,111 @@ __global__ __launch_bounds__(kLanes) void k_verify_deferred(Store s) {
                 if (cm_equal_row(s, op, rec.y, rec.z, cidx)) break;
             }
             pos = slot_next(s, pos);
+        }
+    }
+}
+
+// Group version of the deferred verification (rows of 2..64 chunks): one
+// group of G lanes per record, operands and the compared rows read as
+// coalesced chunks.  The operator varies per group, so every group runs the
+// same instructions with operator-selected operands (ballots stay uniform).
+template <int G>
+__global__ __launch_bounds__(kLanes) void k_verify_grp(Store s) {
+    const uint64_t n0 = s.ctr[C_DEF0];
+    const uint64_t n = n0 < s.def0_cap ? n0 : s.def0_cap;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(&s.ctr[C_DEFERRED], (unsigned long long)n);
+    const uint32_t NQ = s.Wp / 4;
+    const uint32_t lane = __lane_id(), k = lane % G, base = lane - k;
+    const uint64_t gid = ((uint64_t)blockIdx.x * kLanes + threadIdx.x) / G;
+    const uint64_t ngroups = (uint64_t)gridDim.x * kLanes / G;
+    const uint4* rows4 = reinterpret_cast<const uint4*>(s.rows);
+    const uint4* atoms4 = reinterpret_cast<const uint4*>(s.atoms);
+    const uint4 zero = make_uint4(0, 0, 0, 0);
+    const bool kin = k < NQ;
+    const uint4 V = load_if(kin, &reinterpret_cast<const uint4*>(s.V)[k]);
+    const uint4 S = load_if(kin, &reinterpret_cast<const uint4*>(s.S)[k]);
+    const uint4 P = load_if(kin, &reinterpret_cast<const uint4*>(s.P0)[k]);
+    const uint64_t rounds = (n + ngroups - 1) / ngroups;  // uniform over the grid
+    for (uint64_t rd = 0; rd < rounds; ++rd) {
+        const uint64_t i = gid + rd * ngroups;
+        const bool valid = i < n;
+        const uint4 rec0 = load_if(valid, &s.def0[i]);
+        const bool real = valid && (rec0.x & 15u) != kNoRecord;
+        const uint4 rec = real ? rec0 : make_uint4(OP_AND, 0, 0, 0);
+        const uint32_t op = rec.x & 15u, L = rec.y, R = rec.z;
+        uint64_t pos = ((uint64_t)(rec.x >> 4) << 32) | rec.w;
+        const bool in = real && kin;
+        const uint4 a = load_if(in, &(op == OP_ATOM ? atoms4 : rows4)[(uint64_t)L * NQ + k]);
+        const uint4 b = load_if(in && op >= OP_AND, &rows4[(uint64_t)R * NQ + k]);
+        const uint4 o = make_uint4(a.x | b.x, a.y | b.y, a.z | b.z, a.w | b.w);
+        const uint4 ng = make_uint4(V.x & ~a.x, V.y & ~a.y, V.z & ~a.z, V.w & ~a.w);
+        // operands of the one multi-chunk add the operator needs
+        const uint4 x = op == OP_F ? a : op == OP_G ? ng : op == OP_U ? b : zero;
+        const uint4 y = op == OP_F || op == OP_G ? V : op == OP_U ? o : zero;
+        const uint4 sm = group_add<G>(x, y, base, k);
+        const uint4 c = make_uint4(sm.x ^ x.x ^ y.x, sm.y ^ x.y ^ y.y, sm.z ^ x.z ^ y.z, sm.w ^ x.w ^ y.w);
+        uint32_t up = __shfl_up(a.w >> 31, 1, 64);
+        if (k == 0) up = 0;
+        uint4 r;
+        switch (op) {
+        case OP_ATOM: r = a; break;
+        case OP_NOT: r = make_uint4(~a.x & V.x, ~a.y & V.y, ~a.z & V.z, ~a.w & V.w); break;
+        case OP_X:
+            r = make_uint4(((a.x << 1) | up) & V.x, ((a.y << 1) | (a.x >> 31)) & V.y,
+                           ((a.z << 1) | (a.y >> 31)) & V.z, ((a.w << 1) | (a.z >> 31)) & V.w);
+            break;
+        case OP_F: r = make_uint4(a.x | (V.x & c.x), a.y | (V.y & c.y), a.z | (V.z & c.z), a.w | (V.w & c.w)); break;
+        case OP_G:
+            r = make_uint4(V.x & ~(ng.x | (V.x & c.x)), V.y & ~(ng.y | (V.y & c.y)),
+                           V.z & ~(ng.z | (V.z & c.z)), V.w & ~(ng.w | (V.w & c.w)));
+            break;
+        case OP_AND: r = make_uint4(a.x & b.x, a.y & b.y, a.z & b.z, a.w & b.w); break;
+        case OP_OR: r = o; break;
+        default: r = make_uint4(b.x | (a.x & c.x), b.y | (a.y & c.y), b.z | (a.z & c.z), b.w | (a.w & c.w)); break;
+        }
+        if (!in) r = zero;
+        const uint64_t h = hash_fin(group_xor<G>(in ? chunk_hash(k, r) : 0)) & s.hmask;
+        const uint32_t tag = tag_of(h);
+        const bool sep = group_none<G>(in && ((r.x ^ P.x) & S.x | (r.y ^ P.y) & S.y | (r.z ^ P.z) & S.z |
+                                               (r.w ^ P.w) & S.w) != 0, base);
+        // owner (k == 0) walks the table from the slot it met; the group verifies
+        uint32_t st = real && k == 0 ? S_PROBE : S_DONE;
+        uint64_t steps = 0;
+        while (__ballot(st == S_PROBE) != 0) {
+            bool need_v = false;
+            uint32_t vrow = 0;
+            if (st == S_PROBE) {
+                const uint64_t cur = slot_load(&s.table[pos]);
+                if (steps++ > s.tsize) {
+                    st = S_FULL;
+                } else if (cur == kEmpty) {
+                    st = S_WON;  // new after all: re-inserted later
+                } else if ((uint32_t)(cur >> 32) == tag) {
+                    if ((uint32_t)cur == kPending) st = S_FULL;  // only after a row overflow
+                    else {
+                        need_v = true;
+                        vrow = (uint32_t)cur;
+                    }
+                } else {
+                    pos = slot_next(s, pos);
+                }
+            }
+            const bool nv = __shfl((int)need_v, (int)base, 64) != 0;
+            const uint32_t vr = __shfl(vrow, (int)base, 64);
+            const uint4 mrow = load_if(nv && kin, &rows4[(uint64_t)vr * NQ + k]);
+            const bool eq = group_none<G>(nv && kin && diff4(mrow, r) != 0, base);
+            if (need_v) {
+                if (eq) st = S_DUP;
+                else pos = slot_next(s, pos);
+            }
+        }
+        if (st == S_WON) {
+            const unsigned long long d = atomicAdd(&s.ctr[C_DEF1], 1ull);
+            if (d < s.def1_cap) s.def1[d] = make_uint4(op, L, R, 0);
+            else atomicExch(&s.ctr[C_DEF_OVF], 1ull);
+        } else if (st == S_FULL) {
+            atomicExch(&s.ctr[C_OVERFLOW], 1ull);
+            if (sep) report_found(s, op, L, R);
         }
     }
 }
@@ -790,6 +1338,7 @@ __global__ __launch_bounds__(kLanes) void k_rehash(Store s, uint64_t n_rows) {
     const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_rows) return;
     const uint4 mt = s.meta[r];
+    if (mt.y == kDead) return;
     const uint64_t want = ((uint64_t)(mt.x >> 3) << 32) | (uint32_t)r;
     uint64_t pos = (uint64_t)__umulhi(mt.w, (uint32_t)s.tsize);
     for (uint64_t steps = 0; slot_cas(&s.table[pos], kEmpty, want) != kEmpty; ++steps) {
@@ -798,6 +1347,61 @@ __global__ __launch_bounds__(kLanes) void k_rehash(Store s, uint64_t n_rows) {
             return;
         }
         pos = slot_next(s, pos);
+    }
+}
+
+// Level compaction (after a level kept dead rows): the holes below the new
+// end of the level receive the live rows above it.  Scan: list up to `cap`
+// of each (unordered; both lists have the same true length).  Move: copy row
+// and record, repoint the row's table slot (probing from its home slot), and
+// retire the source, so that a further round continues where this one ended.
+__device__ __forceinline__ void list_append(unsigned long long* ctr, bool take, uint32_t v, uint32_t* list,
+                                            uint64_t cap) {
+    const uint64_t m = __ballot(take);
+    if (m == 0) return;
+    unsigned long long b = 0;
+    if (__lane_id() == 0) b = atomicAdd(ctr, (unsigned long long)__popcll(m));
+    b = __shfl(b, 0, 64);
+    const uint64_t i = b + __popcll(m & ((1ull << __lane_id()) - 1));
+    if (take && i < cap) list[i] = v;
+}
+
+__global__ __launch_bounds__(kLanes) void k_compact_scan(Store s, uint64_t lo, uint64_t new_end, uint64_t hi,
+                                                         uint32_t* holes, uint32_t* movers, uint64_t cap) {
+    const uint64_t waves = (uint64_t)gridDim.x * (kLanes / 64);
+    const uint64_t wid = ((uint64_t)blockIdx.x * kLanes + threadIdx.x) / 64;
+    for (uint64_t r0 = lo + wid * 64; r0 < hi; r0 += waves * 64) {
+        const uint64_t r = r0 + __lane_id();
+        const bool valid = r < hi;
+        const bool dead = valid && s.meta[r].y == kDead;
+        list_append(&s.ctr[C_NH], dead && r < new_end, (uint32_t)r, holes, cap);
+        list_append(&s.ctr[C_NM], valid && !dead && r >= new_end, (uint32_t)r, movers, cap);
+    }
+}
+
+__global__ __launch_bounds__(kLanes) void k_compact_move(Store s, const uint32_t* holes, const uint32_t* movers,
+                                                         uint64_t cap) {
+    const uint64_t nh = s.ctr[C_NH], nm = s.ctr[C_NM];
+    uint64_t n = nh < nm ? nh : nm;
+    n = n < cap ? n : cap;
+    const uint32_t NQ = s.Wp / 4;
+    uint4* rows4 = reinterpret_cast<uint4*>(s.rows);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t src = movers[i], dst = holes[i];
+        for (uint32_t q = 0; q < NQ; ++q) rows4[(uint64_t)dst * NQ + q] = rows4[(uint64_t)src * NQ + q];
+        const uint4 mt = s.meta[src];
+        s.meta[dst] = mt;
+        s.meta[src] = make_uint4(0, kDead, 0, 0);
+        const uint64_t tagw = (uint64_t)(mt.x >> 3) << 32;
+        uint64_t pos = slot_of(s, mt.w);
+        for (uint64_t steps = 0; steps <= s.tsize; ++steps) {
+            if (s.table[pos] == (tagw | src)) {
+                s.table[pos] = tagw | dst;
+                break;
+            }
+            pos = slot_next(s, pos);
+        }
     }
 }
 
@@ -939,20 +1543,84 @@ uint64_t lds_bytes(uint32_t Wp) {
     return 16ull * (kLanes * lds_stride(nq) + kTileA * nq + 3ull * nq);
 }
 
-hipError_t launch_generate(const Store& s, const SegTable& t, uint64_t lds_limit, hipStream_t st) {
+static uint64_t grp_lds_bytes(uint32_t Wp) {
+    const uint32_t nq = Wp / 4;
+    return 16ull * ((uint64_t)(kGA + kGU) * nq + 3ull * nq);
+}
+
+static uint32_t group_size(uint32_t nq) {
+    uint32_t g = 4;
+    while (g < nq) g <<= 1;
+    return g;
+}
+
+TileShape tile_shape(uint32_t Wp, uint64_t lds_limit, uint32_t pref) {
+    const uint32_t nq = Wp / 4;
+    const bool group_fits = nq >= 2 && nq <= 64 && grp_lds_bytes(Wp) <= lds_limit;
+    const bool lane_fits = lds_bytes(Wp) <= lds_limit;
+    const TileShape group{KERNEL_GROUP, kGA, kGB, kGU, 1}, lane{KERNEL_LANE, kTileA, kLanes, kLanes, 0};
+    if (pref == KERNEL_GROUP && group_fits) return group;
+    if (lane_fits) return lane;
+    if (group_fits) return group;
+    return TileShape{KERNEL_GENERIC, kTileA, kLanes, kLanes, 0};
+}
+
+template <class K>
+static hipError_t raise_lds(K kernel, uint64_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t generate_blocks(const Store& s, uint64_t n_tiles, uint64_t& blocks) {
+    blocks = n_tiles;
+    if (s.kernel != KERNEL_GROUP) return hipSuccess;
+    const uint64_t lds = grp_lds_bytes(s.Wp);
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    switch (group_size(s.Wp / 4)) {
+#define LTLF_OCC(G)                                                                              \
+    case G:                                                                                      \
+        e = raise_lds(k_generate_grp<G>, lds);                                                   \
+        if (e == hipSuccess)                                                                     \
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_generate_grp<G>, kLanes, lds); \
+        break;
+        LTLF_OCC(4) LTLF_OCC(8) LTLF_OCC(16) LTLF_OCC(32) LTLF_OCC(64)
+#undef LTLF_OCC
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    const uint64_t resident = (uint64_t)(per_cu > 0 ? per_cu : 1) * (uint64_t)(cus > 0 ? cus : 1);
+    blocks = n_tiles < resident ? n_tiles : resident;
+    return hipSuccess;
+}
+
+hipError_t launch_generate(const Store& s, const SegTable& t, uint64_t blocks, hipStream_t st) {
     const uint64_t n = t.tile_end - t.tile_begin;
     if (n == 0) return hipSuccess;
     const dim3 grid((uint32_t)n), block(kLanes);
-    const uint64_t lds = lds_bytes(s.Wp);
-    if (lds <= lds_limit) {
-        static uint64_t raised = 0;  // largest dynamic LDS size enabled so far
-        if (lds > 65536 && lds > raised) {
-            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_generate_lds<kBatch>),
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                     (int)lds);
-            if (e != hipSuccess) return e;
-            raised = lds;
+    hipError_t e = hipSuccess;
+    if (s.kernel == KERNEL_GROUP) {
+        // persistent blocks; the caller sized the grid and the margins
+        if (blocks == 0 || blocks > n) return hipErrorInvalidValue;
+        const uint64_t lds = grp_lds_bytes(s.Wp);
+        switch (group_size(s.Wp / 4)) {
+#define LTLF_GRP(G)                                                                             \
+    case G:                                                                                     \
+        e = raise_lds(k_generate_grp<G>, lds);                                                  \
+        if (e != hipSuccess) return e;                                                          \
+        hipLaunchKernelGGL(k_generate_grp<G>, dim3((uint32_t)blocks), block, (uint32_t)lds, st, s, t); \
+        break;
+            LTLF_GRP(4) LTLF_GRP(8) LTLF_GRP(16) LTLF_GRP(32) LTLF_GRP(64)
+#undef LTLF_GRP
+        default: return hipErrorInvalidValue;
         }
+    } else if (s.kernel == KERNEL_LANE) {
+        const uint64_t lds = lds_bytes(s.Wp);
+        e = raise_lds(k_generate_lds<kBatch>, lds);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_generate_lds<kBatch>, grid, block, (uint32_t)lds, st, s, t);
     } else {
         hipLaunchKernelGGL(k_generate, grid, block, 0, st, s, t);
@@ -961,7 +1629,20 @@ hipError_t launch_generate(const Store& s, const SegTable& t, uint64_t lds_limit
 }
 
 hipError_t launch_verify_deferred(const Store& s, hipStream_t st) {
-    hipLaunchKernelGGL(k_verify_deferred, dim3(2048), dim3(kLanes), 0, st, s);
+    // records are the same for every generation kernel; rows of 2..64
+    // chunks are verified by lane groups (coalesced row reads)
+    const uint32_t nq = s.Wp / 4;
+    if (nq >= 2 && nq <= 64) {
+        switch (group_size(s.Wp / 4)) {
+#define LTLF_VGRP(G) \
+    case G: hipLaunchKernelGGL(k_verify_grp<G>, dim3(2048), dim3(kLanes), 0, st, s); break;
+            LTLF_VGRP(4) LTLF_VGRP(8) LTLF_VGRP(16) LTLF_VGRP(32) LTLF_VGRP(64)
+#undef LTLF_VGRP
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        hipLaunchKernelGGL(k_verify_deferred, dim3(2048), dim3(kLanes), 0, st, s);
+    }
     return hipGetLastError();
 }
 
@@ -979,6 +1660,20 @@ hipError_t launch_between(unsigned long long* ctr, hipStream_t st) {
 hipError_t launch_set_counter(unsigned long long* ctr, uint32_t which, unsigned long long v,
                               hipStream_t st) {
     hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(64), 0, st, ctr, which, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const Store& s, uint64_t lo, uint64_t new_end, uint64_t hi, uint32_t* holes,
+                          uint32_t* movers, uint64_t cap, hipStream_t st) {
+    if (hi <= lo) return hipSuccess;
+    const uint64_t b = blocks_for(hi - lo, kLanes);
+    hipLaunchKernelGGL(k_compact_scan, dim3((uint32_t)(b < 16384 ? b : 16384)), dim3(kLanes), 0, st, s, lo,
+                       new_end, hi, holes, movers, cap);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint64_t m = blocks_for(cap < hi - lo ? cap : hi - lo, kLanes);
+    hipLaunchKernelGGL(k_compact_move, dim3((uint32_t)(m < 16384 ? m : 16384)), dim3(kLanes), 0, st, s, holes,
+                       movers, cap);
     return hipGetLastError();
 }
 

@@ -24,6 +24,8 @@ STATUS_NAMES = {0: "OK", 1: "NOT_FOUND", 2: "CAPACITY", -1: "EINVAL", -2: "ENOME
                 -3: "EDEVICE", -4: "EBUFSZ", -5: "ESTATE"}
 FLAG_EXHAUST = 0x1
 FLAG_PROFILE = 0x2
+FLAG_KERNEL_LANE = 0x4  # one candidate per lane (default where it fits)
+FLAG_KERNEL_GROUP = 0x8  # one candidate per lane group (rows of 2..64 chunks)
 FLAG_WEAK_HASH = 0x100  # test hook: 6-bit hashes, every probe meets an equal tag
 
 OP_NAMES = ("!", "X", "F", "G", "&", "|", "U")  # index = ltlf_op
@@ -58,7 +60,7 @@ class ltlf_result(ctypes.Structure):
                 ("row_bytes", ctypes.c_uint32), ("gen_launches", ctypes.c_uint32),
                 ("verify_launches", ctypes.c_uint32), ("pad", ctypes.c_uint32),
                 ("enum_ms", ctypes.c_double), ("gen_ms", ctypes.c_double),
-                ("verify_ms", ctypes.c_double)]
+                ("verify_ms", ctypes.c_double), ("dead_rows", ctypes.c_uint64)]
 
 
 _lib = None
@@ -208,6 +210,7 @@ class Result:
     verify_launches: int = 0
     gen_ms: float = 0.0
     verify_ms: float = 0.0
+    dead_rows: int = 0
 
     @property
     def status_name(self) -> str:
@@ -282,7 +285,7 @@ class Synthesizer:
                       unique_total=res.unique_total, enum_ms=res.enum_ms, deferred=res.deferred,
                       row_bytes=res.row_bytes, gen_launches=res.gen_launches,
                       verify_launches=res.verify_launches, gen_ms=res.gen_ms,
-                      verify_ms=res.verify_ms)
+                      verify_ms=res.verify_ms, dead_rows=res.dead_rows)
 
     def solve(self, problem, cost_bound: Optional[int] = None, op_cost=UNIT_ALL, atom_cost: int = 1,
               flags: int = 0) -> Result:

@@ -64,7 +64,7 @@ def test_struct_layouts_match_header():
     # ltlf_costs: 8 uint32; ltlf_spec: 2 uint32 + 3 pointers
     assert ctypes.sizeof(L.ltlf_costs) == 32
     assert ctypes.sizeof(L.ltlf_spec) == 8 + 3 * ctypes.sizeof(ctypes.c_void_p)
-    assert ctypes.sizeof(L.ltlf_result) == 4 * 4 + 8 * 8 + 4 * 4 + 3 * 8
+    assert ctypes.sizeof(L.ltlf_result) == 4 * 4 + 8 * 8 + 4 * 4 + 3 * 8 + 8
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -71,8 +71,13 @@ def test_medium_plain(synth, seed):
     compare(synth, p, p.cost_bound)
 
 
-def test_medium_exhaustive_to_8(synth):
-    compare(synth, workload.medium(1), 8, exhaust=True)
+KERNELS = pytest.mark.parametrize("kflag", [0, m.FLAG_KERNEL_LANE, m.FLAG_KERNEL_GROUP],
+                                  ids=["default", "lane", "group"])
+
+
+@KERNELS
+def test_medium_exhaustive_to_8(synth, kflag):
+    compare(synth, workload.medium(1), 8, exhaust=True, flags=kflag)
 
 
 @pytest.mark.parametrize("ops", [oracle.UNIT_ALL, oracle.UNIT_PAPER], ids=["all", "paper"])
@@ -102,11 +107,20 @@ def test_weak_hash_forces_collisions(synth, seed):
     compare(synth, workload.tiny(seed), 5, exhaust=True, flags=m.FLAG_WEAK_HASH)
 
 
-def test_row_limit_matches_oracle_capacity(synth):
-    p = workload.tiny(3)
+@KERNELS
+@pytest.mark.parametrize("seed", [2, 3])
+def test_weak_hash_wide_rows(synth, seed, kflag):
+    """The same stress on 40-word rows, for each generation kernel."""
+    compare(synth, workload.medium(seed), 5, exhaust=True, flags=m.FLAG_WEAK_HASH | kflag)
+
+
+@pytest.mark.parametrize("problem", ["tiny", "medium"])
+@pytest.mark.parametrize("kflag", [0, m.FLAG_KERNEL_GROUP], ids=["default", "group"])
+def test_row_limit_matches_oracle_capacity(synth, problem, kflag):
+    p = workload.tiny(3) if problem == "tiny" else workload.medium(3)
     full = oracle.solve(p, cost_bound=7, exhaust=True)
     cap = sum(full.level_counts[:5]) + 3
-    r, o = compare(synth, p, 7, exhaust=True, row_limit=cap)
+    r, o = compare(synth, p, 7, exhaust=True, row_limit=cap, flags=kflag)
     assert r.overflow_level == 5
 
 
@@ -152,10 +166,17 @@ def test_edge_long_traces_cross_words(synth):
     compare(synth, p, 5, exhaust=True)
 
 
-def test_edge_wide_rows(synth):
-    """A CM of several hundred words (many traces)."""
-    p = workload.make_problem(21, 4, 40, 40, 40, 64, 5, 5, q_range=(0.3, 0.7), name="wide")
-    compare(synth, p, 4, exhaust=True)
+@pytest.mark.parametrize("shape", [(8, 8, 2, 6), (16, 16, 3, 9), (20, 20, 8, 16), (30, 30, 16, 24),
+                                   (40, 40, 40, 64), (60, 60, 60, 64), (90, 90, 60, 64)],
+                         ids=["rows-1q", "rows-2q", "rows-5q", "rows-16q", "rows-33q", "rows-60q",
+                              "rows-90q"])
+@pytest.mark.parametrize("kflag", [0, m.FLAG_KERNEL_GROUP], ids=["default", "group"])
+def test_edge_row_widths(synth, shape, kflag):
+    """Row widths across the lane kernel's LDS limit, the group sizes (4..64
+    lanes per candidate) and past them (generic kernel)."""
+    npos, nneg, lo, hi = shape
+    p = workload.make_problem(21, 3, npos, nneg, lo, hi, 5, 5, q_range=(0.3, 0.7), name=f"wide{hi}")
+    compare(synth, p, 4, exhaust=True, flags=kflag)
 
 
 def test_repeat_runs_identical(synth):

@@ -79,7 +79,7 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--bound", type=int, default=13)
     ap.add_argument("--workspace-gb", type=float, default=0.0)
-    ap.add_argument("--cpu-bound", type=int, default=9)
+    ap.add_argument("--cpu-bound", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttf", action="store_true")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,

@@ -302,12 +302,14 @@ LevelPlan plan_level(const ltlf_ctx* c, const ltlf_costs* k, uint32_t lev, const
 }
 
 // Grows the table (clear + re-insert every stored row) so that it keeps at
-// least two slots per row after `extra` more rows.
-ltlf_status ensure_table(ltlf_ctx* c, uint64_t rows, uint64_t extra, hipStream_t s) {
+// least two slots per row after `extra` more rows.  A growth re-inserts every
+// stored row, so it goes at least to twice the size, and to room for `ahead`
+// more rows (the rows expected before the next growth would otherwise come).
+ltlf_status ensure_table(ltlf_ctx* c, uint64_t rows, uint64_t extra, hipStream_t s, uint64_t ahead = 0) {
     const uint64_t want = std::max<uint64_t>(2 * (rows + extra), kMinTableSlots);
     if (want <= c->st.tsize || c->st.tsize == c->table_max) return LTLF_OK;
-    // grow by at least 2x: a growth re-inserts every stored row
-    const uint64_t need = std::min<uint64_t>(std::max<uint64_t>(want, 2 * c->st.tsize), c->table_max);
+    const uint64_t need = std::min<uint64_t>(
+        std::max<uint64_t>(std::max<uint64_t>(want, 2 * (rows + ahead)), 2 * c->st.tsize), c->table_max);
     c->st.tsize = need;
     TRY_HIP(launch_fill_u64(c->st.table, need, ~0ull, s));
     TRY_HIP(launch_rehash(c->st, rows, s));
@@ -558,13 +560,18 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
         // whatever the estimate, growing the table between chunks if needed.
         // rows_ub is an upper bound on the rows stored so far (kept without
         // a sync).
+        // A growth is sized for the next level too (same growth ratio), so
+        // the largest stored rows are not re-inserted twice.
+        uint64_t ahead = 0;
         {
             uint64_t est = p.cand_ub;
             if (lev >= 3 && c->lcount[lev - 1] && c->lcount[lev - 2]) {
                 const double ratio = (double)c->lcount[lev - 1] / (double)c->lcount[lev - 2];
                 est = std::min<uint64_t>(est, (uint64_t)(1.5 * ratio * (double)c->lcount[lev - 1]) + 4096);
+                if (lev < bound) ahead = est + (uint64_t)(ratio * (double)est);
             }
-            TRY(ensure_table(c, rows, std::min<uint64_t>(est, c->st.cap - rows), s));
+            ahead = std::min<uint64_t>(std::max(ahead, est), c->st.cap - rows);
+            TRY(ensure_table(c, rows, std::min<uint64_t>(est, c->st.cap - rows), s, ahead));
         }
         uint64_t rows_ub = rows;
         TRY_HIP(launch_set_counter(c->d_ctr, C_DEAD, 0, s));
@@ -656,7 +663,8 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
                 if (2 * (rows_ub + chunk) > c->st.tsize) {
                     TRY(read_counters(c, s));
                     rows_ub = std::min<uint64_t>(c->h_ctr[C_ROWS], c->st.cap);
-                    TRY(ensure_table(c, rows_ub, std::min<uint64_t>(chunk, c->st.cap - rows_ub), s));
+                    TRY(ensure_table(c, rows_ub, std::min<uint64_t>(chunk, c->st.cap - rows_ub), s,
+                                     ahead > rows_ub - rows ? ahead - (rows_ub - rows) : 0));
                 }
                 rows_ub = std::min<uint64_t>(rows_ub + chunk, c->st.cap);
                 t.tile_begin = tile;

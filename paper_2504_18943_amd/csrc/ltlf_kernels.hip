@@ -162,6 +162,10 @@ __device__ __forceinline__ uint4 load_if(bool c, const uint4* p) {
     return v;
 }
 
+__device__ __forceinline__ uint32_t diff4(uint4 a, uint4 b) {
+    return (a.x ^ b.x) | (a.y ^ b.y) | (a.z ^ b.z) | (a.w ^ b.w);
+}
+
 __device__ __forceinline__ bool is_binary(uint32_t op) { return op >= OP_AND; }
 
 __device__ __forceinline__ const uint32_t* operand(const Store& s, uint32_t op, uint32_t idx) {
@@ -205,6 +209,7 @@ __device__ __forceinline__ void stream_cm(const Store& s, uint32_t op, uint32_t 
 // generic emitter reads both operands from the row store; the register
 // emitters below read them from VGPRs and LDS.
 struct GlobalEmit {
+    static constexpr bool kChunked = false;
     const Store& s;
     uint32_t op, L, R;
     template <class Fn>
@@ -223,16 +228,39 @@ __device__ __forceinline__ uint64_t emit_hash(const Store& s, const Emit& e) {
     return h.fin() & s.hmask;
 }
 
+constexpr uint32_t kVerifyGroup = 8;
+
+// Full comparison of candidate e with stored row `row`.  Emitters that can
+// produce chunk q directly (kChunked) compare in groups of kVerifyGroup chunks whose
+// loads are issued together, so a row costs ceil(chunks / kVerifyGroup) memory round
+// trips instead of one per chunk (the early exit of the streamed form makes
+// every load wait for the previous comparison).
 template <class Emit>
 __device__ __forceinline__ bool emit_equal_row(const Store& s, uint64_t row, const Emit& e) {
     const uint4* M = reinterpret_cast<const uint4*>(s.rows + row * s.Wp);
-    bool eq = true;
-    e([&](uint32_t w, uint4 r) {
-        const uint4 m = M[w >> 2];
-        eq = (r.x == m.x) && (r.y == m.y) && (r.z == m.z) && (r.w == m.w);
+    if constexpr (Emit::kChunked) {
+        const uint32_t nq = s.Wp / 4;
+        uint32_t st = 0;
+        for (uint32_t q0 = 0; q0 < nq; q0 += kVerifyGroup) {
+            uint4 m[kVerifyGroup];
+#pragma unroll
+            for (uint32_t i = 0; i < kVerifyGroup; ++i) m[i] = load_if(q0 + i < nq, &M[q0 + i]);
+            uint32_t d = 0;
+#pragma unroll
+            for (uint32_t i = 0; i < kVerifyGroup; ++i)
+                if (q0 + i < nq) d |= diff4(e.at(q0 + i, st), m[i]);
+            if (d != 0) return false;
+        }
+        return true;
+    } else {
+        bool eq = true;
+        e([&](uint32_t w, uint4 r) {
+            const uint4 m = M[w >> 2];
+            eq = (r.x == m.x) && (r.y == m.y) && (r.z == m.z) && (r.w == m.w);
+            return eq;
+        });
         return eq;
-    });
-    return eq;
+    }
 }
 
 // Spec check (paper: phi separates (P, N) iff it holds at position 0 of every
@@ -410,9 +438,12 @@ __device__ __forceinline__ uint4 binary_any(uint32_t op, uint4 a, uint4 b, uint3
 
 // Unary operator `op` over a row in LDS (v), with V in LDS.
 struct LdsUnaryEmit {
+    static constexpr bool kChunked = true;
     const uint4* v;
     const uint4* V;
     uint32_t nq, op;
+    // chunk q, given the carry state st of chunks < q (updated)
+    __device__ __forceinline__ uint4 at(uint32_t q, uint32_t& st) const { return unary_any(op, v[q], V[q], st); }
     template <class Fn>
     __device__ __forceinline__ void operator()(Fn&& fn) const {
         uint32_t st = 0;
@@ -424,9 +455,11 @@ struct LdsUnaryEmit {
 
 // Binary operator `op` with left operand l and right operand r (LDS rows).
 struct LdsPairEmit {
+    static constexpr bool kChunked = true;
     const uint4* l;
     const uint4* r;
     uint32_t nq, op;
+    __device__ __forceinline__ uint4 at(uint32_t q, uint32_t& st) const { return binary_any(op, l[q], r[q], st); }
     template <class Fn>
     __device__ __forceinline__ void operator()(Fn&& fn) const {
         uint32_t st = 0;
@@ -601,9 +634,6 @@ __device__ __forceinline__ void wave_take(const Store& s, WaveAlloc& wa, uint32_
     dbase = chunk_take(&s.ctr[C_DEF0], wa.dnext, wa.dend, total >> 16, excl >> 16);
 }
 
-__device__ __forceinline__ uint32_t diff4(uint4 a, uint4 b) {
-    return (a.x ^ b.x) | (a.y ^ b.y) | (a.z ^ b.z) | (a.w ^ b.w);
-}
 
 
 // Per-candidate state of one iteration.

@@ -101,9 +101,13 @@ typedef struct {
                                   choice wherever it fits) */
 #define LTLF_FLAG_KERNEL_GROUP 0x8u /* generation with one candidate per group
                                   of lanes (one 16-byte chunk per lane) where
-                                  rows have 2..64 chunks; else the default.
+                                  rows have 2..64 chunks;
+                                  else the default */
+#define LTLF_FLAG_KERNEL_WAVE 0x10u /* generation with one candidate per
+                                  wavefront, rows streamed 64 chunks at a time
+                                  (the default for rows over 64 chunks).
                                   Results never depend on the kernel: these
-                                  two flags exist for testing and tuning */
+                                  three flags exist for testing and tuning */
 #define LTLF_FLAG_DEBUG_WEAK_HASH 0x100u /* test hook: keep 6 bits of every hash,
                                   so all candidates share a few slots and one
                                   tag; exercises the verify/defer paths */

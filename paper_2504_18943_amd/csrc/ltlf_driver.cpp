@@ -516,8 +516,10 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
     c->lcount.assign(bound + 1, 0);
     c->st.cap = c->plan_cap;  // the row limit is applied to live rows per level
     c->st.hmask = (flags & LTLF_FLAG_DEBUG_WEAK_HASH) ? 0x3Full : ~0ull;
-    const uint32_t pref = (flags & LTLF_FLAG_KERNEL_GROUP) ? KERNEL_GROUP
-                          : (flags & LTLF_FLAG_KERNEL_LANE) ? KERNEL_LANE : KERNEL_AUTO;
+    const uint32_t pref = (flags & LTLF_FLAG_KERNEL_WAVE)    ? KERNEL_WAVE
+                          : (flags & LTLF_FLAG_KERNEL_GROUP) ? KERNEL_GROUP
+                          : (flags & LTLF_FLAG_KERNEL_LANE)  ? KERNEL_LANE
+                                                             : KERNEL_AUTO;
     const TileShape shape = tile_shape(c->Wp, c->lds_limit, pref);
     c->st.kernel = shape.kind;
 
@@ -575,7 +577,7 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
         }
         uint64_t rows_ub = rows;
         TRY_HIP(launch_set_counter(c->d_ctr, C_DEAD, 0, s));
-        const bool persistent = shape.kind == KERNEL_GROUP;
+        const bool persistent = shape.kind == KERNEL_GROUP || shape.kind == KERNEL_WAVE;
         // launch in groups of at most kMaxSegs segments
         for (size_t g0 = 0; g0 < p.segs.size(); g0 += kMaxSegs) {
             const size_t g1 = std::min(p.segs.size(), g0 + kMaxSegs);

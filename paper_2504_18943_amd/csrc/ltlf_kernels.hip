@@ -377,7 +377,8 @@ __device__ __forceinline__ void write_defer(const Store& s, unsigned long long d
     s.def0[d] = make_uint4(op | ((uint32_t)(pos >> 32) << 4), L, R, (uint32_t)pos);
 }
 
-// One candidate end to end, with per-wave counter aggregation (generic path).
+// One candidate end to end, operands from the row store (atoms and re-inserted
+// records), with per-wave counter aggregation.
 template <class Emit>
 __device__ void insert_emit(const Store& s, const Masks& m, uint32_t op, uint32_t L, uint32_t R,
                             uint64_t h, uint64_t pos, uint64_t cur0, uint64_t snap, const Emit& e) {
@@ -480,64 +481,6 @@ __device__ __forceinline__ void tri_tile(uint64_t lt, uint64_t& ta, uint64_t& tb
 }
 
 // ------------------------------------------------------------------ kernels --
-__global__ __launch_bounds__(kLanes) void k_generate(Store s, SegTable t) {
-    const uint64_t tile = t.tile_begin + blockIdx.x;
-    if (tile >= t.tile_end) return;
-    const uint64_t snap = s.ctr[C_SNAP];
-    uint32_t si = 0;
-    while (si + 1 < t.n && t.first[si + 1] <= tile) ++si;
-    const Seg& g = t.seg[si];
-    const uint64_t lt = tile - t.first[si];
-    const uint32_t tid = threadIdx.x;
-    uint32_t count = 0;
-
-    if (g.kind == SEG_ATOM) {
-        if (tid < g.nb) {
-            process(s, OP_ATOM, tid, 0, snap);
-            ++count;
-        }
-    } else if (g.kind == SEG_UNARY) {
-        const uint64_t vl = lt * kLanes + tid;
-        if (vl < g.nb) {
-            const uint32_t v = (uint32_t)(g.b0 + vl);
-            const uint32_t vop = s.meta[v].x & 7u;
-            // not not a = a, F F a = F a, G G a = G a: those candidates are
-            // cheaper formulas' CMs and are skipped without changing any set.
-            if ((g.opmask & M_NOT) && vop != OP_NOT) { process(s, OP_NOT, v, 0, snap); ++count; }
-            if (g.opmask & M_X) { process(s, OP_X, v, 0, snap); ++count; }
-            if ((g.opmask & M_F) && vop != OP_F) { process(s, OP_F, v, 0, snap); ++count; }
-            if ((g.opmask & M_G) && vop != OP_G) { process(s, OP_G, v, 0, snap); ++count; }
-        }
-    } else {
-        uint64_t ta, tb;
-        if (g.tri) {
-            tri_tile(lt, ta, tb);
-        } else {
-            const uint64_t tiles_b = (g.nb + kLanes - 1) / kLanes;
-            ta = lt / tiles_b;
-            tb = lt % tiles_b;
-        }
-        const uint64_t bl = tb * kLanes + tid;
-        if (bl < g.nb) {
-            const uint32_t b = (uint32_t)(g.b0 + bl);
-            for (uint32_t i = 0; i < kTileA; ++i) {
-                const uint64_t al = ta * kTileA + i;
-                if (al >= g.na) break;
-                if (g.tri && al >= bl) break;  // pairs a < b only; a grows with i
-                const uint32_t a = (uint32_t)(g.a0 + al);
-                if (g.opmask & M_AND) { process(s, OP_AND, a, b, snap); ++count; }
-                if (g.opmask & M_OR) { process(s, OP_OR, a, b, snap); ++count; }
-                if (g.opmask & M_UAB) { process(s, OP_U, a, b, snap); ++count; }
-                if (g.opmask & M_UBA) { process(s, OP_U, b, a, snap); ++count; }
-            }
-        }
-    }
-    // one atomic per wave for the candidate statistics
-    unsigned long long c = count;
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
-    if (__lane_id() == 0 && c) atomicAdd(&s.ctr[C_CAND], c);
-}
-
 // Wave-wide allocation of rows and deferral records: every active lane
 // brings how many rows (nrow) and records (ndef) it needs (each <= 4); one
 // atomic per counter and wave hands out consecutive indices.  No barrier, so
@@ -596,7 +539,7 @@ __device__ __forceinline__ void retire_records(const Store& s, unsigned long lon
 // (each lane takes at most one).  Returns the lane's index.
 __device__ __forceinline__ unsigned long long chunk_take(unsigned long long* ctr, unsigned long long& next,
                                                          unsigned long long& end, uint32_t total,
-                                                         uint32_t excl) {
+                                                         uint32_t excl, uint32_t chunk) {
     if (total == 0) return 0;
     const unsigned long long rem = end - next;
     if (total <= rem) {
@@ -605,7 +548,7 @@ __device__ __forceinline__ unsigned long long chunk_take(unsigned long long* ctr
         return mine;
     }
     const uint32_t need = total - (uint32_t)rem;
-    const uint32_t ch = need > kAllocChunk ? need : kAllocChunk;
+    const uint32_t ch = need > chunk ? need : chunk;
     unsigned long long b = 0;
     if (__lane_id() == 0) b = atomicAdd(ctr, (unsigned long long)ch);
     b = __shfl(b, 0, 64);
@@ -615,11 +558,17 @@ __device__ __forceinline__ unsigned long long chunk_take(unsigned long long* ctr
     return mine;
 }
 
+// Wave-wide: adds every lane's n to counter `which` with one atomic.
+__device__ __forceinline__ void wave_count(const Store& s, uint32_t which, uint32_t n) {
+    for (int off = 32; off > 0; off >>= 1) n += __shfl_down(n, off, 64);
+    if (__lane_id() == 0 && n) atomicAdd(&s.ctr[which], (unsigned long long)n);
+}
+
 // Wave-wide (every lane calls it): lane needs nrow rows and ndef records
 // (each 0 or 1); returns its indices.
 __device__ __forceinline__ void wave_take(const Store& s, WaveAlloc& wa, uint32_t nrow,
                                           uint32_t ndef, unsigned long long& rbase,
-                                          unsigned long long& dbase) {
+                                          unsigned long long& dbase, uint32_t chunk = kAllocChunk) {
     const uint32_t lane = __lane_id();
     const uint32_t mine = nrow | (ndef << 16);
     uint32_t incl = mine;
@@ -630,8 +579,8 @@ __device__ __forceinline__ void wave_take(const Store& s, WaveAlloc& wa, uint32_
     }
     const uint32_t total = __shfl(incl, 63, 64);
     const uint32_t excl = incl - mine;
-    rbase = chunk_take(&s.ctr[C_ROWS], wa.rnext, wa.rend, total & 0xFFFFu, excl & 0xFFFFu);
-    dbase = chunk_take(&s.ctr[C_DEF0], wa.dnext, wa.dend, total >> 16, excl >> 16);
+    rbase = chunk_take(&s.ctr[C_ROWS], wa.rnext, wa.rend, total & 0xFFFFu, excl & 0xFFFFu, chunk);
+    dbase = chunk_take(&s.ctr[C_DEF0], wa.dnext, wa.dend, total >> 16, excl >> 16, chunk);
 }
 
 
@@ -1190,17 +1139,454 @@ __global__ __launch_bounds__(kLanes) void k_generate_grp(Store s, SegTable t) {
     if (__lane_id() == 0 && cc) atomicAdd(&s.ctr[C_CAND], cc);
 }
 
+// ---------------------------------------------------- one wave per candidate --
+// Rows of any width: a wavefront takes one work item (a pair and its four
+// candidates, or an operand and its four unary results) and streams the rows
+// in steps of 64 chunks (lane k holds chunk 64*step + k), with every load and
+// store a coalesced 1 KB transfer.  Operands are read from global memory (a
+// tile's operands stay L2-resident); candidates are recomputed in each pass
+// (hash and tests, verification, write) instead of being held.  Carries of
+// the multi-word adds cross lanes by ballot carry-lookahead and steps through
+// the top lane.
+
+constexpr uint32_t kWA = 8;   // left operands per pair tile
+constexpr uint32_t kWB = 8;   // right operands per pair tile (square triangles)
+constexpr uint32_t kWU = 16;  // operands per unary tile
+constexpr uint32_t kWaveChunk = 8;  // rows / records a wave takes per atomic
+
+// X + Y over a whole row, one step of 64 chunks: `carry` (wave-uniform) is
+// the carry into lane 0 on entry and the carry out of lane 63 on return.
+__device__ __forceinline__ uint4 wave_add(uint4 x, uint4 y, uint32_t& carry) {
+    uint32_t co = 0;
+    const uint4 s0 = add128(x, y, 0, co);
+    const bool gen = co != 0;
+    const bool prop = !gen && (s0.x & s0.y & s0.z & s0.w) == 0xFFFFFFFFu;
+    const uint64_t g = __ballot(gen), p = __ballot(prop);
+    const uint64_t a = g | p;
+    // carries into the lanes: (a + g + carry) ^ a ^ g; out of lane 63: its overflow
+    const uint64_t t = a + g;
+    const uint64_t sum = t + carry;
+    const uint32_t out = (t < a || sum < t) ? 1u : 0u;
+    const uint32_t cin = (uint32_t)(((sum ^ a ^ g) >> __lane_id()) & 1u);
+    carry = out;
+    uint32_t dummy;
+    return add128(x, y, cin, dummy);
+}
+
+// Top bit of the lower chunk for X: lane k takes lane k-1's, lane 0 the
+// carried bit of the previous step; `carry` becomes lane 63's top bit.
+__device__ __forceinline__ uint32_t wave_shift_in(uint4 v, uint32_t& carry) {
+    const uint32_t top = v.w >> 31;
+    uint32_t up = __shfl_up(top, 1, 64);
+    if (__lane_id() == 0) up = carry;
+    carry = __shfl(top, 63, 64);
+    return up;
+}
+
+__device__ __forceinline__ uint4 x_chunk(uint4 a, uint32_t up, uint4 V) {
+    return make_uint4(((a.x << 1) | up) & V.x, ((a.y << 1) | (a.x >> 31)) & V.y,
+                      ((a.z << 1) | (a.y >> 31)) & V.z, ((a.w << 1) | (a.z >> 31)) & V.w);
+}
+
+__device__ __forceinline__ uint32_t check_chunk(uint4 r, uint4 P, uint4 S) {
+    return ((r.x ^ P.x) & S.x) | ((r.y ^ P.y) & S.y) | ((r.z ^ P.z) & S.z) | ((r.w ^ P.w) & S.w);
+}
+
+// Streams the four results of a work item over the row.  Pair (unary ==
+// false): a & b, a | b, a U b, b U a of rows A, B.  Unary: not, X, F, G of
+// row A.  body(q, in, a, b, r0, r1, r2, r3) runs once per step (a, b: the
+// operands' chunks; in: chunk q exists).
+template <class Body>
+__device__ __forceinline__ void wave_pass(const Store& s, bool unary, const uint4* A, const uint4* B,
+                                          uint32_t nq, Body&& body) {
+    const uint4* V4 = reinterpret_cast<const uint4*>(s.V);
+    uint32_t c0 = 0, c1 = 0, c2 = 0;
+    const uint32_t steps = (nq + 63) / 64;
+    for (uint32_t st = 0; st < steps; ++st) {
+        const uint32_t q = st * 64 + __lane_id();
+        const bool in = q < nq;
+        const uint4 a = load_if(in, &A[q]);
+        if (unary) {
+            const uint4 V = load_if(in, &V4[q]);
+            const uint4 rn = make_uint4(~a.x & V.x, ~a.y & V.y, ~a.z & V.z, ~a.w & V.w);
+            const uint4 rx = x_chunk(a, wave_shift_in(a, c0), V);
+            const uint4 sf = wave_add(a, V, c1);
+            const uint4 rf = make_uint4(a.x | (V.x & (sf.x ^ a.x ^ V.x)), a.y | (V.y & (sf.y ^ a.y ^ V.y)),
+                                        a.z | (V.z & (sf.z ^ a.z ^ V.z)), a.w | (V.w & (sf.w ^ a.w ^ V.w)));
+            const uint4 x = make_uint4(V.x & ~a.x, V.y & ~a.y, V.z & ~a.z, V.w & ~a.w);
+            const uint4 sg = wave_add(x, V, c2);
+            const uint4 rg = make_uint4(V.x & ~(x.x | (V.x & (sg.x ^ x.x ^ V.x))),
+                                        V.y & ~(x.y | (V.y & (sg.y ^ x.y ^ V.y))),
+                                        V.z & ~(x.z | (V.z & (sg.z ^ x.z ^ V.z))),
+                                        V.w & ~(x.w | (V.w & (sg.w ^ x.w ^ V.w))));
+            body(q, in, a, a, rn, rx, rf, rg);
+        } else {
+            const uint4 b = load_if(in, &B[q]);
+            const uint4 o = make_uint4(a.x | b.x, a.y | b.y, a.z | b.z, a.w | b.w);
+            const uint4 rA = make_uint4(a.x & b.x, a.y & b.y, a.z & b.z, a.w & b.w);
+            const uint4 s1 = wave_add(b, o, c1);
+            const uint4 rU = make_uint4(b.x | (a.x & (s1.x ^ b.x ^ o.x)), b.y | (a.y & (s1.y ^ b.y ^ o.y)),
+                                        b.z | (a.z & (s1.z ^ b.z ^ o.z)), b.w | (a.w & (s1.w ^ b.w ^ o.w)));
+            const uint4 s2 = wave_add(a, o, c2);
+            const uint4 rV = make_uint4(a.x | (b.x & (s2.x ^ a.x ^ o.x)), a.y | (b.y & (s2.y ^ a.y ^ o.y)),
+                                        a.z | (b.z & (s2.z ^ a.z ^ o.z)), a.w | (b.w & (s2.w ^ a.w ^ o.w)));
+            body(q, in, a, b, rA, o, rU, rV);
+        }
+    }
+}
+
+__device__ __forceinline__ uint64_t lane_pick4(uint32_t j, uint64_t v0, uint64_t v1, uint64_t v2, uint64_t v3) {
+    return j == 0 ? v0 : j == 1 ? v1 : j == 2 ? v2 : v3;
+}
+
+// Hash, operand-equality tests, spec check and table work of one work item
+// (every lane of the wave calls it).  act[j]: candidate j is enabled; op[j],
+// L[j], R[j]: its derivation.  Lane j (< 4) owns candidate j.
+__device__ __forceinline__ void wave_item(const Store& s, WaveAlloc& wa, bool unary, const uint4* A,
+                                          const uint4* B, uint32_t nq, uint64_t snap, bool full_store,
+                                          const bool (&en)[4], const uint32_t (&op)[4], const uint32_t (&L)[4],
+                                          const uint32_t (&R)[4]) {
+    const uint4* P4 = reinterpret_cast<const uint4*>(s.P0);
+    const uint4* S4 = reinterpret_cast<const uint4*>(s.S);
+    uint4* rows4 = reinterpret_cast<uint4*>(s.rows);
+    const uint32_t lane = __lane_id();
+    uint64_t h[4] = {0, 0, 0, 0};
+    uint32_t da[4] = {0, 0, 0, 0}, db[4] = {0, 0, 0, 0}, ck[4] = {0, 0, 0, 0};
+    wave_pass(s, unary, A, B, nq, [&](uint32_t q, bool in, uint4 a, uint4 b, uint4 r0, uint4 r1, uint4 r2, uint4 r3) {
+        if (!in) return;
+        const uint4 P = P4[q], S = S4[q];
+        const uint4 r[4] = {r0, r1, r2, r3};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            h[j] ^= chunk_hash(q, r[j]);
+            da[j] |= diff4(r[j], a);
+            db[j] |= diff4(r[j], b);
+            ck[j] |= check_chunk(r[j], P, S);
+        }
+    });
+    bool act[4], sep[4];
+    uint64_t hj[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        hj[j] = hash_fin(group_xor<64>(h[j])) & s.hmask;
+        // a result equal to an operand is a stored, cheaper CM
+        const bool eq = __ballot(da[j] != 0) == 0 || __ballot(db[j] != 0) == 0;
+        act[j] = en[j] && !eq;
+        sep[j] = __ballot(ck[j] != 0) == 0;
+    }
+    // owner lanes 0..3 run the probe; tag matches are verified by the wave
+    const bool mine = lane < 4 && (lane == 0 ? act[0] : lane == 1 ? act[1] : lane == 2 ? act[2] : act[3]);
+    const uint64_t hh = lane_pick4(lane & 3u, hj[0], hj[1], hj[2], hj[3]);
+    const uint32_t tag = tag_of(hh);
+    uint32_t st = mine ? S_PROBE : S_DONE;
+    uint64_t pos = 0, cur = 0, steps = 0;
+    if (mine) {
+        pos = slot_of(s, hh);
+        cur = slot_load(&s.table[pos]);
+    }
+    while (__ballot(st == S_PROBE) != 0) {
+        bool need_v = false;
+        uint32_t vrow = 0;
+        if (st == S_PROBE) {
+            if (steps++ >= s.tsize) st = S_FULL;
+            if (st == S_PROBE && cur == kEmpty) {
+                if (full_store) {
+                    st = S_FULL;
+                } else {
+                    const uint64_t old = slot_cas(&s.table[pos], kEmpty, ((uint64_t)tag << 32) | kPending);
+                    if (old == kEmpty) st = S_WON;
+                    else cur = old;
+                }
+            }
+            if (st == S_PROBE) {
+                const uint32_t cidx = (uint32_t)cur;
+                if ((uint32_t)(cur >> 32) == tag) {
+                    if (cidx == kPending || cidx >= snap) st = S_DEFER;
+                    else {
+                        need_v = true;
+                        vrow = cidx;
+                    }
+                } else {
+                    pos = slot_next(s, pos);
+                    cur = slot_load(&s.table[pos]);
+                }
+            }
+        }
+        const uint64_t nvm = __ballot(need_v) & 0xFull;
+        if (nvm) {
+            uint32_t vr[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) vr[j] = __shfl(vrow, j, 64);
+            uint32_t d[4] = {0, 0, 0, 0};
+            wave_pass(s, unary, A, B, nq,
+                      [&](uint32_t q, bool in, uint4, uint4, uint4 r0, uint4 r1, uint4 r2, uint4 r3) {
+                          const uint4 r[4] = {r0, r1, r2, r3};
+#pragma unroll
+                          for (int j = 0; j < 4; ++j) {
+                              const bool v = ((nvm >> j) & 1u) && in;
+                              d[j] |= diff4(load_if(v, &rows4[(uint64_t)vr[j] * nq + q]), v ? r[j] : make_uint4(0, 0, 0, 0));
+                          }
+                      });
+            bool eq_mine = false;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool eq = __ballot(d[j] != 0) == 0;
+                if (lane == (uint32_t)j) eq_mine = eq;
+            }
+            if (need_v) {
+                if (eq_mine) st = S_DUP;
+                else {
+                    pos = slot_next(s, pos);
+                    cur = slot_load(&s.table[pos]);
+                }
+            }
+        }
+    }
+    unsigned long long rb, dbase;
+    // a wave stores at most four rows per work item: small chunks keep the
+    // unused tails short
+    wave_take(s, wa, st == S_WON ? 1u : 0u, st == S_DEFER ? 1u : 0u, rb, dbase, kWaveChunk);
+    const uint64_t wonm = __ballot(st == S_WON) & 0xFull;
+    const uint32_t myrow = st == S_WON && rb < s.cap ? (uint32_t)rb : 0xFFFFFFFFu;
+    if (wonm) {
+        uint32_t wr[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) wr[j] = __shfl(myrow, j, 64);
+        wave_pass(s, unary, A, B, nq, [&](uint32_t q, bool in, uint4, uint4, uint4 r0, uint4 r1, uint4 r2, uint4 r3) {
+            const uint4 r[4] = {r0, r1, r2, r3};
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (((wonm >> j) & 1u) && in && wr[j] < s.cap) rows4[(uint64_t)wr[j] * nq + q] = r[j];
+        });
+    }
+    if (lane < 4) {
+        const uint32_t j = lane;
+        const uint32_t opj = op[0] * (j == 0) + op[1] * (j == 1) + op[2] * (j == 2) + op[3] * (j == 3);
+        const uint32_t Lj = L[0] * (j == 0) + L[1] * (j == 1) + L[2] * (j == 2) + L[3] * (j == 3);
+        const uint32_t Rj = R[0] * (j == 0) + R[1] * (j == 1) + R[2] * (j == 2) + R[3] * (j == 3);
+        const bool sepj = j == 0 ? sep[0] : j == 1 ? sep[1] : j == 2 ? sep[2] : sep[3];
+        if (st == S_WON) {
+            if (rb >= s.cap) {  // the slot stays reserved; the level will not be stored
+                atomicExch(&s.ctr[C_OVERFLOW], 1ull);
+            } else {
+                s.meta[rb] = make_uint4(opj | (tag << 3), Lj, Rj, (uint32_t)hh);
+                slot_store(&s.table[pos], ((uint64_t)tag << 32) | (uint32_t)rb);
+            }
+            if (sepj) report_found(s, opj, Lj, Rj);
+        } else if (st == S_DEFER) {
+            write_defer(s, dbase, opj, Lj, Rj, pos);
+        } else if (st == S_FULL) {
+            atomicExch(&s.ctr[C_OVERFLOW], 1ull);
+            if (sepj) report_found(s, opj, Lj, Rj);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kLanes) void k_generate_wave(Store s, SegTable t) {
+    __shared__ unsigned long long sh_tile;
+    const uint32_t NQ = s.Wp / 4;
+    const uint64_t snap = s.ctr[C_SNAP];
+    const bool full_store = s.ctr[C_OVERFLOW] != 0;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t wave = tid / 64;
+    const uint4* rows4 = reinterpret_cast<const uint4*>(s.rows);
+    WaveAlloc wa;
+    uint32_t count = 0;
+    // persistent: tiles from the cursor while the lists can take the tiles in flight
+    for (;;) {
+        if (tid == 0) {
+            unsigned long long tl = ~0ull;
+            const unsigned long long d = __hip_atomic_load(&s.ctr[C_DEF0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long r = __hip_atomic_load(&s.ctr[C_ROWS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (d + t.def_margin <= s.def0_cap && (full_store || r + t.row_margin <= t.row_budget))
+                tl = atomicAdd(&s.ctr[C_TILE], 1ull);
+            sh_tile = tl;
+        }
+        __syncthreads();
+        const uint64_t tile = sh_tile;
+        __syncthreads();
+        if (tile >= t.tile_end) break;
+        uint32_t si = 0;
+        while (si + 1 < t.n && t.first[si + 1] <= tile) ++si;
+        const Seg& g = t.seg[si];
+        const uint64_t lt = tile - t.first[si];
+        if (g.kind == SEG_ATOM) {
+            if (tid < g.nb) {
+                process(s, OP_ATOM, tid, 0, snap);
+                ++count;
+            }
+        } else if (g.kind == SEG_UNARY) {
+            for (uint32_t iv = wave; iv < kWU; iv += kLanes / 64) {
+                const uint64_t vl = lt * kWU + iv;
+                if (vl >= g.nb) break;  // uniform over the wave
+                const uint32_t vi = (uint32_t)(g.b0 + vl);
+                const uint32_t vop = s.meta[vi].x & 7u;
+                // not not a, F F a, G G a are cheaper formulas' CMs: skipped
+                const bool en[4] = {(g.opmask & M_NOT) && vop != OP_NOT, (g.opmask & M_X) != 0,
+                                    (g.opmask & M_F) && vop != OP_F, (g.opmask & M_G) && vop != OP_G};
+                const uint32_t op[4] = {OP_NOT, OP_X, OP_F, OP_G};
+                const uint32_t L[4] = {vi, vi, vi, vi}, R[4] = {0, 0, 0, 0};
+                wave_item(s, wa, true, rows4 + (uint64_t)vi * NQ, nullptr, NQ, snap, full_store, en, op, L, R);
+                if (tid % 64 == 0) count += (uint32_t)en[0] + en[1] + en[2] + en[3];
+            }
+        } else {
+            uint64_t ta, tb;
+            if (g.tri) {  // square tiles, upper triangle ta <= tb, column by column
+                tb = (uint64_t)((sqrt(8.0 * (double)lt + 1.0) - 1.0) * 0.5);
+                while ((tb + 1) * (tb + 2) / 2 <= lt) ++tb;
+                while (tb > 0 && tb * (tb + 1) / 2 > lt) --tb;
+                ta = lt - tb * (tb + 1) / 2;
+            } else {
+                const uint64_t tiles_b = (g.nb + kWB - 1) / kWB;
+                ta = lt / tiles_b;
+                tb = lt % tiles_b;
+            }
+            const bool mA = (g.opmask & M_AND) != 0, mO = (g.opmask & M_OR) != 0;
+            const bool mU = (g.opmask & M_UAB) != 0, mV = (g.opmask & M_UBA) != 0;
+            for (uint32_t it = wave; it < kWA * kWB; it += kLanes / 64) {
+                const uint64_t al = ta * kWA + it / kWB, bl = tb * kWB + it % kWB;
+                if (al >= g.na || bl >= g.nb || (g.tri && al >= bl)) continue;  // uniform over the wave
+                const uint32_t ai = (uint32_t)(g.a0 + al), bi = (uint32_t)(g.b0 + bl);
+                const bool en[4] = {mA, mO, mU, mV};
+                const uint32_t op[4] = {OP_AND, OP_OR, OP_U, OP_U};
+                const uint32_t L[4] = {ai, ai, ai, bi}, R[4] = {bi, bi, bi, ai};
+                wave_item(s, wa, false, rows4 + (uint64_t)ai * NQ, rows4 + (uint64_t)bi * NQ, NQ, snap,
+                          full_store, en, op, L, R);
+                if (tid % 64 == 0) count += (uint32_t)mA + mO + mU + mV;
+            }
+        }
+        __syncthreads();
+    }
+    retire_rows(s, wa.rnext, wa.rend);
+    retire_records(s, wa.dnext, wa.dend);
+    unsigned long long cc = count;
+    for (int off = 32; off > 0; off >>= 1) cc += __shfl_down(cc, off);
+    if (__lane_id() == 0 && cc) atomicAdd(&s.ctr[C_CAND], cc);
+}
+
+// Deferred records of wide rows: one wave per record, recomputing the
+// candidate step by step (any operator) against the rows it meets.
+__global__ __launch_bounds__(kLanes) void k_verify_wave(Store s) {
+    const uint64_t n0 = s.ctr[C_DEF0];
+    const uint64_t n = n0 < s.def0_cap ? n0 : s.def0_cap;
+    const uint32_t nq = s.Wp / 4, lane = __lane_id();
+    const uint64_t waves = (uint64_t)gridDim.x * (kLanes / 64);
+    uint32_t nrec = 0;  // real records verified (statistics)
+    const uint4* rows4 = reinterpret_cast<const uint4*>(s.rows);
+    const uint4* atoms4 = reinterpret_cast<const uint4*>(s.atoms);
+    const uint4* V4 = reinterpret_cast<const uint4*>(s.V);
+    const uint4* P4 = reinterpret_cast<const uint4*>(s.P0);
+    const uint4* S4 = reinterpret_cast<const uint4*>(s.S);
+    for (uint64_t i = ((uint64_t)blockIdx.x * kLanes + threadIdx.x) / 64; i < n; i += waves) {
+        const uint4 rec = s.def0[i];
+        const uint32_t op = rec.x & 15u, L = rec.y, R = rec.z;
+        if (op == kNoRecord) continue;  // uniform over the wave
+        nrec += lane == 0;
+        uint64_t pos = ((uint64_t)(rec.x >> 4) << 32) | rec.w;
+        const uint4* A = (op == OP_ATOM ? atoms4 : rows4) + (uint64_t)L * nq;
+        const uint4* B = rows4 + (uint64_t)R * nq;
+        // the candidate, step by step: `body(q, in, r)`
+        auto pass = [&](auto&& body) {
+            uint32_t c0 = 0, c1 = 0;
+            const uint32_t steps = (nq + 63) / 64;
+            for (uint32_t stp = 0; stp < steps; ++stp) {
+                const uint32_t q = stp * 64 + lane;
+                const bool in = q < nq;
+                const uint4 a = load_if(in, &A[q]);
+                const uint4 b = load_if(in && op >= OP_AND, &B[q]);
+                const uint4 V = load_if(in, &V4[q]);
+                uint4 r;
+                switch (op) {
+                case OP_ATOM: r = a; break;
+                case OP_NOT: r = make_uint4(~a.x & V.x, ~a.y & V.y, ~a.z & V.z, ~a.w & V.w); break;
+                case OP_X: r = x_chunk(a, wave_shift_in(a, c0), V); break;
+                case OP_F: {
+                    const uint4 sf = wave_add(a, V, c1);
+                    r = make_uint4(a.x | (V.x & (sf.x ^ a.x ^ V.x)), a.y | (V.y & (sf.y ^ a.y ^ V.y)),
+                                   a.z | (V.z & (sf.z ^ a.z ^ V.z)), a.w | (V.w & (sf.w ^ a.w ^ V.w)));
+                    break;
+                }
+                case OP_G: {
+                    const uint4 x = make_uint4(V.x & ~a.x, V.y & ~a.y, V.z & ~a.z, V.w & ~a.w);
+                    const uint4 sg = wave_add(x, V, c1);
+                    r = make_uint4(V.x & ~(x.x | (V.x & (sg.x ^ x.x ^ V.x))), V.y & ~(x.y | (V.y & (sg.y ^ x.y ^ V.y))),
+                                   V.z & ~(x.z | (V.z & (sg.z ^ x.z ^ V.z))), V.w & ~(x.w | (V.w & (sg.w ^ x.w ^ V.w))));
+                    break;
+                }
+                case OP_AND: r = make_uint4(a.x & b.x, a.y & b.y, a.z & b.z, a.w & b.w); break;
+                case OP_OR: r = make_uint4(a.x | b.x, a.y | b.y, a.z | b.z, a.w | b.w); break;
+                default: {
+                    const uint4 o = make_uint4(a.x | b.x, a.y | b.y, a.z | b.z, a.w | b.w);
+                    const uint4 su = wave_add(b, o, c1);
+                    r = make_uint4(b.x | (a.x & (su.x ^ b.x ^ o.x)), b.y | (a.y & (su.y ^ b.y ^ o.y)),
+                                   b.z | (a.z & (su.z ^ b.z ^ o.z)), b.w | (a.w & (su.w ^ b.w ^ o.w)));
+                    break;
+                }
+                }
+                if (!in) r = make_uint4(0, 0, 0, 0);
+                body(q, in, r);
+            }
+        };
+        uint64_t hx = 0;
+        uint32_t ck = 0;
+        pass([&](uint32_t q, bool in, uint4 r) {
+            if (!in) return;
+            hx ^= chunk_hash(q, r);
+            ck |= check_chunk(r, P4[q], S4[q]);
+        });
+        const uint64_t h = hash_fin(group_xor<64>(hx)) & s.hmask;
+        const bool sep = __ballot(ck != 0) == 0;
+        const uint32_t tag = tag_of(h);
+        // walk from the slot it met (wave-uniform: every lane follows)
+        uint32_t st = S_PROBE;
+        for (uint64_t steps = 0; st == S_PROBE; ++steps) {
+            const uint64_t cur = slot_load(&s.table[pos]);
+            if (steps > s.tsize) {
+                st = S_FULL;
+            } else if (cur == kEmpty) {
+                st = S_WON;  // new after all: re-inserted later
+            } else if ((uint32_t)(cur >> 32) == tag) {
+                if ((uint32_t)cur == kPending) {
+                    st = S_FULL;  // only after a row overflow
+                } else {
+                    const uint32_t vr = (uint32_t)cur;
+                    uint32_t d = 0;
+                    pass([&](uint32_t q, bool in, uint4 r) {
+                        if (in) d |= diff4(rows4[(uint64_t)vr * nq + q], r);
+                    });
+                    if (__ballot(d != 0) == 0) st = S_DUP;
+                    else pos = slot_next(s, pos);
+                }
+            } else {
+                pos = slot_next(s, pos);
+            }
+        }
+        if (lane == 0) {
+            if (st == S_WON) {
+                const unsigned long long d = atomicAdd(&s.ctr[C_DEF1], 1ull);
+                if (d < s.def1_cap) s.def1[d] = make_uint4(op, L, R, 0);
+                else atomicExch(&s.ctr[C_DEF_OVF], 1ull);
+            } else if (st == S_FULL) {
+                atomicExch(&s.ctr[C_OVERFLOW], 1ull);
+                if (sep) report_found(s, op, L, R);
+            }
+        }
+    }
+    wave_count(s, C_DEFERRED, nrec);
+}
+
 // Verifies deferred candidates against the entries they met (now visible).
 // Candidates that turn out to be new go to list 1 for re-insertion.
 __global__ __launch_bounds__(kLanes) void k_verify_deferred(Store s) {
     const uint64_t n = s.ctr[C_DEF0];
     const uint64_t lim = n < s.def0_cap ? n : s.def0_cap;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && lim) atomicAdd(&s.ctr[C_DEFERRED], (unsigned long long)lim);
+    uint32_t nrec = 0;  // real records verified (statistics)
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < lim;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const uint4 rec = s.def0[i];
         const uint32_t op = rec.x & 15u;
         if (op == kNoRecord) continue;
+        ++nrec;
         uint64_t pos = ((uint64_t)(rec.x >> 4) << 32) | rec.w;
         const uint64_t h = cm_hash(s, op, rec.y, rec.z);
         const uint32_t tag = tag_of(h);
@@ -1228,6 +1614,7 @@ __global__ __launch_bounds__(kLanes) void k_verify_deferred(Store s) {
             pos = slot_next(s, pos);
         }
     }
+    wave_count(s, C_DEFERRED, nrec);
 }
 
 // Group version of the deferred verification (rows of 2..64 chunks): one
@@ -1238,9 +1625,9 @@ template <int G>
 __global__ __launch_bounds__(kLanes) void k_verify_grp(Store s) {
     const uint64_t n0 = s.ctr[C_DEF0];
     const uint64_t n = n0 < s.def0_cap ? n0 : s.def0_cap;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(&s.ctr[C_DEFERRED], (unsigned long long)n);
     const uint32_t NQ = s.Wp / 4;
     const uint32_t lane = __lane_id(), k = lane % G, base = lane - k;
+    uint32_t nrec = 0;  // real records verified (statistics)
     const uint64_t gid = ((uint64_t)blockIdx.x * kLanes + threadIdx.x) / G;
     const uint64_t ngroups = (uint64_t)gridDim.x * kLanes / G;
     const uint4* rows4 = reinterpret_cast<const uint4*>(s.rows);
@@ -1256,6 +1643,7 @@ __global__ __launch_bounds__(kLanes) void k_verify_grp(Store s) {
         const bool valid = i < n;
         const uint4 rec0 = load_if(valid, &s.def0[i]);
         const bool real = valid && (rec0.x & 15u) != kNoRecord;
+        nrec += real && k == 0;
         const uint4 rec = real ? rec0 : make_uint4(OP_AND, 0, 0, 0);
         const uint32_t op = rec.x & 15u, L = rec.y, R = rec.z;
         uint64_t pos = ((uint64_t)(rec.x >> 4) << 32) | rec.w;
@@ -1333,6 +1721,7 @@ __global__ __launch_bounds__(kLanes) void k_verify_grp(Store s) {
             if (sep) report_found(s, op, L, R);
         }
     }
+    wave_count(s, C_DEFERRED, nrec);
 }
 
 // Re-inserts list-1 records (the rare deferred candidates that were new).
@@ -1589,10 +1978,12 @@ TileShape tile_shape(uint32_t Wp, uint64_t lds_limit, uint32_t pref) {
     const bool group_fits = nq >= 2 && nq <= 64 && grp_lds_bytes(Wp) <= lds_limit;
     const bool lane_fits = lds_bytes(Wp) <= lds_limit;
     const TileShape group{KERNEL_GROUP, kGA, kGB, kGU, 1}, lane{KERNEL_LANE, kTileA, kLanes, kLanes, 0};
+    const TileShape wave{KERNEL_WAVE, kWA, kWB, kWU, 1};
+    if (pref == KERNEL_WAVE) return wave;
     if (pref == KERNEL_GROUP && group_fits) return group;
     if (lane_fits) return lane;
     if (group_fits) return group;
-    return TileShape{KERNEL_GENERIC, kTileA, kLanes, kLanes, 0};
+    return wave;
 }
 
 template <class K>
@@ -1604,12 +1995,19 @@ static hipError_t raise_lds(K kernel, uint64_t lds) {
 
 hipError_t generate_blocks(const Store& s, uint64_t n_tiles, uint64_t& blocks) {
     blocks = n_tiles;
-    if (s.kernel != KERNEL_GROUP) return hipSuccess;
+    if (s.kernel != KERNEL_GROUP && s.kernel != KERNEL_WAVE) return hipSuccess;
     const uint64_t lds = grp_lds_bytes(s.Wp);
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
+    if (s.kernel == KERNEL_WAVE) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_generate_wave, kLanes, 0);
+        if (e != hipSuccess) return e;
+        const uint64_t resident = (uint64_t)(per_cu > 0 ? per_cu : 1) * (uint64_t)(cus > 0 ? cus : 1);
+        blocks = n_tiles < resident ? n_tiles : resident;
+        return hipSuccess;
+    }
     switch (group_size(s.Wp / 4)) {
 #define LTLF_OCC(G)                                                                              \
     case G:                                                                                      \
@@ -1647,13 +2045,16 @@ hipError_t launch_generate(const Store& s, const SegTable& t, uint64_t blocks, h
 #undef LTLF_GRP
         default: return hipErrorInvalidValue;
         }
+    } else if (s.kernel == KERNEL_WAVE) {
+        if (blocks == 0 || blocks > n) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_generate_wave, dim3((uint32_t)blocks), block, 0, st, s, t);
     } else if (s.kernel == KERNEL_LANE) {
         const uint64_t lds = lds_bytes(s.Wp);
         e = raise_lds(k_generate_lds<kBatch>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_generate_lds<kBatch>, grid, block, (uint32_t)lds, st, s, t);
     } else {
-        hipLaunchKernelGGL(k_generate, grid, block, 0, st, s, t);
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -1662,7 +2063,9 @@ hipError_t launch_verify_deferred(const Store& s, hipStream_t st) {
     // records are the same for every generation kernel; rows of 2..64
     // chunks are verified by lane groups (coalesced row reads)
     const uint32_t nq = s.Wp / 4;
-    if (nq >= 2 && nq <= 64) {
+    if (nq > 64) {
+        hipLaunchKernelGGL(k_verify_wave, dim3(2048), dim3(kLanes), 0, st, s);
+    } else if (nq >= 2) {
         switch (group_size(s.Wp / 4)) {
 #define LTLF_VGRP(G) \
     case G: hipLaunchKernelGGL(k_verify_grp<G>, dim3(2048), dim3(kLanes), 0, st, s); break;

@@ -26,6 +26,7 @@ FLAG_EXHAUST = 0x1
 FLAG_PROFILE = 0x2
 FLAG_KERNEL_LANE = 0x4  # one candidate per lane (default where it fits)
 FLAG_KERNEL_GROUP = 0x8  # one candidate per lane group (rows of 2..64 chunks)
+FLAG_KERNEL_WAVE = 0x10  # one candidate per wavefront (any row width)
 FLAG_WEAK_HASH = 0x100  # test hook: 6-bit hashes, every probe meets an equal tag
 
 OP_NAMES = ("!", "X", "F", "G", "&", "|", "U")  # index = ltlf_op

@@ -65,14 +65,33 @@ def test_tiny_exhaustive(synth, seed):
     compare(synth, workload.tiny(seed), 8, exhaust=True)
 
 
+@pytest.mark.parametrize("seed", [1, 2])
+def test_tiny_exhaustive_wave(synth, seed):
+    """One-chunk rows through the wave kernel (63 of 64 lanes past the row)."""
+    compare(synth, workload.tiny(seed), 8, exhaust=True, flags=m.FLAG_KERNEL_WAVE)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_large_exhaustive(synth, seed):
+    """The large configuration (1024 traces, ~41,000 bits per CM: 328 chunks,
+    six 64-chunk steps per row) to cost 5, every level compared."""
+    compare(synth, workload.large(seed), 5, exhaust=True)
+
+
+def test_large_weak_hash(synth):
+    """Wide rows with every probe meeting an equal tag: the wave kernel's
+    verification passes and the wave verification kernel carry the work."""
+    compare(synth, workload.large(3), 4, exhaust=True, flags=m.FLAG_WEAK_HASH)
+
+
 @pytest.mark.parametrize("seed", [1, 2, 3, 4])
 def test_medium_plain(synth, seed):
     p = workload.medium(seed)
     compare(synth, p, p.cost_bound)
 
 
-KERNELS = pytest.mark.parametrize("kflag", [0, m.FLAG_KERNEL_LANE, m.FLAG_KERNEL_GROUP],
-                                  ids=["default", "lane", "group"])
+KERNELS = pytest.mark.parametrize("kflag", [0, m.FLAG_KERNEL_LANE, m.FLAG_KERNEL_GROUP, m.FLAG_KERNEL_WAVE],
+                                  ids=["default", "lane", "group", "wave"])
 
 
 @KERNELS
@@ -115,7 +134,7 @@ def test_weak_hash_wide_rows(synth, seed, kflag):
 
 
 @pytest.mark.parametrize("problem", ["tiny", "medium"])
-@pytest.mark.parametrize("kflag", [0, m.FLAG_KERNEL_GROUP], ids=["default", "group"])
+@pytest.mark.parametrize("kflag", [0, m.FLAG_KERNEL_GROUP, m.FLAG_KERNEL_WAVE], ids=["default", "group", "wave"])
 def test_row_limit_matches_oracle_capacity(synth, problem, kflag):
     p = workload.tiny(3) if problem == "tiny" else workload.medium(3)
     full = oracle.solve(p, cost_bound=7, exhaust=True)
@@ -170,10 +189,10 @@ def test_edge_long_traces_cross_words(synth):
                                    (40, 40, 40, 64), (60, 60, 60, 64), (90, 90, 60, 64)],
                          ids=["rows-1q", "rows-2q", "rows-5q", "rows-16q", "rows-33q", "rows-60q",
                               "rows-90q"])
-@pytest.mark.parametrize("kflag", [0, m.FLAG_KERNEL_GROUP], ids=["default", "group"])
+@pytest.mark.parametrize("kflag", [0, m.FLAG_KERNEL_GROUP, m.FLAG_KERNEL_WAVE], ids=["default", "group", "wave"])
 def test_edge_row_widths(synth, shape, kflag):
     """Row widths across the lane kernel's LDS limit, the group sizes (4..64
-    lanes per candidate) and past them (generic kernel)."""
+    lanes per candidate) and past them (wave kernel)."""
     npos, nneg, lo, hi = shape
     p = workload.make_problem(21, 3, npos, nneg, lo, hi, 5, 5, q_range=(0.3, 0.7), name=f"wide{hi}")
     compare(synth, p, 4, exhaust=True, flags=kflag)

@@ -12,8 +12,10 @@ once before timing (inputs resident in HBM); each step is one ltlf_run.
 value = sum over levels of |U_c| / step time.  Also reported: time to
 formula of the plain solve (upload + enumeration to the minimal cost +
 witness) on the medium problems of seeds 1..4, the roofline of the dominant
-kernel (generation) from HIP events around its launches, and the CPU oracle
-on a bounded sample of the same problem.
+kernel (generation) from HIP events around its launches, the CPU oracle
+on a bounded sample of the same problem, and the batched configuration
+(256 problems of mixed shape) solved one by one and in one
+ltlf_solve_batch call, with identical results required.
 """
 from __future__ import annotations
 
@@ -71,6 +73,48 @@ def cpu_baseline(seed: int, bound: int):
                       f"enumeration, {wall:.2f} s wall"}
 
 
+def batched_compare(synth, count: int):
+    """The batched configuration (count problems, each to its own bound of
+    planted cost + 3, plain solve): one by one (upload + solve each), then in
+    one ltlf_solve_batch call; the results must agree."""
+    import torch
+    import workload
+
+    ps = workload.batched(1, count)
+    synth.solve(ps[0])  # warm-up
+    torch.cuda.synchronize()
+    solo, each = [], []
+    t0 = time.perf_counter()
+    for p in ps:
+        a = time.perf_counter()
+        solo.append(synth.solve(p))
+        each.append((time.perf_counter() - a) * 1e3)
+    torch.cuda.synchronize()
+    t_solo = time.perf_counter() - t0
+    log(f"[bench] batched config: one by one {count} problems in {t_solo:.3f} s")
+    t_batch = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        bat = synth.solve_batch(ps)
+        torch.cuda.synchronize()
+        t_batch.append(time.perf_counter() - a)
+        log(f"[bench] batched config: ltlf_solve_batch {count} problems in {t_batch[-1]:.3f} s")
+    for p, a, b in zip(ps, solo, bat):
+        assert (a.status, a.min_cost, a.levels_done, a.level_counts) == \
+            (b.status, b.min_cost, b.levels_done, b.level_counts), p.name
+    each.sort()
+    tb = min(t_batch)
+    return {"problems": count, "one_by_one_problems_per_s": round(count / t_solo, 2),
+            "batch_problems_per_s": round(count / tb, 2), "speedup": round(t_solo / tb, 3),
+            "one_by_one_ms_p50": round(each[len(each) // 2], 3),
+            "one_by_one_ms_p99": round(each[min(len(each) - 1, (len(each) * 99) // 100)], 3),
+            "batch_wall_ms": round(tb * 1e3, 1), "batch_launches_per_level_loop": bat[0].gen_launches,
+            "results_identical": True,
+            "config": "props U{2..5}, traces per class U{8..256}, lengths 4-64, planted cost U{6..12}, "
+                      "bound planted+3, master seed 1"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +126,9 @@ def main() -> int:
     ap.add_argument("--cpu-bound", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttf", action="store_true")
+    ap.add_argument("--batched", type=int, default=256,
+                    help="problems of the batched configuration solved one by one and with "
+                         "ltlf_solve_batch (0 = skip)")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (for scaling "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -175,6 +222,10 @@ def main() -> int:
         ttf = {"median_ms": round(statistics.median(v["ms"] for v in per_seed.values()), 3),
                "per_seed": per_seed, "includes": "host-to-device upload of the specification"}
 
+    batched = None
+    if args.batched > 0:
+        batched = batched_compare(synth, args.batched)
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.seed, args.cpu_bound)
     if cpu:
         log(f"[bench] cpu baseline {cpu['value']:.0f} unique/s")
@@ -200,6 +251,7 @@ def main() -> int:
                    "candidates": last.candidates, "deferred": last.deferred,
                    "status": last.status_name, "min_cost": last.min_cost},
         "time_to_formula": ttf,
+        "batched": batched,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

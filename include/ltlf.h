@@ -136,9 +136,9 @@ typedef struct {
     double enum_ms;           /* out: stream time of the whole run (events) */
     double gen_ms;            /* out: summed generation kernel time (PROFILE) */
     double verify_ms;         /* out: summed verification kernel time (PROFILE) */
-    uint64_t dead_rows;       /* out: row indices taken but left unused (lost
-                                 slot claims, allocation tails); each level is
-                                 compacted at its end (statistics) */
+    uint64_t dead_rows;       /* out: row indices taken but left unused (the
+                                 allocation tails of the persistent kernels);
+                                 each level is compacted at its end (statistics) */
 } ltlf_result;
 
 typedef struct ltlf_ctx ltlf_ctx;
@@ -190,6 +190,35 @@ ltlf_status ltlf_run(ltlf_ctx *ctx, const ltlf_costs *costs, uint32_t cost_bound
 /* ltlf_load followed by ltlf_run. */
 ltlf_status ltlf_solve(ltlf_ctx *ctx, const ltlf_spec *spec, const ltlf_costs *costs,
                        uint32_t cost_bound, uint32_t flags, void *stream, ltlf_result *res);
+
+/* Solve n independent problems together: the batched form of ltlf_solve
+ * (paper, "Program synthesis": the same bottom-up enumeration, run for many
+ * specifications at once).  The context's workspace is divided among the
+ * problems in proportion to their row width; all problems advance one cost
+ * level at a time, with one generation launch (one wavefront per candidate,
+ * any row width), one verification launch and one transfer of every
+ * problem's counters per level for the whole batch.  A problem leaves the
+ * batch when the candidates of its next level might not fit its share (or it
+ * overflows the row limit), and is then solved alone, from the start, with
+ * the whole workspace; so every result equals that of ltlf_solve on the same
+ * problem: status,
+ * minimal cost, levels_done and level counts (the witness may be another
+ * formula of the same cost).
+ *   specs[i], bounds[i], results[i]: problem i; results[i] as for ltlf_run
+ *     (level_counts and formula are caller buffers, or NULL).
+ *   costs: shared by all problems.  flags: LTLF_FLAG_EXHAUST and
+ *     LTLF_FLAG_DEBUG_WEAK_HASH as for ltlf_run (others are ignored).
+ * The context's row limit applies to every problem as in ltlf_solve.
+ * Statistics in results[i]: enum_ms is the whole batch's time, gen_launches
+ * the batch's generation launches.  The context's loaded problem is
+ * discarded (call ltlf_load again before ltlf_run).  An invalid spec or
+ * bound gives results[i].status = EINVAL without stopping the batch.
+ * Returns OK, or EINVAL (null pointers, n == 0, atom_cost == 0), ENOMEM
+ * (workspace below 64 MiB per problem), EDEVICE. */
+ltlf_status ltlf_solve_batch(ltlf_ctx *ctx, uint32_t n, const ltlf_spec *specs,
+                             const ltlf_costs *costs, const uint32_t *bounds,
+                             uint32_t flags, void *hip_stream,
+                             ltlf_result *results);
 
 /* Export CMs first .. first+count-1 (clipped to |U_cost|) of U_cost from the
  * last run in the canonical layout: per CM, trace by trace in the caller's

@@ -6,12 +6,12 @@ include/ltlf.h); this package only binds it.
 from .ltlf import (Synthesizer, Result, LtlfError, load_library, ltlf_status_str, ltlf_ctx_create,
                    ltlf_ctx_last_error,
                    ltlf_ctx_set_workspace, ltlf_ctx_set_row_limit, ltlf_ctx_destroy, ltlf_load,
-                   ltlf_run, ltlf_solve, ltlf_export_level, ltlf_formula_of, FLAG_EXHAUST, FLAG_PROFILE,
+                   ltlf_run, ltlf_solve, ltlf_solve_batch, ltlf_export_level, ltlf_formula_of, FLAG_EXHAUST, FLAG_PROFILE,
                    FLAG_KERNEL_LANE, FLAG_KERNEL_GROUP, FLAG_KERNEL_WAVE,
                    FLAG_WEAK_HASH, UNIT_ALL, STATUS_NAMES, LIB_PATH)
 
 __all__ = ["Synthesizer", "Result", "LtlfError", "load_library", "ltlf_status_str",
            "ltlf_ctx_create", "ltlf_ctx_last_error", "ltlf_ctx_set_workspace", "ltlf_ctx_set_row_limit",
-           "ltlf_ctx_destroy", "ltlf_load", "ltlf_run", "ltlf_solve", "ltlf_export_level",
+           "ltlf_ctx_destroy", "ltlf_load", "ltlf_run", "ltlf_solve", "ltlf_solve_batch", "ltlf_export_level",
            "ltlf_formula_of", "FLAG_EXHAUST", "FLAG_PROFILE", "FLAG_KERNEL_LANE", "FLAG_KERNEL_GROUP", "FLAG_KERNEL_WAVE", "FLAG_WEAK_HASH", "UNIT_ALL", "STATUS_NAMES",
            "LIB_PATH"]

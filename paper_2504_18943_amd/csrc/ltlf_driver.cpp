@@ -76,6 +76,13 @@ struct ltlf_ctx {
 
     // description of the last failure (empty after a successful call)
     std::string err;
+
+    // batched solving: export staging of this context (sub-contexts of a
+    // batch need none), and the pooled sub-contexts with their pinned mirror
+    uint64_t staging_bytes = kStagingBytes;
+    std::vector<ltlf_ctx*> subs;
+    unsigned long long* h_batch = nullptr;  // pinned, h_batch_cap counters
+    uint64_t h_batch_cap = 0;
 };
 
 namespace {
@@ -131,7 +138,7 @@ ltlf_status plan_memory_impl(ltlf_ctx* c) {
     c->d_atoms = reinterpret_cast<uint32_t*>(take(4 * Wp * c->n_props));
     c->d_ctr = reinterpret_cast<unsigned long long*>(take(8 * C_NUM));
     c->d_tokens = reinterpret_cast<uint32_t*>(take(4 * (1 + kMaxTokens + 3 * (kMaxTokens + 1))));
-    c->d_stage = reinterpret_cast<uint64_t*>(take(kStagingBytes));
+    c->d_stage = reinterpret_cast<uint64_t*>(take(c->staging_bytes));
     off = align_up(off, 256);
     if (off >= c->ws_bytes) return LTLF_ENOMEM;
     uint64_t rest = c->ws_bytes - off;
@@ -354,6 +361,70 @@ struct Profiler {
     }
 };
 
+// Start of a run: per-level bookkeeping, store settings, and on the stream
+// (a1) encoding of the atoms and masks, counters reset, initial table.
+ltlf_status begin_run(ltlf_ctx* c, uint32_t bound, uint32_t flags, uint32_t kernel, hipStream_t s) {
+    c->ran = false;
+    c->lstart.assign(bound + 1, 0);
+    c->lcount.assign(bound + 1, 0);
+    c->st.cap = c->plan_cap;  // the row limit is applied to live rows per level
+    c->st.hmask = (flags & LTLF_FLAG_DEBUG_WEAK_HASH) ? 0x3Full : ~0ull;
+    c->st.kernel = kernel;
+    TRY_HIP(launch_encode(c->d_letters, c->d_lengths, c->d_pos_off, c->d_seg_off, c->d_positive,
+                          c->n_traces, c->n_props, c->Wp, c->d_V, c->d_S, c->d_P0, c->d_atoms, s));
+    TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(c->d_ctr), C_NUM, 0, s));
+    const uint64_t slots0 = std::min<uint64_t>(pow2_ceil(std::max<uint64_t>(4ull * c->n_props, kMinTableSlots)),
+                                               c->table_max);
+    c->st.tsize = slots0;
+    TRY_HIP(launch_fill_u64(c->st.table, slots0, ~0ull, s));
+    return LTLF_OK;
+}
+
+void reset_result(ltlf_result* res, uint32_t row_bytes) {
+    res->status = LTLF_NOT_FOUND;
+    res->min_cost = 0;
+    res->levels_done = 0;
+    res->overflow_level = 0;
+    res->formula_len = 0;
+    res->candidates = 0;
+    res->unique_total = 0;
+    res->deferred = 0;
+    res->row_bytes = row_bytes;
+    res->gen_launches = 0;
+    res->verify_launches = 0;
+    res->enum_ms = 0.0;
+    res->gen_ms = 0.0;
+    res->verify_ms = 0.0;
+    res->dead_rows = 0;
+}
+
+// Copies the witness formula (or an empty string) and the level counts of a
+// finished run into the caller's buffers.
+ltlf_status finish_result(ltlf_ctx* c, ltlf_result* res, ltlf_status status, uint32_t wit_op, uint32_t wit_a,
+                          uint32_t wit_b, hipStream_t s) {
+    uint64_t uniq = 0;
+    for (uint32_t lev = 1; lev <= res->levels_done; ++lev) uniq += c->lcount[lev];
+    res->unique_total = uniq;
+    if (res->level_counts) {
+        for (uint32_t i = 0; i < res->level_counts_len; ++i)
+            res->level_counts[i] = (i <= res->levels_done && i < c->lcount.size()) ? c->lcount[i] : 0;
+    }
+    res->status = status;
+    if (status == LTLF_OK) {
+        std::string f;
+        TRY(render_formula(c, wit_op, wit_a, wit_b, s, f));
+        res->formula_len = f.size() + 1;
+        if (res->formula) {
+            if (res->formula_cap < f.size() + 1) return LTLF_EBUFSZ;
+            std::memcpy(res->formula, f.c_str(), f.size() + 1);
+        }
+    } else if (res->formula && res->formula_cap) {
+        res->formula[0] = 0;
+        res->formula_len = 1;
+    }
+    return LTLF_OK;
+}
+
 ltlf_status validate_spec(const ltlf_spec* sp) {
     if (!sp || !sp->lengths || !sp->letters || !sp->positive) return LTLF_EINVAL;
     if (sp->n_props < 1 || sp->n_props > 32 || sp->n_traces < 1) return LTLF_EINVAL;
@@ -439,7 +510,10 @@ ltlf_status ltlf_ctx_set_row_limit(ltlf_ctx* c, uint64_t max_rows) {
 
 void ltlf_ctx_destroy(ltlf_ctx* c) {
     if (!c) return;
+    for (ltlf_ctx* sub : c->subs) ltlf_ctx_destroy(sub);
+    c->subs.clear();
     (void)hipSetDevice(c->device);
+    if (c->h_batch) (void)hipHostFree(c->h_batch);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
     if (c->h_tokens) (void)hipHostFree(c->h_tokens);
@@ -493,35 +567,15 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bool exhaust = (flags & LTLF_FLAG_EXHAUST) != 0;
 
-    res->status = LTLF_NOT_FOUND;
-    res->min_cost = 0;
-    res->levels_done = 0;
-    res->overflow_level = 0;
-    res->formula_len = 0;
-    res->candidates = 0;
-    res->unique_total = 0;
-    res->deferred = 0;
-    res->row_bytes = 4 * c->Wp;
-    res->gen_launches = 0;
-    res->verify_launches = 0;
-    res->enum_ms = 0.0;
-    res->gen_ms = 0.0;
-    res->verify_ms = 0.0;
-    res->dead_rows = 0;
+    reset_result(res, 4 * c->Wp);
     const bool profile = (flags & LTLF_FLAG_PROFILE) != 0;
     Profiler prof;
     prof.c = c;
-    c->ran = false;
-    c->lstart.assign(bound + 1, 0);
-    c->lcount.assign(bound + 1, 0);
-    c->st.cap = c->plan_cap;  // the row limit is applied to live rows per level
-    c->st.hmask = (flags & LTLF_FLAG_DEBUG_WEAK_HASH) ? 0x3Full : ~0ull;
     const uint32_t pref = (flags & LTLF_FLAG_KERNEL_WAVE)    ? KERNEL_WAVE
                           : (flags & LTLF_FLAG_KERNEL_GROUP) ? KERNEL_GROUP
                           : (flags & LTLF_FLAG_KERNEL_LANE)  ? KERNEL_LANE
                                                              : KERNEL_AUTO;
     const TileShape shape = tile_shape(c->Wp, c->lds_limit, pref);
-    c->st.kernel = shape.kind;
 
     hipEvent_t e0, e1;
     TRY_HIP(hipEventCreate(&e0));
@@ -535,14 +589,7 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
     } guard{e0, e1};
     TRY_HIP(hipEventRecord(e0, s));
 
-    // a1: encode atoms and masks; reset counters and the initial table
-    TRY_HIP(launch_encode(c->d_letters, c->d_lengths, c->d_pos_off, c->d_seg_off, c->d_positive,
-                          c->n_traces, c->n_props, c->Wp, c->d_V, c->d_S, c->d_P0, c->d_atoms, s));
-    TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(c->d_ctr), C_NUM, 0, s));
-    const uint64_t slots0 = std::min<uint64_t>(pow2_ceil(std::max<uint64_t>(4ull * c->n_props, kMinTableSlots)),
-                                               c->table_max);
-    c->st.tsize = slots0;
-    TRY_HIP(launch_fill_u64(c->st.table, slots0, ~0ull, s));
+    TRY(begin_run(c, bound, flags, shape.kind, s));
 
     uint64_t rows = 0;
     ltlf_status status = LTLF_NOT_FOUND;
@@ -748,30 +795,11 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
     float ms = 0.f;
     TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
     res->enum_ms = ms;
-    res->status = status;
     res->candidates = candidates;
     res->deferred = c->h_ctr[C_DEFERRED];
     c->levels_done = res->levels_done;
-    uint64_t uniq = 0;
-    for (uint32_t lev = 1; lev <= res->levels_done; ++lev) uniq += c->lcount[lev];
-    res->unique_total = uniq;
-    if (res->level_counts) {
-        for (uint32_t i = 0; i < res->level_counts_len; ++i)
-            res->level_counts[i] = (i <= res->levels_done && i < c->lcount.size()) ? c->lcount[i] : 0;
-    }
     c->ran = true;
-    if (status == LTLF_OK) {
-        std::string f;
-        TRY(render_formula(c, wit_op, wit_a, wit_b, s, f));
-        res->formula_len = f.size() + 1;
-        if (res->formula) {
-            if (res->formula_cap < f.size() + 1) return LTLF_EBUFSZ;
-            std::memcpy(res->formula, f.c_str(), f.size() + 1);
-        }
-    } else if (res->formula && res->formula_cap) {
-        res->formula[0] = 0;
-        res->formula_len = 1;
-    }
+    TRY(finish_result(c, res, status, wit_op, wit_a, wit_b, s));
     return status;
 }
 
@@ -779,6 +807,269 @@ ltlf_status ltlf_solve(ltlf_ctx* c, const ltlf_spec* sp, const ltlf_costs* k, ui
                        uint32_t flags, void* stream, ltlf_result* res) {
     TRY(ltlf_load(c, sp, stream));
     return ltlf_run(c, k, bound, flags, stream, res);
+}
+
+ltlf_status ltlf_solve_batch(ltlf_ctx* c, uint32_t n, const ltlf_spec* specs, const ltlf_costs* k,
+                             const uint32_t* bounds, uint32_t flags, void* stream, ltlf_result* results) {
+    if (!c || !specs || !k || !bounds || !results || n == 0) return LTLF_EINVAL;
+    c->err.clear();
+    if (k->atom_cost == 0) return LTLF_EINVAL;
+    TRY_HIP(hipSetDevice(c->device));
+    TRY(ensure_workspace(c));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool exhaust = (flags & LTLF_FLAG_EXHAUST) != 0;
+    c->loaded = false;  // the workspace is re-carved below
+    c->ran = false;
+
+    // problems that can run in the batch, and their row widths
+    std::vector<uint32_t> wp(n, 0);
+    std::vector<char> in_batch(n, 0), solo(n, 0);
+    uint32_t maxb = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        ltlf_result* r = &results[i];
+        reset_result(r, 0);
+        if (validate_spec(&specs[i]) != LTLF_OK || bounds[i] < k->atom_cost || bounds[i] > kMaxBound) {
+            r->status = LTLF_EINVAL;
+            continue;
+        }
+        uint64_t bits = 0;
+        for (uint32_t t = 0; t < specs[i].n_traces; ++t) bits += specs[i].lengths[t] + 1;
+        wp[i] = (uint32_t)align_up((bits + 31) / 32, 4);
+        r->row_bytes = 4 * wp[i];
+        in_batch[i] = 1;
+        maxb = std::max(maxb, bounds[i]);
+    }
+
+    // control region: per-problem stores, segment pieces, gathered counters
+    constexpr uint64_t kBatchSegs = 1ull << 16;
+    const uint64_t off_segs = align_up(sizeof(Store) * (uint64_t)n, 256);
+    const uint64_t off_gather = off_segs + align_up(sizeof(BSeg) * kBatchSegs, 256);
+    const uint64_t off_slices = off_gather + align_up(8ull * C_NUM * n, 256);
+    if (off_slices + 64ull * n * (1ull << 20) > c->ws_bytes) return fail(c, LTLF_ENOMEM, "workspace too small for the batch");
+    Store* d_stores = reinterpret_cast<Store*>(c->ws);
+    BSeg* d_segs = reinterpret_cast<BSeg*>(c->ws + off_segs);
+    unsigned long long* d_gather = reinterpret_cast<unsigned long long*>(c->ws + off_gather);
+    if (c->h_batch_cap < (uint64_t)C_NUM * n) {
+        if (c->h_batch) (void)hipHostFree(c->h_batch);
+        c->h_batch = nullptr;
+        c->h_batch_cap = 0;
+        TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_batch), 8ull * C_NUM * n, hipHostMallocDefault));
+        c->h_batch_cap = (uint64_t)C_NUM * n;
+    }
+
+    // slices of the rest, proportional to the bytes a stored row costs
+    double wsum = 0;
+    for (uint32_t i = 0; i < n; ++i)
+        if (in_batch[i]) wsum += 4.0 * wp[i] + 48.0;
+    while (c->subs.size() < n) {
+        ltlf_ctx* sub = nullptr;
+        TRY(ltlf_ctx_create(c->device, 0, &sub));
+        sub->staging_bytes = 4096;
+        c->subs.push_back(sub);
+    }
+    const uint64_t rest = c->ws_bytes - off_slices;
+    uint64_t off = off_slices;
+    std::vector<uint32_t> act;  // batch slot -> problem
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!in_batch[i]) continue;
+        const uint64_t bytes = (uint64_t)((double)rest * (4.0 * wp[i] + 48.0) / wsum) / 256 * 256;
+        ltlf_ctx* sub = c->subs[i];
+        sub->ws = c->ws + off;
+        sub->ws_bytes = bytes;
+        sub->own_ws = false;
+        sub->row_limit = c->row_limit;
+        off += bytes;
+        if (bytes < (16ull << 20) || ltlf_load(sub, &specs[i], stream) != LTLF_OK) {
+            solo[i] = 1;  // does not fit a slice: solved alone below
+            continue;
+        }
+        TRY(begin_run(sub, bounds[i], flags & LTLF_FLAG_DEBUG_WEAK_HASH, KERNEL_WAVE, s));
+        act.push_back(i);
+    }
+
+    struct State {
+        uint64_t rows = 0, next_tile = 0, total = 0;
+        LevelPlan plan;
+        ltlf_status status = LTLF_NOT_FOUND;
+        uint32_t wit_op = 0, wit_a = 0, wit_b = 0;
+        bool done = false;
+    };
+    std::vector<State> st(n);
+    hipEvent_t e0, e1;
+    TRY_HIP(hipEventCreate(&e0));
+    TRY_HIP(hipEventCreate(&e1));
+    struct EventGuard {
+        hipEvent_t a, b;
+        ~EventGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+    TRY_HIP(hipEventRecord(e0, s));
+    uint32_t gen_launches = 0;
+    std::vector<Store> h_stores;
+    std::vector<BSeg> pieces;
+    std::vector<uint32_t> live;  // batch slot -> problem, problems still running
+    for (uint32_t lev = 1; lev <= maxb; ++lev) {
+        live.clear();
+        for (uint32_t i : act)
+            if (!st[i].done && !solo[i] && lev <= bounds[i]) live.push_back(i);
+        if (live.empty()) break;
+        // plan every problem's level; table room for every candidate being new
+        for (uint32_t i : live) {
+            ltlf_ctx* sub = c->subs[i];
+            State& q = st[i];
+            sub->lstart[lev] = q.rows;
+            q.plan = plan_level(sub, k, lev, tile_shape(sub->Wp, sub->lds_limit, KERNEL_WAVE));
+            q.next_tile = 0;
+            q.total = 0;
+            for (const Seg& g : q.plan.segs) q.total += g.tiles;
+            if (q.total) {
+                // a problem stays in the batch while every candidate of its next
+                // level could be stored in its slice; past that it is solved
+                // alone (from the start, with the whole workspace)
+                if (q.plan.cand_ub > sub->st.cap - q.rows || 2 * (q.rows + q.plan.cand_ub) > sub->table_max) {
+                    solo[i] = 1;
+                    q.total = 0;
+                    continue;
+                }
+                if (ensure_table(sub, q.rows, q.plan.cand_ub, s) != LTLF_OK)
+                    return fail(c, LTLF_EDEVICE, sub->err.c_str());
+            }
+        }
+        {  // drop the problems that left the batch
+            size_t w = 0;
+            for (uint32_t i : live)
+                if (!solo[i]) live[w++] = i;
+            live.resize(w);
+        }
+        if (live.empty()) break;
+        h_stores.resize(live.size());
+        for (size_t j = 0; j < live.size(); ++j) h_stores[j] = c->subs[live[j]]->st;
+        TRY_HIP(hipMemcpyAsync(d_stores, h_stores.data(), sizeof(Store) * live.size(), hipMemcpyHostToDevice, s));
+        // launches: each takes, per problem, the next tiles whose candidates fit
+        // its deferral list
+        for (;;) {
+            pieces.clear();
+            uint64_t first = 0;
+            for (size_t j = 0; j < live.size() && pieces.size() + kMaxSegs < kBatchSegs; ++j) {
+                State& q = st[live[j]];
+                uint64_t budget = c->subs[live[j]]->st.def0_cap;
+                uint64_t seg_first = 0;
+                for (size_t g = 0; g < q.plan.segs.size() && q.next_tile < q.total; ++g) {
+                    const Seg& sg = q.plan.segs[g];
+                    const uint64_t seg_end = seg_first + sg.tiles;
+                    if (q.next_tile < seg_end) {
+                        const uint64_t per = q.plan.cand_per_tile[g];
+                        const uint64_t fit = per ? budget / per : seg_end - q.next_tile;
+                        const uint64_t take = std::min<uint64_t>(fit, seg_end - q.next_tile);
+                        if (take == 0) break;
+                        BSeg b{};
+                        b.problem = (uint32_t)j;
+                        b.first = first;
+                        b.lt0 = q.next_tile - seg_first;
+                        b.seg = sg;
+                        pieces.push_back(b);
+                        first += take;
+                        q.next_tile += take;
+                        budget -= take * per;
+                    }
+                    seg_first = seg_end;
+                }
+            }
+            if (pieces.empty()) break;
+            TRY_HIP(hipMemcpyAsync(d_segs, pieces.data(), sizeof(BSeg) * pieces.size(), hipMemcpyHostToDevice, s));
+            TRY_HIP(launch_generate_batch(d_stores, d_segs, (uint32_t)pieces.size(), 0, first, s));
+            TRY_HIP(launch_verify_batch(d_stores, (uint32_t)live.size(), s));
+            TRY_HIP(launch_between_batch(d_stores, (uint32_t)live.size(), s));
+            ++gen_launches;
+            // a host copy of pieces must outlive the asynchronous transfer
+            TRY_HIP(hipStreamSynchronize(s));
+        }
+        TRY_HIP(launch_gather_ctr(d_stores, (uint32_t)live.size(), d_gather, s));
+        TRY_HIP(hipMemcpyAsync(c->h_batch, d_gather, 8ull * C_NUM * live.size(), hipMemcpyDeviceToHost, s));
+        TRY_HIP(hipStreamSynchronize(s));
+        // close the level of every problem
+        for (size_t j = 0; j < live.size(); ++j) {
+            const uint32_t i = live[j];
+            ltlf_ctx* sub = c->subs[i];
+            State& q = st[i];
+            ltlf_result* r = &results[i];
+            if (q.total == 0) {
+                r->levels_done = lev;
+                if (lev == bounds[i]) q.done = true;
+                continue;
+            }
+            std::memcpy(sub->h_ctr, c->h_batch + (uint64_t)j * C_NUM, 8ull * C_NUM);
+            // rare: deferred candidates that were new after all (as in ltlf_run)
+            const uint64_t n0 = sub->h_ctr[C_DEF1];
+            for (uint64_t round = 0; sub->h_ctr[C_DEF1] > 0 && !sub->h_ctr[C_DEF_OVF]; ++round) {
+                if (round > n0 + 16) return fail(c, LTLF_EDEVICE, "re-insertion rounds made no progress");
+                const uint64_t m = sub->h_ctr[C_DEF1];
+                const uint64_t now_rows = std::min<uint64_t>(sub->h_ctr[C_ROWS], sub->st.cap);
+                if (ensure_table(sub, now_rows, std::min<uint64_t>(m, sub->st.cap - now_rows), s) != LTLF_OK)
+                    return fail(c, LTLF_EDEVICE, sub->err.c_str());
+                TRY_HIP(launch_reinsert(sub->st, m, s));
+                TRY_HIP(launch_set_counter(sub->d_ctr, C_DEF1, 0, s));
+                TRY_HIP(launch_verify_deferred(sub->st, s));
+                TRY_HIP(launch_between(sub->d_ctr, s));
+                if (read_counters(sub, s) != LTLF_OK) return fail(c, LTLF_EDEVICE, sub->err.c_str());
+            }
+            const uint64_t now = std::min<uint64_t>(sub->h_ctr[C_ROWS], sub->st.cap);
+            r->candidates = sub->h_ctr[C_CAND];
+            r->deferred = sub->h_ctr[C_DEFERRED];
+            if (sub->h_ctr[C_DEF_OVF] || sub->h_ctr[C_OVERFLOW] || (sub->row_limit && now > sub->row_limit)) {
+                // the slice (or the row limit) was too small: solved alone with
+                // the whole workspace, which reports what ltlf_solve reports
+                solo[i] = 1;
+                continue;
+            }
+            sub->lcount[lev] = now - q.rows;
+            q.rows = now;
+            if (sub->h_ctr[C_FOUND] && q.status != LTLF_OK) {
+                q.status = LTLF_OK;
+                r->min_cost = lev;
+                q.wit_op = (uint32_t)sub->h_ctr[C_WIT_OP];
+                q.wit_a = (uint32_t)sub->h_ctr[C_WIT_A];
+                q.wit_b = (uint32_t)sub->h_ctr[C_WIT_B];
+            }
+            r->levels_done = lev;
+            if ((q.status == LTLF_OK && !exhaust) || lev == bounds[i]) q.done = true;
+        }
+    }
+    TRY_HIP(hipEventRecord(e1, s));
+    TRY_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+    for (uint32_t i : act) {
+        if (solo[i]) continue;
+        ltlf_ctx* sub = c->subs[i];
+        ltlf_result* r = &results[i];
+        r->enum_ms = ms;
+        r->gen_launches = gen_launches;
+        r->verify_launches = gen_launches;
+        sub->levels_done = r->levels_done;
+        const ltlf_status fs = finish_result(sub, r, st[i].status, st[i].wit_op, st[i].wit_a, st[i].wit_b, s);
+        if (fs != LTLF_OK && fs != LTLF_EBUFSZ) return fail(c, fs, sub->err.c_str());
+        sub->loaded = false;  // its slice is the parent's workspace
+    }
+    // problems that did not fit their slice, alone with the whole workspace
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!solo[i]) continue;
+        uint64_t* lc = results[i].level_counts;
+        const uint32_t lcl = results[i].level_counts_len;
+        char* f = results[i].formula;
+        const uint64_t fc = results[i].formula_cap;
+        reset_result(&results[i], 4 * wp[i]);
+        const ltlf_status r = ltlf_solve(c, &specs[i], k, bounds[i], flags, stream, &results[i]);
+        results[i].level_counts = lc;
+        results[i].level_counts_len = lcl;
+        results[i].formula = f;
+        results[i].formula_cap = fc;
+        if (r < 0 && r != LTLF_EBUFSZ) return r;
+    }
+    c->loaded = false;
+    return LTLF_OK;
 }
 
 ltlf_status ltlf_export_level(ltlf_ctx* c, uint32_t cost, uint64_t first, uint64_t count,
@@ -796,7 +1087,8 @@ ltlf_status ltlf_export_level(ltlf_ctx* c, uint32_t cost, uint64_t first, uint64
     if (!host_buf) return LTLF_OK;
     if (cap_words < n * cw) return LTLF_EBUFSZ;
     TRY_HIP(hipSetDevice(c->device));
-    const uint64_t per = std::max<uint64_t>(1, kStagingBytes / 8 / cw);
+    if (c->staging_bytes < 8 * cw) return LTLF_ESTATE;
+    const uint64_t per = std::max<uint64_t>(1, c->staging_bytes / 8 / cw);
     for (uint64_t q = 0; q < n; q += per) {
         const uint64_t m = std::min<uint64_t>(per, n - q);
         TRY_HIP(launch_export(c->st.rows, c->Wp, c->lstart[cost] + lo + q, m, c->d_canon, c->n_pos,

@@ -83,6 +83,16 @@ struct SegTable {
     Seg seg[kMaxSegs];
 };
 
+// Piece of a segment in a batched launch: launch tiles [first, first + n)
+// are the segment's local tiles [lt0, lt0 + n) of problem `problem` (pieces
+// sorted by first, contiguous).
+struct BSeg {
+    uint32_t problem;
+    uint32_t pad;
+    uint64_t first, lt0;
+    Seg seg;
+};
+
 // Device-side view of one loaded problem and its store.
 struct Store {
     const uint32_t* V;      // valid-position mask, Wp words
@@ -130,6 +140,12 @@ uint64_t lds_bytes(uint32_t Wp);
 hipError_t generate_blocks(const Store& s, uint64_t n_tiles, uint64_t& blocks);
 hipError_t launch_generate(const Store& s, const SegTable& t, uint64_t blocks, hipStream_t st);
 hipError_t launch_verify_deferred(const Store& s, hipStream_t st);
+// Batched solving (device arrays of per-problem stores and segments).
+hipError_t launch_generate_batch(const Store* d_stores, const BSeg* d_segs, uint32_t nsegs, uint64_t tile0,
+                                 uint64_t tiles, hipStream_t st);
+hipError_t launch_verify_batch(const Store* d_stores, uint32_t n, hipStream_t st);
+hipError_t launch_between_batch(const Store* d_stores, uint32_t n, hipStream_t st);
+hipError_t launch_gather_ctr(const Store* d_stores, uint32_t n, unsigned long long* out, hipStream_t st);
 hipError_t launch_reinsert(const Store& s, uint64_t n, hipStream_t st);
 // Sets C_DEF0 = 0 and C_SNAP = C_ROWS; must run between any launch that
 // allocates rows and the next inserting launch.

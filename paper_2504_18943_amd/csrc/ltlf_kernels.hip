@@ -67,6 +67,14 @@ __device__ __forceinline__ void slot_store(uint64_t* p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The store has overflowed (no more slots are reserved; candidates are only
+// checked).  A coherent load: the flag is set by other blocks of the running
+// launch, and a launch that kept reserving slots after it was set could fill
+// the table.
+__device__ __forceinline__ bool store_full(const Store& s) {
+    return __hip_atomic_load(&s.ctr[C_OVERFLOW], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
 // One atomicAdd per wave for every lane that is active at the call site.
 __device__ __forceinline__ unsigned long long wave_alloc(unsigned long long* ctr) {
     const uint64_t active = __ballot(1);
@@ -382,7 +390,7 @@ __device__ __forceinline__ void write_defer(const Store& s, unsigned long long d
 template <class Emit>
 __device__ void insert_emit(const Store& s, const Masks& m, uint32_t op, uint32_t L, uint32_t R,
                             uint64_t h, uint64_t pos, uint64_t cur0, uint64_t snap, const Emit& e) {
-    const uint32_t o = probe_reserve(s, h, pos, cur0, snap, s.ctr[C_OVERFLOW] != 0, e);
+    const uint32_t o = probe_reserve(s, h, pos, cur0, snap, store_full(s), e);
     if (o == P_WON) {
         write_row(s, m, op, L, R, h, pos, wave_alloc(&s.ctr[C_ROWS]), e);
     } else if (o == P_DEFER) {
@@ -660,7 +668,7 @@ __global__ __launch_bounds__(kLanes) void k_generate_lds(Store s, SegTable t) {
     const uint64_t tile = t.tile_begin + blockIdx.x;
     if (tile >= t.tile_end) return;
     const uint64_t snap = s.ctr[C_SNAP];
-    const bool full_store = s.ctr[C_OVERFLOW] != 0;
+    const bool full_store = store_full(s);
     uint32_t si = 0;
     while (si + 1 < t.n && t.first[si + 1] <= tile) ++si;
     const Seg& g = t.seg[si];
@@ -961,8 +969,9 @@ __global__ __launch_bounds__(kLanes) void k_generate_grp(Store s, SegTable t) {
     uint4* sh_v = sh_b + kGU * NQ;
     uint4* sh_s = sh_v + NQ;
     uint4* sh_p = sh_s + NQ;
+    __shared__ uint32_t sh_full;
     const uint64_t snap = s.ctr[C_SNAP];
-    const bool full_store = s.ctr[C_OVERFLOW] != 0;
+    bool full_store = false;  // refreshed for every tile
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = __lane_id();
     const uint32_t k = lane % G, base = lane - k, grp = tid / G;
@@ -982,12 +991,15 @@ __global__ __launch_bounds__(kLanes) void k_generate_grp(Store s, SegTable t) {
         unsigned long long tl = ~0ull;
         const unsigned long long d = __hip_atomic_load(&s.ctr[C_DEF0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned long long r = __hip_atomic_load(&s.ctr[C_ROWS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (d + t.def_margin <= s.def0_cap && (full_store || r + t.row_margin <= t.row_budget))
+        const bool full = store_full(s);
+        if (d + t.def_margin <= s.def0_cap && (full || r + t.row_margin <= t.row_budget))
             tl = atomicAdd(&s.ctr[C_TILE], 1ull);
         sh_tile = tl;
+        sh_full = full;
     }
     __syncthreads();
     const uint64_t tile = sh_tile;
+    full_store = sh_full != 0;
     __syncthreads();
     if (tile >= t.tile_end) break;
     uint32_t si = 0;
@@ -1245,7 +1257,7 @@ __device__ __forceinline__ uint64_t lane_pick4(uint32_t j, uint64_t v0, uint64_t
 __device__ __forceinline__ void wave_item(const Store& s, WaveAlloc& wa, bool unary, const uint4* A,
                                           const uint4* B, uint32_t nq, uint64_t snap, bool full_store,
                                           const bool (&en)[4], const uint32_t (&op)[4], const uint32_t (&L)[4],
-                                          const uint32_t (&R)[4]) {
+                                          const uint32_t (&R)[4], uint32_t chunk) {
     const uint4* P4 = reinterpret_cast<const uint4*>(s.P0);
     const uint4* S4 = reinterpret_cast<const uint4*>(s.S);
     uint4* rows4 = reinterpret_cast<uint4*>(s.rows);
@@ -1345,7 +1357,7 @@ __device__ __forceinline__ void wave_item(const Store& s, WaveAlloc& wa, bool un
     unsigned long long rb, dbase;
     // a wave stores at most four rows per work item: small chunks keep the
     // unused tails short
-    wave_take(s, wa, st == S_WON ? 1u : 0u, st == S_DEFER ? 1u : 0u, rb, dbase, kWaveChunk);
+    wave_take(s, wa, st == S_WON ? 1u : 0u, st == S_DEFER ? 1u : 0u, rb, dbase, chunk);
     const uint64_t wonm = __ballot(st == S_WON) & 0xFull;
     const uint32_t myrow = st == S_WON && rb < s.cap ? (uint32_t)rb : 0xFFFFFFFFu;
     if (wonm) {
@@ -1382,102 +1394,134 @@ __device__ __forceinline__ void wave_item(const Store& s, WaveAlloc& wa, bool un
     }
 }
 
-__global__ __launch_bounds__(kLanes) void k_generate_wave(Store s, SegTable t) {
-    __shared__ unsigned long long sh_tile;
+// One tile of the wave kernel (every thread of the block calls it): atoms,
+// unary operands or pairs of segment g, rows and records taken per wave with
+// `chunk`-sized allocations.  Returns the candidates counted by this thread.
+__device__ __forceinline__ uint32_t wave_tile(const Store& s, const Seg& g, uint64_t lt, WaveAlloc& wa,
+                                              uint64_t snap, bool full_store, uint32_t chunk) {
     const uint32_t NQ = s.Wp / 4;
-    const uint64_t snap = s.ctr[C_SNAP];
-    const bool full_store = s.ctr[C_OVERFLOW] != 0;
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid / 64;
     const uint4* rows4 = reinterpret_cast<const uint4*>(s.rows);
+    uint32_t count = 0;
+    if (g.kind == SEG_ATOM) {
+        if (tid < g.nb) {
+            process(s, OP_ATOM, tid, 0, snap);
+            ++count;
+        }
+    } else if (g.kind == SEG_UNARY) {
+        for (uint32_t iv = wave; iv < kWU; iv += kLanes / 64) {
+            const uint64_t vl = lt * kWU + iv;
+            if (vl >= g.nb) break;  // uniform over the wave
+            const uint32_t vi = (uint32_t)(g.b0 + vl);
+            const uint32_t vop = s.meta[vi].x & 7u;
+            // not not a, F F a, G G a are cheaper formulas' CMs: skipped
+            const bool en[4] = {(g.opmask & M_NOT) && vop != OP_NOT, (g.opmask & M_X) != 0,
+                                (g.opmask & M_F) && vop != OP_F, (g.opmask & M_G) && vop != OP_G};
+            const uint32_t op[4] = {OP_NOT, OP_X, OP_F, OP_G};
+            const uint32_t L[4] = {vi, vi, vi, vi}, R[4] = {0, 0, 0, 0};
+            wave_item(s, wa, true, rows4 + (uint64_t)vi * NQ, nullptr, NQ, snap, full_store, en, op, L, R, chunk);
+            if (tid % 64 == 0) count += (uint32_t)en[0] + en[1] + en[2] + en[3];
+        }
+    } else {
+        uint64_t ta, tb;
+        if (g.tri) {  // square tiles, upper triangle ta <= tb, column by column
+            tb = (uint64_t)((sqrt(8.0 * (double)lt + 1.0) - 1.0) * 0.5);
+            while ((tb + 1) * (tb + 2) / 2 <= lt) ++tb;
+            while (tb > 0 && tb * (tb + 1) / 2 > lt) --tb;
+            ta = lt - tb * (tb + 1) / 2;
+        } else {
+            const uint64_t tiles_b = (g.nb + kWB - 1) / kWB;
+            ta = lt / tiles_b;
+            tb = lt % tiles_b;
+        }
+        const bool mA = (g.opmask & M_AND) != 0, mO = (g.opmask & M_OR) != 0;
+        const bool mU = (g.opmask & M_UAB) != 0, mV = (g.opmask & M_UBA) != 0;
+        for (uint32_t it = wave; it < kWA * kWB; it += kLanes / 64) {
+            const uint64_t al = ta * kWA + it / kWB, bl = tb * kWB + it % kWB;
+            if (al >= g.na || bl >= g.nb || (g.tri && al >= bl)) continue;  // uniform over the wave
+            const uint32_t ai = (uint32_t)(g.a0 + al), bi = (uint32_t)(g.b0 + bl);
+            const bool en[4] = {mA, mO, mU, mV};
+            const uint32_t op[4] = {OP_AND, OP_OR, OP_U, OP_U};
+            const uint32_t L[4] = {ai, ai, ai, bi}, R[4] = {bi, bi, bi, ai};
+            wave_item(s, wa, false, rows4 + (uint64_t)ai * NQ, rows4 + (uint64_t)bi * NQ, NQ, snap, full_store,
+                      en, op, L, R, chunk);
+            if (tid % 64 == 0) count += (uint32_t)mA + mO + mU + mV;
+        }
+    }
+    return count;
+}
+
+__global__ __launch_bounds__(kLanes) void k_generate_wave(Store s, SegTable t) {
+    __shared__ unsigned long long sh_tile;
+    __shared__ uint32_t sh_full;
+    const uint64_t snap = s.ctr[C_SNAP];
+    const uint32_t tid = threadIdx.x;
     WaveAlloc wa;
     uint32_t count = 0;
-    // persistent: tiles from the cursor while the lists can take the tiles in flight
+    // persistent: tiles from the cursor while the lists can take the tiles in
+    // flight; the overflow flag is refreshed for every tile
     for (;;) {
         if (tid == 0) {
             unsigned long long tl = ~0ull;
             const unsigned long long d = __hip_atomic_load(&s.ctr[C_DEF0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned long long r = __hip_atomic_load(&s.ctr[C_ROWS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (d + t.def_margin <= s.def0_cap && (full_store || r + t.row_margin <= t.row_budget))
+            const bool full = store_full(s);
+            if (d + t.def_margin <= s.def0_cap && (full || r + t.row_margin <= t.row_budget))
                 tl = atomicAdd(&s.ctr[C_TILE], 1ull);
             sh_tile = tl;
+            sh_full = full;
         }
         __syncthreads();
         const uint64_t tile = sh_tile;
+        const bool full_store = sh_full != 0;
         __syncthreads();
         if (tile >= t.tile_end) break;
         uint32_t si = 0;
         while (si + 1 < t.n && t.first[si + 1] <= tile) ++si;
-        const Seg& g = t.seg[si];
-        const uint64_t lt = tile - t.first[si];
-        if (g.kind == SEG_ATOM) {
-            if (tid < g.nb) {
-                process(s, OP_ATOM, tid, 0, snap);
-                ++count;
-            }
-        } else if (g.kind == SEG_UNARY) {
-            for (uint32_t iv = wave; iv < kWU; iv += kLanes / 64) {
-                const uint64_t vl = lt * kWU + iv;
-                if (vl >= g.nb) break;  // uniform over the wave
-                const uint32_t vi = (uint32_t)(g.b0 + vl);
-                const uint32_t vop = s.meta[vi].x & 7u;
-                // not not a, F F a, G G a are cheaper formulas' CMs: skipped
-                const bool en[4] = {(g.opmask & M_NOT) && vop != OP_NOT, (g.opmask & M_X) != 0,
-                                    (g.opmask & M_F) && vop != OP_F, (g.opmask & M_G) && vop != OP_G};
-                const uint32_t op[4] = {OP_NOT, OP_X, OP_F, OP_G};
-                const uint32_t L[4] = {vi, vi, vi, vi}, R[4] = {0, 0, 0, 0};
-                wave_item(s, wa, true, rows4 + (uint64_t)vi * NQ, nullptr, NQ, snap, full_store, en, op, L, R);
-                if (tid % 64 == 0) count += (uint32_t)en[0] + en[1] + en[2] + en[3];
-            }
-        } else {
-            uint64_t ta, tb;
-            if (g.tri) {  // square tiles, upper triangle ta <= tb, column by column
-                tb = (uint64_t)((sqrt(8.0 * (double)lt + 1.0) - 1.0) * 0.5);
-                while ((tb + 1) * (tb + 2) / 2 <= lt) ++tb;
-                while (tb > 0 && tb * (tb + 1) / 2 > lt) --tb;
-                ta = lt - tb * (tb + 1) / 2;
-            } else {
-                const uint64_t tiles_b = (g.nb + kWB - 1) / kWB;
-                ta = lt / tiles_b;
-                tb = lt % tiles_b;
-            }
-            const bool mA = (g.opmask & M_AND) != 0, mO = (g.opmask & M_OR) != 0;
-            const bool mU = (g.opmask & M_UAB) != 0, mV = (g.opmask & M_UBA) != 0;
-            for (uint32_t it = wave; it < kWA * kWB; it += kLanes / 64) {
-                const uint64_t al = ta * kWA + it / kWB, bl = tb * kWB + it % kWB;
-                if (al >= g.na || bl >= g.nb || (g.tri && al >= bl)) continue;  // uniform over the wave
-                const uint32_t ai = (uint32_t)(g.a0 + al), bi = (uint32_t)(g.b0 + bl);
-                const bool en[4] = {mA, mO, mU, mV};
-                const uint32_t op[4] = {OP_AND, OP_OR, OP_U, OP_U};
-                const uint32_t L[4] = {ai, ai, ai, bi}, R[4] = {bi, bi, bi, ai};
-                wave_item(s, wa, false, rows4 + (uint64_t)ai * NQ, rows4 + (uint64_t)bi * NQ, NQ, snap,
-                          full_store, en, op, L, R);
-                if (tid % 64 == 0) count += (uint32_t)mA + mO + mU + mV;
-            }
-        }
+        count += wave_tile(s, t.seg[si], tile - t.first[si], wa, snap, full_store, kWaveChunk);
         __syncthreads();
     }
     retire_rows(s, wa.rnext, wa.rend);
     retire_records(s, wa.dnext, wa.dend);
-    unsigned long long cc = count;
-    for (int off = 32; off > 0; off >>= 1) cc += __shfl_down(cc, off);
-    if (__lane_id() == 0 && cc) atomicAdd(&s.ctr[C_CAND], cc);
+    wave_count(s, C_CAND, count);
+}
+
+// Batched form: tiles of many problems in one launch, one block per tile;
+// segs[] sorted by first tile, each naming its problem's store.  Rows and
+// records are taken exactly (chunk 1: no unused tails), each problem's
+// counters being its own addresses.
+__global__ __launch_bounds__(kLanes) void k_generate_wave_batch(const Store* stores, const BSeg* segs, uint32_t nsegs,
+                                                                uint64_t tile0) {
+    const uint64_t tile = tile0 + blockIdx.x;
+    uint32_t lo = 0, hi = nsegs;  // last seg with first <= tile
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (segs[mid].first <= tile) lo = mid;
+        else hi = mid;
+    }
+    const BSeg& b = segs[lo];
+    const Store s = stores[b.problem];
+    const uint64_t snap = s.ctr[C_SNAP];
+    const bool full_store = store_full(s);
+    WaveAlloc wa;
+    const uint32_t count = wave_tile(s, b.seg, b.lt0 + (tile - b.first), wa, snap, full_store, 1);
+    wave_count(s, C_CAND, count);
 }
 
 // Deferred records of wide rows: one wave per record, recomputing the
 // candidate step by step (any operator) against the rows it meets.
-__global__ __launch_bounds__(kLanes) void k_verify_wave(Store s) {
+__device__ __forceinline__ void verify_wave_records(const Store& s, uint64_t first_wave, uint64_t waves) {
     const uint64_t n0 = s.ctr[C_DEF0];
     const uint64_t n = n0 < s.def0_cap ? n0 : s.def0_cap;
     const uint32_t nq = s.Wp / 4, lane = __lane_id();
-    const uint64_t waves = (uint64_t)gridDim.x * (kLanes / 64);
     uint32_t nrec = 0;  // real records verified (statistics)
     const uint4* rows4 = reinterpret_cast<const uint4*>(s.rows);
     const uint4* atoms4 = reinterpret_cast<const uint4*>(s.atoms);
     const uint4* V4 = reinterpret_cast<const uint4*>(s.V);
     const uint4* P4 = reinterpret_cast<const uint4*>(s.P0);
     const uint4* S4 = reinterpret_cast<const uint4*>(s.S);
-    for (uint64_t i = ((uint64_t)blockIdx.x * kLanes + threadIdx.x) / 64; i < n; i += waves) {
+    for (uint64_t i = first_wave; i < n; i += waves) {
         const uint4 rec = s.def0[i];
         const uint32_t op = rec.x & 15u, L = rec.y, R = rec.z;
         if (op == kNoRecord) continue;  // uniform over the wave
@@ -1573,6 +1617,33 @@ __global__ __launch_bounds__(kLanes) void k_verify_wave(Store s) {
         }
     }
     wave_count(s, C_DEFERRED, nrec);
+}
+
+__global__ __launch_bounds__(kLanes) void k_verify_wave(Store s) {
+    verify_wave_records(s, ((uint64_t)blockIdx.x * kLanes + threadIdx.x) / 64, (uint64_t)gridDim.x * (kLanes / 64));
+}
+
+// Batched form: blockIdx.y is the problem.
+__global__ __launch_bounds__(kLanes) void k_verify_wave_batch(const Store* stores) {
+    const Store s = stores[blockIdx.y];
+    verify_wave_records(s, ((uint64_t)blockIdx.x * kLanes + threadIdx.x) / 64, (uint64_t)gridDim.x * (kLanes / 64));
+}
+
+// Between batched launches: every problem's deferral list is emptied and its
+// launch snapshot taken (see k_between).
+__global__ void k_between_batch(const Store* stores, uint32_t n) {
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    unsigned long long* ctr = stores[p].ctr;
+    ctr[C_DEF0] = 0;
+    ctr[C_SNAP] = ctr[C_ROWS];
+}
+
+// Copies every problem's counters to out[p * C_NUM + i] (one transfer to the host).
+__global__ void k_gather_ctr(const Store* stores, uint32_t n, unsigned long long* out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * C_NUM) return;
+    out[i] = stores[i / C_NUM].ctr[i % C_NUM];
 }
 
 // Verifies deferred candidates against the entries they met (now visible).
@@ -2056,6 +2127,34 @@ hipError_t launch_generate(const Store& s, const SegTable& t, uint64_t blocks, h
     } else {
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_generate_batch(const Store* d_stores, const BSeg* d_segs, uint32_t nsegs, uint64_t tile0,
+                                 uint64_t tiles, hipStream_t st) {
+    if (tiles == 0) return hipSuccess;
+    if (tiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_generate_wave_batch, dim3((uint32_t)tiles), dim3(kLanes), 0, st, d_stores, d_segs, nsegs,
+                       tile0);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify_batch(const Store* d_stores, uint32_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_verify_wave_batch, dim3(8, n), dim3(kLanes), 0, st, d_stores);
+    return hipGetLastError();
+}
+
+hipError_t launch_between_batch(const Store* d_stores, uint32_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_between_batch, dim3(blocks_for(n, 256)), dim3(256), 0, st, d_stores, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_ctr(const Store* d_stores, uint32_t n, unsigned long long* out, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_ctr, dim3(blocks_for((uint64_t)n * C_NUM, 256)), dim3(256), 0, st, d_stores, n,
+                       out);
     return hipGetLastError();
 }
 

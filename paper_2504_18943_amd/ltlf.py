@@ -95,6 +95,9 @@ def load_library() -> ctypes.CDLL:
     L.ltlf_solve.restype = i32
     L.ltlf_solve.argtypes = [vp, ctypes.POINTER(ltlf_spec), ctypes.POINTER(ltlf_costs), u32, u32, vp,
                              ctypes.POINTER(ltlf_result)]
+    L.ltlf_solve_batch.restype = i32
+    L.ltlf_solve_batch.argtypes = [vp, u32, ctypes.POINTER(ltlf_spec), ctypes.POINTER(ltlf_costs),
+                                   ctypes.POINTER(u32), u32, vp, ctypes.POINTER(ltlf_result)]
     L.ltlf_export_level.restype = i32
     L.ltlf_export_level.argtypes = [vp, u32, u64, u64, vp, u64, ctypes.POINTER(u64),
                                     ctypes.POINTER(u64)]
@@ -167,6 +170,22 @@ def ltlf_solve(ctx, n_props, lengths, letters, positive, op_cost, atom_cost, cos
     c = _costs(op_cost, atom_cost)
     return load_library().ltlf_solve(ctx, ctypes.byref(sp), ctypes.byref(c), cost_bound, flags,
                                      ctypes.c_void_p(stream), ctypes.byref(res))
+
+
+def ltlf_solve_batch(ctx, problems, op_cost, atom_cost, bounds, flags, stream, results) -> int:
+    """problems: (n_props, lengths, letters, positive) per problem; results:
+    ctypes array of ltlf_result with the caller's buffers set."""
+    n = len(problems)
+    specs = (ltlf_spec * n)()
+    keep = []
+    for i, (n_props, lengths, letters, positive) in enumerate(problems):
+        sp, k = _spec(n_props, lengths, letters, positive)
+        specs[i] = sp
+        keep.append(k)
+    c = _costs(op_cost, atom_cost)
+    b = (ctypes.c_uint32 * n)(*bounds)
+    return load_library().ltlf_solve_batch(ctx, n, specs, ctypes.byref(c), b, flags, ctypes.c_void_p(stream),
+                                           results)
 
 
 def ltlf_export_level(ctx, cost: int, first: int = 0, count: int = (1 << 64) - 1):
@@ -293,6 +312,36 @@ class Synthesizer:
         self.load(problem)
         return self.run(int(cost_bound if cost_bound is not None else problem.cost_bound),
                         op_cost=op_cost, atom_cost=atom_cost, flags=flags)
+
+    def solve_batch(self, problems, cost_bounds=None, op_cost=UNIT_ALL, atom_cost: int = 1,
+                    flags: int = 0) -> List[Result]:
+        """All problems in one ltlf_solve_batch call (see include/ltlf.h)."""
+        bounds = [int(b) for b in (cost_bounds if cost_bounds is not None else
+                                   [p.cost_bound for p in problems])]
+        n = len(problems)
+        results = (ltlf_result * n)()
+        counts = [(ctypes.c_uint64 * (b + 1))() for b in bounds]
+        fbufs = [ctypes.create_string_buffer(8192) for _ in range(n)]
+        for i in range(n):
+            results[i].level_counts = counts[i]
+            results[i].level_counts_len = bounds[i] + 1
+            results[i].formula = ctypes.cast(fbufs[i], ctypes.c_char_p)
+            results[i].formula_cap = len(fbufs[i])
+        st = ltlf_solve_batch(self._ctx, [(p.n_props,) + tuple(p.arrays()) for p in problems], op_cost,
+                              atom_cost, bounds, flags, self._stream(), results)
+        if st != OK:
+            raise LtlfError(st, "ltlf_solve_batch", ltlf_ctx_last_error(self._ctx))
+        out = []
+        for i in range(n):
+            r = results[i]
+            out.append(Result(status=r.status, min_cost=r.min_cost, levels_done=r.levels_done,
+                              overflow_level=r.overflow_level, level_counts=list(counts[i]),
+                              formula=fbufs[i].value.decode(), candidates=r.candidates,
+                              unique_total=r.unique_total, enum_ms=r.enum_ms, deferred=r.deferred,
+                              row_bytes=r.row_bytes, gen_launches=r.gen_launches,
+                              verify_launches=r.verify_launches, gen_ms=r.gen_ms, verify_ms=r.verify_ms,
+                              dead_rows=r.dead_rows))
+        return out
 
     def export_level(self, cost: int, first: int = 0, count: int = (1 << 64) - 1) -> np.ndarray:
         st, out = ltlf_export_level(self._ctx, cost, first, count)

@@ -1,0 +1,113 @@
+"""GPU parity of the batched solve (ltlf_solve_batch) against the CPU oracle
+and against solving each problem alone.
+
+Bar: per problem, status, minimal cost, levels_done and |U_c| of every
+stored level identical to the oracle's (and to the problem solved alone on
+the GPU); the witness separates and costs the minimal cost.
+"""
+from __future__ import annotations
+
+import pytest
+
+import oracle
+import paper_2504_18943_amd as m
+import workload
+from oracle import evaluator as ev
+
+pytestmark = pytest.mark.gpu
+
+# batched-configuration problems whose oracle runs take seconds at bound <= 8
+SUBSET = [0, 1, 2, 3, 5, 6, 8, 9, 11, 13, 14, 15, 16, 19, 20, 22]
+
+
+@pytest.fixture(scope="module")
+def big():
+    s = m.Synthesizer(device=0, workspace_bytes=8 << 30)
+    yield s
+    s.close()
+
+
+def check(r, o, p):
+    assert (r.status, r.min_cost, r.levels_done, r.overflow_level) == \
+        (o.status, o.min_cost, o.levels_done, o.overflow_level), (p.name, r, o)
+    assert r.level_counts[: o.levels_done + 1] == o.level_counts[: o.levels_done + 1], p.name
+    if r.status == m.ltlf.OK:
+        assert ev.separates(r.formula, p.traces, p.positive), (p.name, r.formula)
+        assert ev.cost(r.formula) == r.min_cost, (p.name, r.formula)
+
+
+def test_batch_matches_oracle(big):
+    ps = workload.batched(1, 24)
+    ps = [ps[i] for i in SUBSET]
+    bounds = [min(p.cost_bound, 8) for p in ps]
+    print(f"[batch] {len(ps)} batched-config problems", flush=True)
+    rs = big.solve_batch(ps, bounds)
+    for p, b, r in zip(ps, bounds, rs):
+        check(r, oracle.solve(p, cost_bound=b), p)
+
+
+def test_batch_mixed_widths_exhaustive(big):
+    """One-chunk, 10-chunk and 328-chunk rows in one batch, every level."""
+    ps = [workload.tiny(s) for s in (1, 2, 3, 4)] + [workload.medium(1), workload.large(1)]
+    bounds = [8, 8, 8, 8, 7, 5]
+    print("[batch] mixed widths exhaustive", flush=True)
+    rs = big.solve_batch(ps, bounds, flags=m.FLAG_EXHAUST)
+    for p, b, r in zip(ps, bounds, rs):
+        check(r, oracle.solve(p, cost_bound=b, exhaust=True), p)
+
+
+def test_alone_and_in_the_mix_identical(big):
+    ps = [workload.medium(2), workload.tiny(5), workload.medium(3), workload.tiny(6)]
+    bounds = [p.cost_bound for p in ps]
+    print("[batch] alone vs mix", flush=True)
+    mix = big.solve_batch(ps, bounds)
+    for p, b, r in zip(ps, bounds, mix):
+        a = big.solve(p, cost_bound=b)
+        assert (a.status, a.min_cost, a.levels_done, a.level_counts) == \
+            (r.status, r.min_cost, r.levels_done, r.level_counts), p.name
+        assert ev.separates(r.formula, p.traces, p.positive)
+
+
+def test_batch_row_limit_falls_back_alone(big):
+    """A problem that exceeds the row limit in the batch is solved alone and
+    reports exactly what the oracle reports under that capacity."""
+    p = workload.tiny(3)
+    full = oracle.solve(p, cost_bound=7, exhaust=True)
+    cap = sum(full.level_counts[:5]) + 3
+    ps = [p, workload.tiny(1), workload.tiny(2)]
+    print("[batch] row limit fallback", flush=True)
+    big.set_row_limit(cap)
+    try:
+        rs = big.solve_batch(ps, [7, 7, 7], flags=m.FLAG_EXHAUST)
+    finally:
+        big.set_row_limit(0)
+    for q, r in zip(ps, rs):
+        check(r, oracle.solve(q, cost_bound=7, exhaust=True, max_rows=cap), q)
+    assert rs[0].overflow_level == 5
+
+
+def test_batch_invalid_problem_isolated(big):
+    bad = workload.Problem(n_props=2, traces=[[1], []], positive=[1, 0], cost_bound=4)
+    ps = [workload.tiny(1), bad, workload.tiny(2)]
+    print("[batch] invalid member", flush=True)
+    rs = big.solve_batch(ps, [p.cost_bound for p in ps])
+    assert rs[1].status == m.ltlf.EINVAL
+    for q, r in ((ps[0], rs[0]), (ps[2], rs[2])):
+        check(r, oracle.solve(q), q)
+
+
+def test_batch_weak_hash(big):
+    ps = [workload.medium(2), workload.large(3), workload.tiny(4)]
+    bounds = [5, 4, 5]
+    print("[batch] weak hash", flush=True)
+    rs = big.solve_batch(ps, bounds, flags=m.FLAG_EXHAUST | m.FLAG_WEAK_HASH)
+    for p, b, r in zip(ps, bounds, rs):
+        check(r, oracle.solve(p, cost_bound=b, exhaust=True), p)
+
+
+def test_context_usable_after_batch(big):
+    big.solve_batch([workload.tiny(1), workload.tiny(2)], [8, 8])
+    p = workload.tiny(7)
+    r = big.solve(p, cost_bound=7, flags=m.FLAG_EXHAUST)
+    check(r, oracle.solve(p, cost_bound=7, exhaust=True), p)
+    assert len(big.export_level(3)) == r.level_counts[3]

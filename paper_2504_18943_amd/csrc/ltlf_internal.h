@@ -32,25 +32,29 @@ enum : uint32_t {
 };
 
 // Slots of the device counter block (uint64 each).
+// Device counters (64-bit).  The ones that take atomics all the time (row,
+// deferral and tile counters) each have a 128-byte cache line of their own,
+// and the read-mostly flags share another: a coherent read of a line that is
+// under constant atomic traffic waits behind that traffic.
 enum : uint32_t {
-    C_ROWS = 0,       // rows allocated (may run past capacity on overflow)
-    C_FOUND = 1,      // 1 once a separating CM was seen
-    C_OVERFLOW = 2,   // 1 once a row could not be allocated
-    C_DEF0 = 3,       // records in deferral list 0
-    C_DEF1 = 4,       // records in deferral list 1
-    C_CAND = 5,       // candidates generated
-    C_DEF_OVF = 6,    // a deferral list ran out of room (internal error)
-    C_WIT_OP = 7,     // witness derivation
-    C_WIT_A = 8,
-    C_WIT_B = 9,
-    C_DEFERRED = 10,  // total deferrals (statistics)
-    C_VERIFY = 11,    // verification reads (statistics)
-    C_SNAP = 12,      // row count when the running inserting launch started
-    C_TILE = 13,      // group kernel: tile cursor, kept over the launches of one segment table
-    C_DEAD = 14,      // rows of the level left unused (retired chunk tails)
-    C_NH = 15,        // compaction: holes found
-    C_NM = 16,        // compaction: rows to move
-    C_NUM = 24,
+    C_ROWS = 0,        // rows allocated (may run past capacity on overflow)
+    C_DEF0 = 16,       // records in deferral list 0
+    C_TILE = 32,       // persistent kernels: tile cursor, kept over the launches of one segment table
+    C_DEF1 = 48,       // records in deferral list 1
+    C_CAND = 49,       // candidates generated
+    C_DEF_OVF = 50,    // a deferral list ran out of room (internal error)
+    C_DEFERRED = 51,   // deferred records verified (statistics)
+    C_VERIFY = 52,     // verification reads (statistics)
+    C_DEAD = 53,       // rows of the level left unused (retired chunk tails)
+    C_NH = 54,         // compaction: holes found
+    C_NM = 55,         // compaction: rows to move
+    C_SNAP = 64,       // row count when the running inserting launch started
+    C_OVERFLOW = 65,   // 1 once a row could not be allocated
+    C_FOUND = 66,      // 1 once a separating CM was seen
+    C_WIT_OP = 67,     // witness derivation
+    C_WIT_A = 68,
+    C_WIT_B = 69,
+    C_NUM = 80,
 };
 
 enum : uint32_t { SEG_ATOM = 0, SEG_UNARY = 1, SEG_PAIR = 2 };

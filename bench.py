@@ -15,7 +15,8 @@ witness) on the medium problems of seeds 1..4, the roofline of the dominant
 kernel (generation) from HIP events around its launches, the CPU oracle
 on a bounded sample of the same problem, and the batched configuration
 (256 problems of mixed shape) solved one by one and in one
-ltlf_solve_batch call, with identical results required.
+ltlf_solve_batch call, and a served stream (Poisson arrivals) through the
+request server and one at a time, with identical results required.
 """
 from __future__ import annotations
 
@@ -115,6 +116,82 @@ def batched_compare(synth, count: int):
                       "bound planted+3, master seed 1"}
 
 
+def served_compare(synth, count: int):
+    """Served stream: requests drawn from the batched configuration's shape
+    mix (master seed 2) arrive as a Poisson process at 1.5 x the rate one at
+    a time solving sustains; the request server (continuous batching) and a
+    one-at-a-time FIFO loop face the same arrival times.  Time to formula =
+    completion - arrival (host clock, upload included)."""
+    import numpy as np
+    import torch
+    import workload
+
+    import paper_2504_18943_amd as m
+
+    ps = workload.batched(2, count)
+    synth.solve(ps[0])  # warm-up
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for p in ps:
+        synth.solve(p)
+    torch.cuda.synchronize()
+    solo_rate = count / (time.perf_counter() - a)
+    rate = 1.5 * solo_rate
+    rng = np.random.Generator(np.random.PCG64(7))
+    arrive = np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+    def pct(v, q):
+        v = sorted(v)
+        return v[min(len(v) - 1, int(q * len(v)))]
+
+    # one at a time, first come first served
+    t0 = time.perf_counter()
+    done_solo, res_solo = [], []
+    for i, p in enumerate(ps):
+        now = time.perf_counter() - t0
+        if now < arrive[i]:
+            time.sleep(arrive[i] - now)
+        res_solo.append(synth.solve(p))
+        done_solo.append(time.perf_counter() - t0)
+    ttf_solo = [(d - arr) * 1e3 for d, arr in zip(done_solo, arrive)]
+    span_solo = done_solo[-1]
+    # the request server
+    srv = m.Server(synth, max_resident=min(count, 512))
+    t0 = time.perf_counter()
+    nxt, tickets, done_srv, res_srv = 0, {}, [0.0] * count, [None] * count
+    while len(tickets) or nxt < count:
+        now = time.perf_counter() - t0
+        while nxt < count and arrive[nxt] <= now:
+            tickets[srv.submit(ps[nxt])] = nxt
+            nxt += 1
+        if not tickets:
+            time.sleep(max(0.0, arrive[nxt] - now))
+            continue
+        srv.step()
+        for t in list(tickets):
+            r = srv.poll(t)
+            if r is not None:
+                i = tickets.pop(t)
+                done_srv[i] = time.perf_counter() - t0
+                res_srv[i] = r
+    srv.close()
+    ttf_srv = [(d - arr) * 1e3 for d, arr in zip(done_srv, arrive)]
+    span_srv = max(done_srv)
+    for p, x, y in zip(ps, res_solo, res_srv):
+        assert (x.status, x.min_cost, x.levels_done, x.level_counts) == \
+            (y.status, y.min_cost, y.levels_done, y.level_counts), p.name
+    log(f"[bench] served: one at a time p50 {pct(ttf_solo, 0.5):.1f} ms p99 {pct(ttf_solo, 0.99):.1f} ms, "
+        f"server p50 {pct(ttf_srv, 0.5):.1f} ms p99 {pct(ttf_srv, 0.99):.1f} ms")
+    return {"requests": count, "arrival_rate_per_s": round(rate, 1),
+            "one_at_a_time": {"ttf_ms_p50": round(pct(ttf_solo, 0.5), 2), "ttf_ms_p99": round(pct(ttf_solo, 0.99), 2),
+                              "problems_per_s": round(count / span_solo, 2)},
+            "server": {"ttf_ms_p50": round(pct(ttf_srv, 0.5), 2), "ttf_ms_p99": round(pct(ttf_srv, 0.99), 2),
+                       "problems_per_s": round(count / span_srv, 2)},
+            "results_identical": True,
+            "config": "Poisson arrivals at 1.5x the one-at-a-time rate; shapes of the batched configuration "
+                      "(master seed 2), bound planted+3"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +203,9 @@ def main() -> int:
     ap.add_argument("--cpu-bound", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttf", action="store_true")
+    ap.add_argument("--served", type=int, default=128,
+                    help="requests of the served stream (Poisson arrivals), server vs one at a "
+                         "time (0 = skip)")
     ap.add_argument("--batched", type=int, default=256,
                     help="problems of the batched configuration solved one by one and with "
                          "ltlf_solve_batch (0 = skip)")
@@ -225,6 +305,9 @@ def main() -> int:
     batched = None
     if args.batched > 0:
         batched = batched_compare(synth, args.batched)
+    served = None
+    if args.served > 0:
+        served = served_compare(synth, args.served)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.seed, args.cpu_bound)
     if cpu:
@@ -252,6 +335,7 @@ def main() -> int:
                    "status": last.status_name, "min_cost": last.min_cost},
         "time_to_formula": ttf,
         "batched": batched,
+        "served": served,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -47,6 +47,7 @@ typedef enum {
     LTLF_OK = 0,         /* a separating formula of minimal cost was found */
     LTLF_NOT_FOUND = 1,  /* no separating formula of cost <= bound */
     LTLF_CAPACITY = 2,   /* the store filled before the bound; levels_done is exact */
+    LTLF_PENDING = 3,    /* server: the request has not finished yet */
     LTLF_EINVAL = -1,    /* invalid argument (see each call) */
     LTLF_ENOMEM = -2,    /* device memory could not be obtained */
     LTLF_EDEVICE = -3,   /* a HIP runtime call failed */
@@ -193,32 +194,90 @@ ltlf_status ltlf_solve(ltlf_ctx *ctx, const ltlf_spec *spec, const ltlf_costs *c
 
 /* Solve n independent problems together: the batched form of ltlf_solve
  * (paper, "Program synthesis": the same bottom-up enumeration, run for many
- * specifications at once).  The context's workspace is divided among the
- * problems in proportion to their row width; all problems advance one cost
- * level at a time, with one generation launch (one wavefront per candidate,
- * any row width), one verification launch and one transfer of every
- * problem's counters per level for the whole batch.  A problem leaves the
- * batch when the candidates of its next level might not fit its share (or it
- * overflows the row limit), and is then solved alone, from the start, with
- * the whole workspace; so every result equals that of ltlf_solve on the same
- * problem: status,
- * minimal cost, levels_done and level counts (the witness may be another
- * formula of the same cost).
+ * specifications at once), through the request server's scheduler (see
+ * ltlf_server_*): all problems are submitted at once, with reservations of
+ * the small pool in proportion to their row width, and stepped until every
+ * one has finished.  Every result equals that of ltlf_solve on the same
+ * problem with the server's large region as capacity: status, minimal cost,
+ * levels_done and level counts (the witness may be another formula of the
+ * same cost); identical to ltlf_solve on this context unless the store
+ * overflows.
  *   specs[i], bounds[i], results[i]: problem i; results[i] as for ltlf_run
  *     (level_counts and formula are caller buffers, or NULL).
  *   costs: shared by all problems.  flags: LTLF_FLAG_EXHAUST and
  *     LTLF_FLAG_DEBUG_WEAK_HASH as for ltlf_run (others are ignored).
  * The context's row limit applies to every problem as in ltlf_solve.
- * Statistics in results[i]: enum_ms is the whole batch's time, gen_launches
- * the batch's generation launches.  The context's loaded problem is
- * discarded (call ltlf_load again before ltlf_run).  An invalid spec or
- * bound gives results[i].status = EINVAL without stopping the batch.
- * Returns OK, or EINVAL (null pointers, n == 0, atom_cost == 0), ENOMEM
- * (workspace below 64 MiB per problem), EDEVICE. */
+ * Statistics in results[i]: enum_ms is the whole batch's time.  The
+ * context's loaded problem is discarded (call ltlf_load again before
+ * ltlf_run).  An invalid spec or bound gives results[i].status = EINVAL
+ * without stopping the batch.  Returns OK, or EINVAL (null pointers,
+ * n == 0, atom_cost == 0), ENOMEM (workspace too small), EDEVICE. */
 ltlf_status ltlf_solve_batch(ltlf_ctx *ctx, uint32_t n, const ltlf_spec *specs,
                              const ltlf_costs *costs, const uint32_t *bounds,
                              uint32_t flags, void *hip_stream,
                              ltlf_result *results);
+
+/* ---------------------------------------------------------------- server --
+ * A request loop over one context (continuous batching).  Requests are
+ * submitted at any time and advanced by ltlf_server_step.  The workspace is
+ * split into a small pool (1/32, at least min(half, 256 MiB)) and one
+ * large region.  Requests start in the small pool, each in its own
+ * reservation, and every step moves all of them by one cost level with one
+ * generation launch, one verification launch and one counter transfer (each
+ * at its own level: the batched form of ltlf_solve).  A request whose next
+ * level is large (over 2^20 candidates) or might not fit its reservation is
+ * restarted, from the start, in the large region, which holds one request at
+ * a time and runs one of its levels per step with the single-problem kernels,
+ * while the small pool keeps flowing.  The large region is a request's
+ * capacity: every result equals that of ltlf_solve with a workspace of the
+ * large region's size (status, minimal cost, levels_done, overflow level,
+ * level counts; the witness may be another formula of the same cost), so it
+ * equals ltlf_solve's on this context whenever the store does not overflow;
+ * a request whose fixed regions do not fit the large region is solved with
+ * the whole workspace once nothing else is on the device.  While a server
+ * exists its context serves it
+ * only (no ltlf_load / run / solve / export on the context); the context's
+ * row limit applies to every request. */
+typedef struct ltlf_server ltlf_server;
+
+/* max_resident: problems on the device at once (1..65535).  EINVAL: null
+ * pointers or max_resident out of range; ENOMEM: workspace too small. */
+ltlf_status ltlf_server_create(ltlf_ctx *ctx, uint32_t max_resident, ltlf_server **out);
+
+/* Queue a request; the specification is copied.  reserve_bytes: its
+ * reservation in the small pool (0 = room for ~2^18 rows, at most an eighth
+ * of the pool; at least 16 MiB).  flags: LTLF_FLAG_EXHAUST,
+ * LTLF_FLAG_DEBUG_WEAK_HASH.  *ticket identifies it in poll / cancel.
+ * EINVAL: invalid specification, costs or bound (nothing is queued). */
+ltlf_status ltlf_server_submit(ltlf_server *srv, const ltlf_spec *spec, const ltlf_costs *costs,
+                               uint32_t cost_bound, uint32_t flags, uint64_t reserve_bytes,
+                               uint64_t *ticket);
+
+/* Admit what fits, then advance every request on the device by one level
+ * (or run one waiting whole-workspace request); *n_done (may be NULL)
+ * receives the number of requests that finished in this step.
+ * Synchronises the stream. */
+ltlf_status ltlf_server_step(ltlf_server *srv, void *hip_stream, uint32_t *n_done);
+
+/* Result of a finished request, as ltlf_run fills it (level_counts and
+ * formula are caller buffers, or NULL); the ticket is then released.
+ * Returns the result's status (OK / NOT_FOUND / CAPACITY), PENDING if the
+ * request has not finished, EBUFSZ if the formula buffer is too small
+ * (formula_len says what is needed; the ticket is released), EINVAL for an
+ * unknown ticket. */
+ltlf_status ltlf_server_poll(ltlf_server *srv, uint64_t ticket, ltlf_result *result);
+
+/* Drop a queued or running request (its reservation is freed).  EINVAL:
+ * unknown ticket. */
+ltlf_status ltlf_server_cancel(ltlf_server *srv, uint64_t ticket);
+
+/* Requests waiting, requests on the device, and free bytes of the small
+ * pool (each pointer may be NULL). */
+ltlf_status ltlf_server_load(const ltlf_server *srv, uint32_t *queued, uint32_t *resident,
+                             uint64_t *free_bytes);
+
+/* Destroy a server; unfinished requests are dropped.  NULL is ignored. */
+void ltlf_server_destroy(ltlf_server *srv);
 
 /* Export CMs first .. first+count-1 (clipped to |U_cost|) of U_cost from the
  * last run in the canonical layout: per CM, trace by trace in the caller's

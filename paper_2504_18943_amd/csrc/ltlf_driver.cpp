@@ -10,6 +10,9 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -439,169 +442,53 @@ ltlf_status validate_spec(const ltlf_spec* sp) {
     return LTLF_OK;
 }
 
-}  // namespace
 
-extern "C" {
-
-const char* ltlf_status_str(ltlf_status s) {
-    switch (s) {
-    case LTLF_OK: return "ok";
-    case LTLF_NOT_FOUND: return "no separating formula within the cost bound";
-    case LTLF_CAPACITY: return "store full before the cost bound";
-    case LTLF_EINVAL: return "invalid argument";
-    case LTLF_ENOMEM: return "out of device memory";
-    case LTLF_EDEVICE: return "HIP runtime error";
-    case LTLF_EBUFSZ: return "buffer too small";
-    case LTLF_ESTATE: return "call out of order";
-    }
-    return "unknown status";
-}
-
-ltlf_status ltlf_ctx_create(int device, uint64_t hbm_budget_bytes, ltlf_ctx** out) {
-    if (!out) return LTLF_EINVAL;
-    *out = nullptr;
-    int n = 0;
-    if (hipGetDeviceCount(&n) != hipSuccess) return LTLF_EDEVICE;
-    if (device < 0 || device >= n) return LTLF_EINVAL;
-    if (hipSetDevice(device) != hipSuccess) return LTLF_EDEVICE;
-    ltlf_ctx* c = new (std::nothrow) ltlf_ctx();
-    if (!c) return LTLF_ENOMEM;
-    c->device = device;
-    int lds = 0;
-    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) {
-        delete c;
-        return LTLF_EDEVICE;
-    }
-    c->lds_limit = lds > 1024 ? (uint64_t)lds - 1024 : 0;  // room for static LDS
-    c->budget = hbm_budget_bytes ? std::max<uint64_t>(hbm_budget_bytes, kMinWorkspace) : kDefaultBudget;
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_ctr), 8 * C_NUM, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&c->h_tokens), 4 * (1 + kMaxTokens), hipHostMallocDefault) !=
-            hipSuccess) {
-        if (c->h_ctr) (void)hipHostFree(c->h_ctr);
-        delete c;
-        return LTLF_EDEVICE;
-    }
-    *out = c;
-    return LTLF_OK;
-}
-
-ltlf_status ltlf_ctx_set_workspace(ltlf_ctx* c, void* dev_ptr, uint64_t bytes) {
-    if (!c || !dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255u) || bytes < kMinWorkspace)
-        return LTLF_EINVAL;
-    if (c->own_ws && c->ws) (void)hipFree(c->ws);
-    c->ws = static_cast<char*>(dev_ptr);
-    c->ws_bytes = bytes;
-    c->own_ws = false;
-    c->loaded = false;
-    c->ran = false;
-    return LTLF_OK;
-}
-
-const char* ltlf_ctx_last_error(const ltlf_ctx* c) {
-    if (!c) return "null context";
-    return c->err.c_str();
-}
-
-ltlf_status ltlf_ctx_set_row_limit(ltlf_ctx* c, uint64_t max_rows) {
-    if (!c) return LTLF_EINVAL;
-    c->row_limit = max_rows;
-    return LTLF_OK;
-}
-
-void ltlf_ctx_destroy(ltlf_ctx* c) {
-    if (!c) return;
-    for (ltlf_ctx* sub : c->subs) ltlf_ctx_destroy(sub);
-    c->subs.clear();
-    (void)hipSetDevice(c->device);
-    if (c->h_batch) (void)hipHostFree(c->h_batch);
-    if (c->own_ws && c->ws) (void)hipFree(c->ws);
-    if (c->h_ctr) (void)hipHostFree(c->h_ctr);
-    if (c->h_tokens) (void)hipHostFree(c->h_tokens);
-    delete c;
-}
-
-ltlf_status ltlf_load(ltlf_ctx* c, const ltlf_spec* sp, void* stream) {
-    if (!c) return LTLF_EINVAL;
-    c->err.clear();
-    TRY(validate_spec(sp));
-    TRY_HIP(hipSetDevice(c->device));
-    TRY(ensure_workspace(c));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const uint32_t T = sp->n_traces;
-    std::vector<uint32_t> pos_off(T + 1), seg_off(T + 1);
-    for (uint32_t t = 0; t < T; ++t) {
-        pos_off[t + 1] = pos_off[t] + sp->lengths[t];
-        seg_off[t + 1] = seg_off[t] + sp->lengths[t] + 1;
-    }
-    c->loaded = false;
-    c->ran = false;
-    c->n_props = sp->n_props;
-    c->n_traces = T;
-    c->n_pos = pos_off[T];
-    c->n_bits = seg_off[T];
-    c->Wp = (uint32_t)align_up((c->n_bits + 31) / 32, 4);
-    TRY(plan_memory(c));
-    // canonical bit g (trace t, position k) -> packed bit of that position
-    std::vector<uint32_t> canon(c->n_pos);
-    for (uint32_t t = 0; t < T; ++t)
-        for (uint32_t k = 0; k < sp->lengths[t]; ++k)
-            canon[pos_off[t] + k] = seg_off[t] + (sp->lengths[t] - 1 - k);
-    TRY_HIP(hipMemcpyAsync(c->d_letters, sp->letters, 4 * c->n_pos, hipMemcpyHostToDevice, s));
-    TRY_HIP(hipMemcpyAsync(c->d_lengths, sp->lengths, 4ull * T, hipMemcpyHostToDevice, s));
-    TRY_HIP(hipMemcpyAsync(c->d_pos_off, pos_off.data(), 4ull * (T + 1), hipMemcpyHostToDevice, s));
-    TRY_HIP(hipMemcpyAsync(c->d_seg_off, seg_off.data(), 4ull * (T + 1), hipMemcpyHostToDevice, s));
-    TRY_HIP(hipMemcpyAsync(c->d_positive, sp->positive, T, hipMemcpyHostToDevice, s));
-    TRY_HIP(hipMemcpyAsync(c->d_canon, canon.data(), 4 * c->n_pos, hipMemcpyHostToDevice, s));
-    TRY_HIP(hipStreamSynchronize(s));
-    c->loaded = true;
-    return LTLF_OK;
-}
-
-ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t flags, void* stream,
-                     ltlf_result* res) {
-    if (!c || !k || !res) return LTLF_EINVAL;
-    c->err.clear();
-    if (k->atom_cost == 0 || bound < k->atom_cost || bound > kMaxBound) return LTLF_EINVAL;
-    if (!c->loaded) return LTLF_ESTATE;
-    TRY_HIP(hipSetDevice(c->device));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const bool exhaust = (flags & LTLF_FLAG_EXHAUST) != 0;
-
-    reset_result(res, 4 * c->Wp);
-    const bool profile = (flags & LTLF_FLAG_PROFILE) != 0;
+// One single-problem run, level by level: the level loop of ltlf_run, also
+// used by the scheduler for resident problems whose levels are large (they
+// keep the single-problem kernels and table sizing).
+struct LevelRun {
+    ltlf_ctx* c = nullptr;
+    const ltlf_costs* k = nullptr;
+    uint32_t bound = 0, flags = 0;
+    bool exhaust = false, profile = false;
+    TileShape shape{};
     Profiler prof;
-    prof.c = c;
-    const uint32_t pref = (flags & LTLF_FLAG_KERNEL_WAVE)    ? KERNEL_WAVE
-                          : (flags & LTLF_FLAG_KERNEL_GROUP) ? KERNEL_GROUP
-                          : (flags & LTLF_FLAG_KERNEL_LANE)  ? KERNEL_LANE
-                                                             : KERNEL_AUTO;
-    const TileShape shape = tile_shape(c->Wp, c->lds_limit, pref);
-
-    hipEvent_t e0, e1;
-    TRY_HIP(hipEventCreate(&e0));
-    TRY_HIP(hipEventCreate(&e1));
-    struct EventGuard {
-        hipEvent_t a, b;
-        ~EventGuard() {
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
-        }
-    } guard{e0, e1};
-    TRY_HIP(hipEventRecord(e0, s));
-
-    TRY(begin_run(c, bound, flags, shape.kind, s));
-
-    uint64_t rows = 0;
+    ltlf_result* res = nullptr;
+    uint64_t rows = 0, candidates = 0;
     ltlf_status status = LTLF_NOT_FOUND;
     uint32_t wit_op = 0, wit_a = 0, wit_b = 0;
-    uint64_t candidates = 0;
+    bool stop = false;  // the run ended: a separating level without EXHAUST, or an overflow
 
-    for (uint32_t lev = 1; lev <= bound; ++lev) {
+    ltlf_status begin(ltlf_ctx* ctx, const ltlf_costs* costs, uint32_t cost_bound, uint32_t run_flags,
+                      ltlf_result* result, hipStream_t s) {
+        c = ctx;
+        k = costs;
+        bound = cost_bound;
+        flags = run_flags;
+        exhaust = (flags & LTLF_FLAG_EXHAUST) != 0;
+        profile = (flags & LTLF_FLAG_PROFILE) != 0;
+        res = result;
+        prof.c = c;
+        const uint32_t pref = (flags & LTLF_FLAG_KERNEL_WAVE)    ? KERNEL_WAVE
+                              : (flags & LTLF_FLAG_KERNEL_GROUP) ? KERNEL_GROUP
+                              : (flags & LTLF_FLAG_KERNEL_LANE)  ? KERNEL_LANE
+                                                                 : KERNEL_AUTO;
+        shape = tile_shape(c->Wp, c->lds_limit, pref);
+        rows = 0;
+        candidates = 0;
+        status = LTLF_NOT_FOUND;
+        stop = false;
+        return begin_run(c, bound, flags, shape.kind, s);
+    }
+
+    // Level `lev` (levels are run in order from 1): generation, dedup, check,
+    // close.  Sets `stop` when the run ends at this level.
+    ltlf_status level(uint32_t lev, hipStream_t s) {
         c->lstart[lev] = rows;
         LevelPlan p = plan_level(c, k, lev, shape);
         if (p.segs.empty()) {
             res->levels_done = lev;
-            continue;
+            return LTLF_OK;
         }
         // Size the table for this level from the growth of the previous
         // levels (1.5x margin, never above the candidate bound); the guard
@@ -785,222 +672,414 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
             if (status != LTLF_OK) status = LTLF_CAPACITY;
             res->overflow_level = lev;
             c->lcount[lev] = 0;
-            break;
+            stop = true;
+            return LTLF_OK;
         }
         res->levels_done = lev;
-        if (status == LTLF_OK && !exhaust) break;
+        if (status == LTLF_OK && !exhaust) stop = true;
+        return LTLF_OK;
     }
-    TRY_HIP(hipEventRecord(e1, s));
-    TRY_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
-    res->enum_ms = ms;
-    res->candidates = candidates;
-    res->deferred = c->h_ctr[C_DEFERRED];
-    c->levels_done = res->levels_done;
-    c->ran = true;
-    TRY(finish_result(c, res, status, wit_op, wit_a, wit_b, s));
-    return status;
-}
+};
 
-ltlf_status ltlf_solve(ltlf_ctx* c, const ltlf_spec* sp, const ltlf_costs* k, uint32_t bound,
-                       uint32_t flags, void* stream, ltlf_result* res) {
-    TRY(ltlf_load(c, sp, stream));
-    return ltlf_run(c, k, bound, flags, stream, res);
-}
+// ------------------------------------------------------------ scheduler --
+// Many problems on one device at once (batched solving and the request
+// server).  The workspace holds a small pool and one large region.  Each
+// problem in the small pool owns a reservation used as an ordinary
+// sub-context (row store, derivations, table, deferral lists, counters) and
+// sits at its own cost level; one step advances all of them by one level
+// with one generation launch (the wave kernel's tile body over pieces of
+// every problem's level plan), one verification launch per deferral budget,
+// and one transfer of all counters.  A problem stays in the pool only while
+// its next level is small and every candidate of it could be stored in its
+// reservation; otherwise it is restarted, from the start, in the large
+// region, which holds one problem at a time and runs one level of it per step
+// with the single-problem path (LevelRun: the level loop of ltlf_run).  The
+// large region is a request's capacity: results equal ltlf_solve's with a
+// workspace of that size, hence ltlf_solve's on the same context whenever
+// the run does not overflow it.
+struct Job {
+    uint64_t ticket = 0;
+    uint32_t n_props = 0;
+    std::vector<uint32_t> lengths, letters;
+    std::vector<uint8_t> positive;
+    ltlf_costs costs{};
+    uint32_t bound = 0, flags = 0, wp = 0;
+    ltlf_ctx* sub = nullptr;
+    uint64_t off = 0, bytes = 0, want = 0;
+    bool resident = false, done = false, solo = false;
+    uint32_t lev = 0;
+    uint64_t rows = 0, next_tile = 0, total = 0;
+    LevelPlan plan;
+    ltlf_status status = LTLF_NOT_FOUND;
+    uint32_t wit_op = 0, wit_a = 0, wit_b = 0;
+    ltlf_result res{};
+    std::vector<uint64_t> counts;
+    std::string formula;
+    std::unique_ptr<LevelRun> run;  // set once its levels are large (single-problem kernels)
+    ltlf_spec spec() const {
+        return ltlf_spec{n_props, (uint32_t)lengths.size(), lengths.data(), letters.data(), positive.data()};
+    }
+};
 
-ltlf_status ltlf_solve_batch(ltlf_ctx* c, uint32_t n, const ltlf_spec* specs, const ltlf_costs* k,
-                             const uint32_t* bounds, uint32_t flags, void* stream, ltlf_result* results) {
-    if (!c || !specs || !k || !bounds || !results || n == 0) return LTLF_EINVAL;
-    c->err.clear();
-    if (k->atom_cost == 0) return LTLF_EINVAL;
-    TRY_HIP(hipSetDevice(c->device));
-    TRY(ensure_workspace(c));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const bool exhaust = (flags & LTLF_FLAG_EXHAUST) != 0;
-    c->loaded = false;  // the workspace is re-carved below
-    c->ran = false;
+struct Scheduler {
+    ltlf_ctx* c = nullptr;
+    uint32_t max_resident = 0;
+    uint64_t base = 0, region = 0, small_end = 0;  // small pool [base, small_end), large region after it
+    std::vector<std::pair<uint64_t, uint64_t>> free_;  // small pool: (offset, bytes), sorted by offset
+    std::deque<Job*> queue;       // waiting for the small pool
+    std::deque<Job*> big_queue;   // waiting for the large region
+    std::deque<Job*> solo_queue;  // waiting for the whole workspace
+    std::vector<Job*> resident;   // in the small pool
+    Job* big = nullptr;           // in the large region
+    std::map<uint64_t, Job*> jobs;
+    uint64_t next_ticket = 1;
+    Store* d_stores = nullptr;
+    BSeg* d_segs = nullptr;
+    unsigned long long* d_gather = nullptr;
+    uint32_t launches = 0;
+    static constexpr uint64_t kSegs = 1ull << 16;
+    static constexpr uint64_t kMinSlice = 16ull << 20;
+    static constexpr uint64_t kBigLevel = 1ull << 20;  // candidates of a level that runs on its own
 
-    // problems that can run in the batch, and their row widths
-    std::vector<uint32_t> wp(n, 0);
-    std::vector<char> in_batch(n, 0), solo(n, 0);
-    uint32_t maxb = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        ltlf_result* r = &results[i];
-        reset_result(r, 0);
-        if (validate_spec(&specs[i]) != LTLF_OK || bounds[i] < k->atom_cost || bounds[i] > kMaxBound) {
-            r->status = LTLF_EINVAL;
-            continue;
+    ~Scheduler() {
+        for (auto& kv : jobs) delete kv.second;
+    }
+
+    ltlf_status init(ltlf_ctx* ctx, uint32_t max_res) {
+        c = ctx;
+        max_resident = max_res;
+        TRY(ensure_workspace(c));
+        c->loaded = false;  // the workspace is carved below
+        c->ran = false;
+        const uint64_t off_segs = align_up(sizeof(Store) * (uint64_t)max_res, 256);
+        const uint64_t off_gather = off_segs + align_up(sizeof(BSeg) * kSegs, 256);
+        base = off_gather + align_up(8ull * C_NUM * max_res, 256);
+        if (base + 4 * kMinSlice > c->ws_bytes) return fail(c, LTLF_ENOMEM, "workspace too small for the scheduler");
+        region = c->ws_bytes - base;
+        // the small pool is kept small: a request that overflows the large
+        // region is solved again with the whole workspace, so the large
+        // region should be nearly all of it
+        const uint64_t small = std::max<uint64_t>(region / 32, std::min<uint64_t>(region / 2, 256ull << 20));
+        small_end = base + small / 256 * 256;
+        d_stores = reinterpret_cast<Store*>(c->ws);
+        d_segs = reinterpret_cast<BSeg*>(c->ws + off_segs);
+        d_gather = reinterpret_cast<unsigned long long*>(c->ws + off_gather);
+        free_.assign(1, {base, small_end - base});
+        if (c->h_batch_cap < (uint64_t)C_NUM * max_res) {
+            if (c->h_batch) (void)hipHostFree(c->h_batch);
+            c->h_batch = nullptr;
+            c->h_batch_cap = 0;
+            TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_batch), 8ull * C_NUM * max_res,
+                                  hipHostMallocDefault));
+            c->h_batch_cap = (uint64_t)C_NUM * max_res;
         }
-        uint64_t bits = 0;
-        for (uint32_t t = 0; t < specs[i].n_traces; ++t) bits += specs[i].lengths[t] + 1;
-        wp[i] = (uint32_t)align_up((bits + 31) / 32, 4);
-        r->row_bytes = 4 * wp[i];
-        in_batch[i] = 1;
-        maxb = std::max(maxb, bounds[i]);
+        while (c->subs.size() < (size_t)max_res + 1) {
+            ltlf_ctx* sub = nullptr;
+            TRY(ltlf_ctx_create(c->device, 0, &sub));
+            sub->staging_bytes = 4096;
+            c->subs.push_back(sub);
+        }
+        return LTLF_OK;
+    }
+    uint64_t small_pool() const { return small_end - base; }
+    uint64_t large_region() const { return base + region - small_end; }
+
+    bool alloc(uint64_t bytes, uint64_t& off) {
+        bytes = align_up(bytes, 256);
+        for (size_t i = 0; i < free_.size(); ++i) {
+            if (free_[i].second >= bytes) {
+                off = free_[i].first;
+                free_[i].first += bytes;
+                free_[i].second -= bytes;
+                if (free_[i].second == 0) free_.erase(free_.begin() + (long)i);
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t bytes) {
+        bytes = align_up(bytes, 256);
+        auto it = std::lower_bound(free_.begin(), free_.end(), std::make_pair(off, (uint64_t)0));
+        it = free_.insert(it, {off, bytes});
+        if (it + 1 != free_.end() && it->first + it->second == (it + 1)->first) {
+            it->second += (it + 1)->second;
+            free_.erase(it + 1);
+        }
+        if (it != free_.begin() && (it - 1)->first + (it - 1)->second == it->first) {
+            (it - 1)->second += it->second;
+            free_.erase(it);
+        }
     }
 
-    // control region: per-problem stores, segment pieces, gathered counters
-    constexpr uint64_t kBatchSegs = 1ull << 16;
-    const uint64_t off_segs = align_up(sizeof(Store) * (uint64_t)n, 256);
-    const uint64_t off_gather = off_segs + align_up(sizeof(BSeg) * kBatchSegs, 256);
-    const uint64_t off_slices = off_gather + align_up(8ull * C_NUM * n, 256);
-    if (off_slices + 64ull * n * (1ull << 20) > c->ws_bytes) return fail(c, LTLF_ENOMEM, "workspace too small for the batch");
-    Store* d_stores = reinterpret_cast<Store*>(c->ws);
-    BSeg* d_segs = reinterpret_cast<BSeg*>(c->ws + off_segs);
-    unsigned long long* d_gather = reinterpret_cast<unsigned long long*>(c->ws + off_gather);
-    if (c->h_batch_cap < (uint64_t)C_NUM * n) {
-        if (c->h_batch) (void)hipHostFree(c->h_batch);
-        c->h_batch = nullptr;
-        c->h_batch_cap = 0;
-        TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_batch), 8ull * C_NUM * n, hipHostMallocDefault));
-        c->h_batch_cap = (uint64_t)C_NUM * n;
+    ltlf_status submit(const ltlf_spec* sp, const ltlf_costs* k, uint32_t bound, uint32_t flags, uint64_t want,
+                       uint64_t* ticket) {
+        if (!k || !ticket) return LTLF_EINVAL;
+        TRY(validate_spec(sp));
+        if (k->atom_cost == 0 || bound < k->atom_cost || bound > kMaxBound) return LTLF_EINVAL;
+        Job* j = new (std::nothrow) Job();
+        if (!j) return LTLF_ENOMEM;
+        j->ticket = next_ticket++;
+        j->n_props = sp->n_props;
+        j->lengths.assign(sp->lengths, sp->lengths + sp->n_traces);
+        uint64_t total = 0, bits = 0;
+        for (uint32_t t = 0; t < sp->n_traces; ++t) {
+            total += sp->lengths[t];
+            bits += sp->lengths[t] + 1;
+        }
+        j->letters.assign(sp->letters, sp->letters + total);
+        j->positive.assign(sp->positive, sp->positive + sp->n_traces);
+        j->costs = *k;
+        j->bound = bound;
+        j->flags = flags & (LTLF_FLAG_EXHAUST | LTLF_FLAG_DEBUG_WEAK_HASH);
+        j->wp = (uint32_t)align_up((bits + 31) / 32, 4);
+        // default reservation: room for ~2^18 rows, at most an eighth of the small pool
+        const uint64_t dflt = std::min<uint64_t>((4ull * j->wp + 48) << 18, small_pool() / 8);
+        j->want = std::min<uint64_t>(std::max<uint64_t>(want ? want : dflt, kMinSlice), small_pool());
+        reset_result(&j->res, 4 * j->wp);
+        jobs[j->ticket] = j;
+        queue.push_back(j);
+        *ticket = j->ticket;
+        return LTLF_OK;
     }
 
-    // slices of the rest, proportional to the bytes a stored row costs
-    double wsum = 0;
-    for (uint32_t i = 0; i < n; ++i)
-        if (in_batch[i]) wsum += 4.0 * wp[i] + 48.0;
-    while (c->subs.size() < n) {
-        ltlf_ctx* sub = nullptr;
-        TRY(ltlf_ctx_create(c->device, 0, &sub));
-        sub->staging_bytes = 4096;
-        c->subs.push_back(sub);
+    ltlf_ctx* take_sub() {
+        for (ltlf_ctx* sub : c->subs) {
+            bool used = big && big->sub == sub;
+            for (Job* r : resident) used |= r->sub == sub;
+            if (!used) return sub;
+        }
+        return nullptr;
     }
-    const uint64_t rest = c->ws_bytes - off_slices;
-    uint64_t off = off_slices;
-    std::vector<uint32_t> act;  // batch slot -> problem
-    for (uint32_t i = 0; i < n; ++i) {
-        if (!in_batch[i]) continue;
-        const uint64_t bytes = (uint64_t)((double)rest * (4.0 * wp[i] + 48.0) / wsum) / 256 * 256;
-        ltlf_ctx* sub = c->subs[i];
+
+    // a job ends: its result is kept until polled; its memory is returned
+    ltlf_status finish(Job* j, hipStream_t s) {
+        ltlf_ctx* sub = j->sub;
+        ltlf_result& r = j->res;
+        j->counts.assign(j->bound + 1, 0);
+        uint64_t uniq = 0;
+        for (uint32_t lev = 1; lev <= r.levels_done; ++lev) {
+            j->counts[lev] = sub->lcount[lev];
+            uniq += sub->lcount[lev];
+        }
+        r.unique_total = uniq;
+        r.status = j->status;
+        j->formula.clear();
+        if (j->status == LTLF_OK && render_formula(sub, j->wit_op, j->wit_a, j->wit_b, s, j->formula) != LTLF_OK)
+            return fail(c, LTLF_EDEVICE, sub->err.c_str());
+        r.formula_len = j->formula.size() + 1;
+        j->done = true;
+        drop(j);
+        return LTLF_OK;
+    }
+
+    // off the device (its reservation is returned); progress is discarded
+    void drop(Job* j) {
+        if (j == big) {
+            big->sub->loaded = false;
+            big->sub = nullptr;
+            big->resident = false;
+            big = nullptr;
+        } else if (j->resident) {
+            release(j->off, j->bytes);
+            j->sub->loaded = false;
+            resident.erase(std::find(resident.begin(), resident.end(), j));
+            j->resident = false;
+            j->sub = nullptr;
+        }
+        j->run.reset();
+    }
+    void restart(Job* j, std::deque<Job*>& to) {
+        drop(j);
+        j->lev = 0;
+        j->rows = 0;
+        j->status = LTLF_NOT_FOUND;
+        reset_result(&j->res, 4 * j->wp);
+        to.push_back(j);
+    }
+
+    ltlf_status start_small(Job* j, hipStream_t s, bool& placed) {
+        placed = false;
+        uint64_t off = 0;
+        if (!alloc(j->want, off)) return LTLF_OK;
+        ltlf_ctx* sub = take_sub();
         sub->ws = c->ws + off;
-        sub->ws_bytes = bytes;
+        sub->ws_bytes = align_up(j->want, 256);
         sub->own_ws = false;
         sub->row_limit = c->row_limit;
-        off += bytes;
-        if (bytes < (16ull << 20) || ltlf_load(sub, &specs[i], stream) != LTLF_OK) {
-            solo[i] = 1;  // does not fit a slice: solved alone below
-            continue;
+        const ltlf_spec sp = j->spec();
+        const ltlf_status ls = ltlf_load(sub, &sp, s);
+        if (ls != LTLF_OK) {
+            release(off, sub->ws_bytes);
+            if (ls != LTLF_ENOMEM) return fail(c, ls, sub->err.c_str());
+            placed = true;  // its fixed regions need more than a slice: the large region
+            queue.erase(std::find(queue.begin(), queue.end(), j));
+            big_queue.push_back(j);
+            return LTLF_OK;
         }
-        TRY(begin_run(sub, bounds[i], flags & LTLF_FLAG_DEBUG_WEAK_HASH, KERNEL_WAVE, s));
-        act.push_back(i);
+        j->sub = sub;
+        j->off = off;
+        j->bytes = sub->ws_bytes;
+        j->resident = true;
+        resident.push_back(j);
+        placed = true;
+        queue.erase(std::find(queue.begin(), queue.end(), j));
+        return begin_run(sub, j->bound, j->flags & LTLF_FLAG_DEBUG_WEAK_HASH, KERNEL_WAVE, s);
     }
 
-    struct State {
-        uint64_t rows = 0, next_tile = 0, total = 0;
-        LevelPlan plan;
-        ltlf_status status = LTLF_NOT_FOUND;
-        uint32_t wit_op = 0, wit_a = 0, wit_b = 0;
-        bool done = false;
-    };
-    std::vector<State> st(n);
-    hipEvent_t e0, e1;
-    TRY_HIP(hipEventCreate(&e0));
-    TRY_HIP(hipEventCreate(&e1));
-    struct EventGuard {
-        hipEvent_t a, b;
-        ~EventGuard() {
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
+    ltlf_status start_big(Job* j, hipStream_t s) {
+        ltlf_ctx* sub = take_sub();
+        sub->ws = c->ws + small_end;
+        sub->ws_bytes = large_region() / 256 * 256;
+        sub->own_ws = false;
+        sub->row_limit = c->row_limit;
+        const ltlf_spec sp = j->spec();
+        const ltlf_status ls = ltlf_load(sub, &sp, s);
+        if (ls == LTLF_ENOMEM) {  // not even the large region: the whole workspace
+            solo_queue.push_back(j);
+            return LTLF_OK;
         }
-    } guard{e0, e1};
-    TRY_HIP(hipEventRecord(e0, s));
-    uint32_t gen_launches = 0;
-    std::vector<Store> h_stores;
-    std::vector<BSeg> pieces;
-    std::vector<uint32_t> live;  // batch slot -> problem, problems still running
-    for (uint32_t lev = 1; lev <= maxb; ++lev) {
-        live.clear();
-        for (uint32_t i : act)
-            if (!st[i].done && !solo[i] && lev <= bounds[i]) live.push_back(i);
-        if (live.empty()) break;
-        // plan every problem's level; table room for every candidate being new
-        for (uint32_t i : live) {
-            ltlf_ctx* sub = c->subs[i];
-            State& q = st[i];
-            sub->lstart[lev] = q.rows;
-            q.plan = plan_level(sub, k, lev, tile_shape(sub->Wp, sub->lds_limit, KERNEL_WAVE));
-            q.next_tile = 0;
-            q.total = 0;
-            for (const Seg& g : q.plan.segs) q.total += g.tiles;
-            if (q.total) {
-                // a problem stays in the batch while every candidate of its next
-                // level could be stored in its slice; past that it is solved
-                // alone (from the start, with the whole workspace)
-                if (q.plan.cand_ub > sub->st.cap - q.rows || 2 * (q.rows + q.plan.cand_ub) > sub->table_max) {
-                    solo[i] = 1;
-                    q.total = 0;
+        if (ls != LTLF_OK) return fail(c, ls, sub->err.c_str());
+        j->sub = sub;
+        j->resident = true;
+        big = j;
+        j->run.reset(new LevelRun());
+        j->lev = 0;
+        const ltlf_status st = j->run->begin(sub, &j->costs, j->bound, j->flags, &j->res, s);
+        if (st != LTLF_OK) return fail(c, st, sub->err.c_str());
+        return LTLF_OK;
+    }
+
+    ltlf_status admit(hipStream_t s) {
+        if (!solo_queue.empty()) return LTLF_OK;  // the whole workspace is wanted: drain first
+        for (size_t i = 0; i < queue.size() && resident.size() < max_resident;) {
+            Job* j = queue[i];
+            bool placed = false;
+            TRY(start_small(j, s, placed));
+            if (!placed) ++i;
+        }
+        if (!big && !big_queue.empty()) {
+            Job* j = big_queue.front();
+            big_queue.pop_front();
+            TRY(start_big(j, s));
+        }
+        return LTLF_OK;
+    }
+
+    // the whole workspace, through ltlf_solve
+    ltlf_status run_solo(Job* j, hipStream_t s) {
+        j->counts.assign(j->bound + 1, 0);
+        std::vector<char> fbuf(kMaxTokens * 8);
+        ltlf_result r{};
+        r.level_counts = j->counts.data();
+        r.level_counts_len = j->bound + 1;
+        r.formula = fbuf.data();
+        r.formula_cap = fbuf.size();
+        const ltlf_spec sp = j->spec();
+        const ltlf_status st = ltlf_solve(c, &sp, &j->costs, j->bound, j->flags, s, &r);
+        c->loaded = false;  // the scheduler's carve-up stands
+        if (st < 0) return st;
+        j->res = r;
+        j->formula = st == LTLF_OK ? std::string(fbuf.data()) : std::string();
+        j->res.formula = nullptr;
+        j->res.level_counts = nullptr;
+        j->done = true;
+        return LTLF_OK;
+    }
+
+    ltlf_status step(hipStream_t s, uint32_t* n_done) {
+        uint32_t finished = 0;
+        TRY(admit(s));
+        if (resident.empty() && !big) {
+            if (!solo_queue.empty()) {
+                Job* j = solo_queue.front();
+                solo_queue.pop_front();
+                TRY(run_solo(j, s));
+                ++finished;
+            }
+            if (n_done) *n_done = finished;
+            return LTLF_OK;
+        }
+        // small problems: plan the next level; a large one leaves for the large region
+        std::vector<Job*> live;
+        for (Job* j : std::vector<Job*>(resident)) {
+            ltlf_ctx* sub = j->sub;
+            const uint32_t lev = j->lev + 1;
+            sub->lstart[lev] = j->rows;
+            j->plan = plan_level(sub, &j->costs, lev, tile_shape(sub->Wp, sub->lds_limit, KERNEL_WAVE));
+            j->next_tile = 0;
+            j->total = 0;
+            for (const Seg& g : j->plan.segs) j->total += g.tiles;
+            if (j->total) {
+                if (j->plan.cand_ub > kBigLevel || j->plan.cand_ub > sub->st.cap - j->rows ||
+                    2 * (j->rows + j->plan.cand_ub) > sub->table_max) {
+                    restart(j, big_queue);
                     continue;
                 }
-                if (ensure_table(sub, q.rows, q.plan.cand_ub, s) != LTLF_OK)
+                if (ensure_table(sub, j->rows, j->plan.cand_ub, s) != LTLF_OK)
                     return fail(c, LTLF_EDEVICE, sub->err.c_str());
             }
+            live.push_back(j);
         }
-        {  // drop the problems that left the batch
-            size_t w = 0;
-            for (uint32_t i : live)
-                if (!solo[i]) live[w++] = i;
-            live.resize(w);
-        }
-        if (live.empty()) break;
-        h_stores.resize(live.size());
-        for (size_t j = 0; j < live.size(); ++j) h_stores[j] = c->subs[live[j]]->st;
-        TRY_HIP(hipMemcpyAsync(d_stores, h_stores.data(), sizeof(Store) * live.size(), hipMemcpyHostToDevice, s));
-        // launches: each takes, per problem, the next tiles whose candidates fit
-        // its deferral list
-        for (;;) {
-            pieces.clear();
-            uint64_t first = 0;
-            for (size_t j = 0; j < live.size() && pieces.size() + kMaxSegs < kBatchSegs; ++j) {
-                State& q = st[live[j]];
-                uint64_t budget = c->subs[live[j]]->st.def0_cap;
-                uint64_t seg_first = 0;
-                for (size_t g = 0; g < q.plan.segs.size() && q.next_tile < q.total; ++g) {
-                    const Seg& sg = q.plan.segs[g];
-                    const uint64_t seg_end = seg_first + sg.tiles;
-                    if (q.next_tile < seg_end) {
-                        const uint64_t per = q.plan.cand_per_tile[g];
-                        const uint64_t fit = per ? budget / per : seg_end - q.next_tile;
-                        const uint64_t take = std::min<uint64_t>(fit, seg_end - q.next_tile);
-                        if (take == 0) break;
-                        BSeg b{};
-                        b.problem = (uint32_t)j;
-                        b.first = first;
-                        b.lt0 = q.next_tile - seg_first;
-                        b.seg = sg;
-                        pieces.push_back(b);
-                        first += take;
-                        q.next_tile += take;
-                        budget -= take * per;
+        if (!live.empty()) {
+            std::vector<Store> h_stores(live.size());
+            for (size_t i = 0; i < live.size(); ++i) h_stores[i] = live[i]->sub->st;
+            TRY_HIP(hipMemcpyAsync(d_stores, h_stores.data(), sizeof(Store) * live.size(), hipMemcpyHostToDevice, s));
+            std::vector<BSeg> pieces;
+            for (;;) {
+                pieces.clear();
+                uint64_t first = 0;
+                for (size_t i = 0; i < live.size() && pieces.size() + kMaxSegs < kSegs; ++i) {
+                    Job* j = live[i];
+                    uint64_t budget = j->sub->st.def0_cap;
+                    uint64_t seg_first = 0;
+                    for (size_t g = 0; g < j->plan.segs.size() && j->next_tile < j->total; ++g) {
+                        const Seg& sg = j->plan.segs[g];
+                        const uint64_t seg_end = seg_first + sg.tiles;
+                        if (j->next_tile < seg_end) {
+                            const uint64_t per = j->plan.cand_per_tile[g];
+                            const uint64_t fit = per ? budget / per : seg_end - j->next_tile;
+                            const uint64_t take = std::min<uint64_t>(fit, seg_end - j->next_tile);
+                            if (take == 0) break;
+                            BSeg b{};
+                            b.problem = (uint32_t)i;
+                            b.first = first;
+                            b.lt0 = j->next_tile - seg_first;
+                            b.seg = sg;
+                            pieces.push_back(b);
+                            first += take;
+                            j->next_tile += take;
+                            budget -= take * per;
+                        }
+                        seg_first = seg_end;
                     }
-                    seg_first = seg_end;
                 }
+                if (pieces.empty()) break;
+                TRY_HIP(hipMemcpyAsync(d_segs, pieces.data(), sizeof(BSeg) * pieces.size(), hipMemcpyHostToDevice, s));
+                TRY_HIP(launch_generate_batch(d_stores, d_segs, (uint32_t)pieces.size(), 0, first, s));
+                TRY_HIP(launch_verify_batch(d_stores, (uint32_t)live.size(), s));
+                TRY_HIP(launch_between_batch(d_stores, (uint32_t)live.size(), s));
+                ++launches;
+                TRY_HIP(hipStreamSynchronize(s));  // `pieces` is reused
             }
-            if (pieces.empty()) break;
-            TRY_HIP(hipMemcpyAsync(d_segs, pieces.data(), sizeof(BSeg) * pieces.size(), hipMemcpyHostToDevice, s));
-            TRY_HIP(launch_generate_batch(d_stores, d_segs, (uint32_t)pieces.size(), 0, first, s));
-            TRY_HIP(launch_verify_batch(d_stores, (uint32_t)live.size(), s));
-            TRY_HIP(launch_between_batch(d_stores, (uint32_t)live.size(), s));
-            ++gen_launches;
-            // a host copy of pieces must outlive the asynchronous transfer
+            TRY_HIP(launch_gather_ctr(d_stores, (uint32_t)live.size(), d_gather, s));
+            TRY_HIP(hipMemcpyAsync(c->h_batch, d_gather, 8ull * C_NUM * live.size(), hipMemcpyDeviceToHost, s));
             TRY_HIP(hipStreamSynchronize(s));
         }
-        TRY_HIP(launch_gather_ctr(d_stores, (uint32_t)live.size(), d_gather, s));
-        TRY_HIP(hipMemcpyAsync(c->h_batch, d_gather, 8ull * C_NUM * live.size(), hipMemcpyDeviceToHost, s));
-        TRY_HIP(hipStreamSynchronize(s));
-        // close the level of every problem
-        for (size_t j = 0; j < live.size(); ++j) {
-            const uint32_t i = live[j];
-            ltlf_ctx* sub = c->subs[i];
-            State& q = st[i];
-            ltlf_result* r = &results[i];
-            if (q.total == 0) {
+        for (size_t i = 0; i < live.size(); ++i) {
+            Job* j = live[i];
+            ltlf_ctx* sub = j->sub;
+            ltlf_result* r = &j->res;
+            const uint32_t lev = j->lev + 1;
+            j->lev = lev;
+            if (j->total == 0) {
                 r->levels_done = lev;
-                if (lev == bounds[i]) q.done = true;
+                if (lev == j->bound) {
+                    TRY(finish(j, s));
+                    ++finished;
+                }
                 continue;
             }
-            std::memcpy(sub->h_ctr, c->h_batch + (uint64_t)j * C_NUM, 8ull * C_NUM);
+            std::memcpy(sub->h_ctr, c->h_batch + (uint64_t)i * C_NUM, 8ull * C_NUM);
             // rare: deferred candidates that were new after all (as in ltlf_run)
             const uint64_t n0 = sub->h_ctr[C_DEF1];
             for (uint64_t round = 0; sub->h_ctr[C_DEF1] > 0 && !sub->h_ctr[C_DEF_OVF]; ++round) {
@@ -1018,58 +1097,380 @@ ltlf_status ltlf_solve_batch(ltlf_ctx* c, uint32_t n, const ltlf_spec* specs, co
             const uint64_t now = std::min<uint64_t>(sub->h_ctr[C_ROWS], sub->st.cap);
             r->candidates = sub->h_ctr[C_CAND];
             r->deferred = sub->h_ctr[C_DEFERRED];
-            if (sub->h_ctr[C_DEF_OVF] || sub->h_ctr[C_OVERFLOW] || (sub->row_limit && now > sub->row_limit)) {
-                // the slice (or the row limit) was too small: solved alone with
-                // the whole workspace, which reports what ltlf_solve reports
-                solo[i] = 1;
+            if (sub->h_ctr[C_DEF_OVF] || sub->h_ctr[C_OVERFLOW]) {
+                restart(j, big_queue);
                 continue;
             }
-            sub->lcount[lev] = now - q.rows;
-            q.rows = now;
-            if (sub->h_ctr[C_FOUND] && q.status != LTLF_OK) {
-                q.status = LTLF_OK;
+            if (sub->row_limit && now > sub->row_limit) {  // the large region applies it as ltlf_run does
+                restart(j, big_queue);
+                continue;
+            }
+            sub->lcount[lev] = now - j->rows;
+            j->rows = now;
+            if (sub->h_ctr[C_FOUND] && j->status != LTLF_OK) {
+                j->status = LTLF_OK;
                 r->min_cost = lev;
-                q.wit_op = (uint32_t)sub->h_ctr[C_WIT_OP];
-                q.wit_a = (uint32_t)sub->h_ctr[C_WIT_A];
-                q.wit_b = (uint32_t)sub->h_ctr[C_WIT_B];
+                j->wit_op = (uint32_t)sub->h_ctr[C_WIT_OP];
+                j->wit_a = (uint32_t)sub->h_ctr[C_WIT_A];
+                j->wit_b = (uint32_t)sub->h_ctr[C_WIT_B];
             }
             r->levels_done = lev;
-            if ((q.status == LTLF_OK && !exhaust) || lev == bounds[i]) q.done = true;
+            if ((j->status == LTLF_OK && !(j->flags & LTLF_FLAG_EXHAUST)) || lev == j->bound) {
+                r->gen_launches = launches;
+                r->verify_launches = launches;
+                TRY(finish(j, s));
+                ++finished;
+            }
         }
+        // the large problem: one level with the single-problem kernels
+        if (big) {
+            Job* j = big;
+            LevelRun& r = *j->run;
+            const uint32_t lev = j->lev + 1;
+            TRY(r.level(lev, s));
+            j->lev = lev;
+            j->res.candidates = r.candidates;
+            j->rows = r.rows;
+            j->status = r.status;
+            j->wit_op = r.wit_op;
+            j->wit_a = r.wit_a;
+            j->wit_b = r.wit_b;
+            // an overflow here is final: the large region is the request's capacity
+            if (r.stop || lev == j->bound) {
+                if (j->status != LTLF_OK && j->res.overflow_level) j->status = LTLF_CAPACITY;
+                TRY(finish(j, s));
+                ++finished;
+            }
+        }
+        if (n_done) *n_done = finished;
+        return LTLF_OK;
     }
+
+    // copies a finished job's result into the caller's buffers and forgets it
+    ltlf_status collect(uint64_t ticket, ltlf_result* out) {
+        auto it = jobs.find(ticket);
+        if (it == jobs.end() || !out) return LTLF_EINVAL;
+        Job* j = it->second;
+        if (!j->done) return LTLF_PENDING;
+        uint64_t* lc = out->level_counts;
+        const uint32_t lcl = out->level_counts_len;
+        char* f = out->formula;
+        const uint64_t fc = out->formula_cap;
+        *out = j->res;
+        out->level_counts = lc;
+        out->level_counts_len = lcl;
+        out->formula = f;
+        out->formula_cap = fc;
+        if (lc)
+            for (uint32_t i = 0; i < lcl; ++i) lc[i] = i < j->counts.size() ? j->counts[i] : 0;
+        ltlf_status st = out->status;
+        out->formula_len = j->formula.size() + 1;
+        if (f && fc) {
+            if (fc < j->formula.size() + 1) st = LTLF_EBUFSZ;
+            else std::memcpy(f, j->formula.c_str(), j->formula.size() + 1);
+        }
+        jobs.erase(it);
+        delete j;
+        return st;
+    }
+
+    ltlf_status cancel(uint64_t ticket) {
+        auto it = jobs.find(ticket);
+        if (it == jobs.end()) return LTLF_EINVAL;
+        Job* j = it->second;
+        drop(j);
+        for (std::deque<Job*>* q : {&queue, &big_queue, &solo_queue}) {
+            auto f = std::find(q->begin(), q->end(), j);
+            if (f != q->end()) q->erase(f);
+        }
+        jobs.erase(it);
+        delete j;
+        return LTLF_OK;
+    }
+
+    uint32_t waiting() const { return (uint32_t)(queue.size() + big_queue.size() + solo_queue.size()); }
+    uint32_t on_device() const { return (uint32_t)resident.size() + (big ? 1u : 0u); }
+    bool idle() const { return waiting() == 0 && on_device() == 0; }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* ltlf_status_str(ltlf_status s) {
+    switch (s) {
+    case LTLF_OK: return "ok";
+    case LTLF_NOT_FOUND: return "no separating formula within the cost bound";
+    case LTLF_CAPACITY: return "store full before the cost bound";
+    case LTLF_PENDING: return "request not finished";
+    case LTLF_EINVAL: return "invalid argument";
+    case LTLF_ENOMEM: return "out of device memory";
+    case LTLF_EDEVICE: return "HIP runtime error";
+    case LTLF_EBUFSZ: return "buffer too small";
+    case LTLF_ESTATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+ltlf_status ltlf_ctx_create(int device, uint64_t hbm_budget_bytes, ltlf_ctx** out) {
+    if (!out) return LTLF_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return LTLF_EDEVICE;
+    if (device < 0 || device >= n) return LTLF_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return LTLF_EDEVICE;
+    ltlf_ctx* c = new (std::nothrow) ltlf_ctx();
+    if (!c) return LTLF_ENOMEM;
+    c->device = device;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) {
+        delete c;
+        return LTLF_EDEVICE;
+    }
+    c->lds_limit = lds > 1024 ? (uint64_t)lds - 1024 : 0;  // room for static LDS
+    c->budget = hbm_budget_bytes ? std::max<uint64_t>(hbm_budget_bytes, kMinWorkspace) : kDefaultBudget;
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_ctr), 8 * C_NUM, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->h_tokens), 4 * (1 + kMaxTokens), hipHostMallocDefault) !=
+            hipSuccess) {
+        if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+        delete c;
+        return LTLF_EDEVICE;
+    }
+    *out = c;
+    return LTLF_OK;
+}
+
+ltlf_status ltlf_ctx_set_workspace(ltlf_ctx* c, void* dev_ptr, uint64_t bytes) {
+    if (!c || !dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255u) || bytes < kMinWorkspace)
+        return LTLF_EINVAL;
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    c->ws = static_cast<char*>(dev_ptr);
+    c->ws_bytes = bytes;
+    c->own_ws = false;
+    c->loaded = false;
+    c->ran = false;
+    return LTLF_OK;
+}
+
+const char* ltlf_ctx_last_error(const ltlf_ctx* c) {
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+ltlf_status ltlf_ctx_set_row_limit(ltlf_ctx* c, uint64_t max_rows) {
+    if (!c) return LTLF_EINVAL;
+    c->row_limit = max_rows;
+    return LTLF_OK;
+}
+
+void ltlf_ctx_destroy(ltlf_ctx* c) {
+    if (!c) return;
+    for (ltlf_ctx* sub : c->subs) ltlf_ctx_destroy(sub);
+    c->subs.clear();
+    (void)hipSetDevice(c->device);
+    if (c->h_batch) (void)hipHostFree(c->h_batch);
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+    if (c->h_tokens) (void)hipHostFree(c->h_tokens);
+    delete c;
+}
+
+ltlf_status ltlf_load(ltlf_ctx* c, const ltlf_spec* sp, void* stream) {
+    if (!c) return LTLF_EINVAL;
+    c->err.clear();
+    TRY(validate_spec(sp));
+    TRY_HIP(hipSetDevice(c->device));
+    TRY(ensure_workspace(c));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint32_t T = sp->n_traces;
+    std::vector<uint32_t> pos_off(T + 1), seg_off(T + 1);
+    for (uint32_t t = 0; t < T; ++t) {
+        pos_off[t + 1] = pos_off[t] + sp->lengths[t];
+        seg_off[t + 1] = seg_off[t] + sp->lengths[t] + 1;
+    }
+    c->loaded = false;
+    c->ran = false;
+    c->n_props = sp->n_props;
+    c->n_traces = T;
+    c->n_pos = pos_off[T];
+    c->n_bits = seg_off[T];
+    c->Wp = (uint32_t)align_up((c->n_bits + 31) / 32, 4);
+    TRY(plan_memory(c));
+    // canonical bit g (trace t, position k) -> packed bit of that position
+    std::vector<uint32_t> canon(c->n_pos);
+    for (uint32_t t = 0; t < T; ++t)
+        for (uint32_t k = 0; k < sp->lengths[t]; ++k)
+            canon[pos_off[t] + k] = seg_off[t] + (sp->lengths[t] - 1 - k);
+    TRY_HIP(hipMemcpyAsync(c->d_letters, sp->letters, 4 * c->n_pos, hipMemcpyHostToDevice, s));
+    TRY_HIP(hipMemcpyAsync(c->d_lengths, sp->lengths, 4ull * T, hipMemcpyHostToDevice, s));
+    TRY_HIP(hipMemcpyAsync(c->d_pos_off, pos_off.data(), 4ull * (T + 1), hipMemcpyHostToDevice, s));
+    TRY_HIP(hipMemcpyAsync(c->d_seg_off, seg_off.data(), 4ull * (T + 1), hipMemcpyHostToDevice, s));
+    TRY_HIP(hipMemcpyAsync(c->d_positive, sp->positive, T, hipMemcpyHostToDevice, s));
+    TRY_HIP(hipMemcpyAsync(c->d_canon, canon.data(), 4 * c->n_pos, hipMemcpyHostToDevice, s));
+    TRY_HIP(hipStreamSynchronize(s));
+    c->loaded = true;
+    return LTLF_OK;
+}
+
+ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t flags, void* stream,
+                     ltlf_result* res) {
+    if (!c || !k || !res) return LTLF_EINVAL;
+    c->err.clear();
+    if (k->atom_cost == 0 || bound < k->atom_cost || bound > kMaxBound) return LTLF_EINVAL;
+    if (!c->loaded) return LTLF_ESTATE;
+    TRY_HIP(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    reset_result(res, 4 * c->Wp);
+
+    hipEvent_t e0, e1;
+    TRY_HIP(hipEventCreate(&e0));
+    TRY_HIP(hipEventCreate(&e1));
+    struct EventGuard {
+        hipEvent_t a, b;
+        ~EventGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+    TRY_HIP(hipEventRecord(e0, s));
+    LevelRun run;
+    TRY(run.begin(c, k, bound, flags, res, s));
+    for (uint32_t lev = 1; lev <= bound && !run.stop; ++lev) TRY(run.level(lev, s));
     TRY_HIP(hipEventRecord(e1, s));
     TRY_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
     TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
-    for (uint32_t i : act) {
-        if (solo[i]) continue;
-        ltlf_ctx* sub = c->subs[i];
-        ltlf_result* r = &results[i];
-        r->enum_ms = ms;
-        r->gen_launches = gen_launches;
-        r->verify_launches = gen_launches;
-        sub->levels_done = r->levels_done;
-        const ltlf_status fs = finish_result(sub, r, st[i].status, st[i].wit_op, st[i].wit_a, st[i].wit_b, s);
-        if (fs != LTLF_OK && fs != LTLF_EBUFSZ) return fail(c, fs, sub->err.c_str());
-        sub->loaded = false;  // its slice is the parent's workspace
-    }
-    // problems that did not fit their slice, alone with the whole workspace
+    res->enum_ms = ms;
+    res->candidates = run.candidates;
+    res->deferred = c->h_ctr[C_DEFERRED];
+    c->levels_done = res->levels_done;
+    c->ran = true;
+    TRY(finish_result(c, res, run.status, run.wit_op, run.wit_a, run.wit_b, s));
+    return run.status;
+}
+
+ltlf_status ltlf_solve(ltlf_ctx* c, const ltlf_spec* sp, const ltlf_costs* k, uint32_t bound,
+                       uint32_t flags, void* stream, ltlf_result* res) {
+    TRY(ltlf_load(c, sp, stream));
+    return ltlf_run(c, k, bound, flags, stream, res);
+}
+
+ltlf_status ltlf_solve_batch(ltlf_ctx* c, uint32_t n, const ltlf_spec* specs, const ltlf_costs* k,
+                             const uint32_t* bounds, uint32_t flags, void* stream, ltlf_result* results) {
+    if (!c || !specs || !k || !bounds || !results || n == 0) return LTLF_EINVAL;
+    c->err.clear();
+    if (k->atom_cost == 0) return LTLF_EINVAL;
+    TRY_HIP(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Scheduler sc;
+    TRY(sc.init(c, n));
+    // reservations in proportion to the bytes a stored row costs
+    std::vector<double> w(n, 0.0);
+    double wsum = 0;
     for (uint32_t i = 0; i < n; ++i) {
-        if (!solo[i]) continue;
-        uint64_t* lc = results[i].level_counts;
-        const uint32_t lcl = results[i].level_counts_len;
-        char* f = results[i].formula;
-        const uint64_t fc = results[i].formula_cap;
-        reset_result(&results[i], 4 * wp[i]);
-        const ltlf_status r = ltlf_solve(c, &specs[i], k, bounds[i], flags, stream, &results[i]);
-        results[i].level_counts = lc;
-        results[i].level_counts_len = lcl;
-        results[i].formula = f;
-        results[i].formula_cap = fc;
-        if (r < 0 && r != LTLF_EBUFSZ) return r;
+        uint64_t bits = 0;
+        if (specs[i].lengths)
+            for (uint32_t t = 0; t < specs[i].n_traces; ++t) bits += specs[i].lengths[t] + 1;
+        w[i] = 4.0 * (double)align_up((bits + 31) / 32, 4) + 48.0;
+        wsum += w[i];
+    }
+    hipEvent_t e0, e1;
+    TRY_HIP(hipEventCreate(&e0));
+    TRY_HIP(hipEventCreate(&e1));
+    struct EventGuard {
+        hipEvent_t a, b;
+        ~EventGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+    TRY_HIP(hipEventRecord(e0, s));
+    std::vector<uint64_t> ticket(n, 0);
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t want = (uint64_t)((double)sc.small_pool() * w[i] / wsum);
+        const ltlf_status st = sc.submit(&specs[i], k, bounds[i], flags, want, &ticket[i]);
+        if (st == LTLF_EINVAL) {
+            reset_result(&results[i], 0);
+            results[i].status = LTLF_EINVAL;
+            ticket[i] = 0;
+        } else if (st != LTLF_OK) {
+            return st;
+        }
+    }
+    while (!sc.idle()) TRY(sc.step(s, nullptr));
+    TRY_HIP(hipEventRecord(e1, s));
+    TRY_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!ticket[i]) continue;
+        const ltlf_status st = sc.collect(ticket[i], &results[i]);
+        if (st < 0 && st != LTLF_EBUFSZ) return st;
+        results[i].enum_ms = ms;
     }
     c->loaded = false;
     return LTLF_OK;
+}
+
+struct ltlf_server {
+    Scheduler sched;
+};
+
+ltlf_status ltlf_server_create(ltlf_ctx* c, uint32_t max_resident, ltlf_server** out) {
+    if (!c || !out || max_resident == 0 || max_resident > 65535) return LTLF_EINVAL;
+    *out = nullptr;
+    c->err.clear();
+    TRY_HIP(hipSetDevice(c->device));
+    ltlf_server* sv = new (std::nothrow) ltlf_server();
+    if (!sv) return LTLF_ENOMEM;
+    const ltlf_status st = sv->sched.init(c, max_resident);
+    if (st != LTLF_OK) {
+        delete sv;
+        return st;
+    }
+    *out = sv;
+    return LTLF_OK;
+}
+
+ltlf_status ltlf_server_submit(ltlf_server* sv, const ltlf_spec* sp, const ltlf_costs* k, uint32_t bound,
+                               uint32_t flags, uint64_t reserve_bytes, uint64_t* ticket) {
+    if (!sv || !ticket) return LTLF_EINVAL;
+    return sv->sched.submit(sp, k, bound, flags, reserve_bytes, ticket);
+}
+
+ltlf_status ltlf_server_step(ltlf_server* sv, void* stream, uint32_t* n_done) {
+    if (!sv) return LTLF_EINVAL;
+    ltlf_ctx* c = sv->sched.c;
+    TRY_HIP(hipSetDevice(c->device));
+    return sv->sched.step(static_cast<hipStream_t>(stream), n_done);
+}
+
+ltlf_status ltlf_server_poll(ltlf_server* sv, uint64_t ticket, ltlf_result* res) {
+    if (!sv || !res) return LTLF_EINVAL;
+    return sv->sched.collect(ticket, res);
+}
+
+ltlf_status ltlf_server_cancel(ltlf_server* sv, uint64_t ticket) {
+    if (!sv) return LTLF_EINVAL;
+    return sv->sched.cancel(ticket);
+}
+
+ltlf_status ltlf_server_load(const ltlf_server* sv, uint32_t* queued, uint32_t* resident, uint64_t* free_bytes) {
+    if (!sv) return LTLF_EINVAL;
+    if (queued) *queued = sv->sched.waiting();
+    if (resident) *resident = sv->sched.on_device();
+    if (free_bytes) {
+        uint64_t f = 0;
+        for (const auto& r : sv->sched.free_) f += r.second;
+        *free_bytes = f;
+    }
+    return LTLF_OK;
+}
+
+void ltlf_server_destroy(ltlf_server* sv) {
+    if (!sv) return;
+    if (sv->sched.c) sv->sched.c->loaded = false;
+    delete sv;
 }
 
 ltlf_status ltlf_export_level(ltlf_ctx* c, uint32_t cost, uint64_t first, uint64_t count,

@@ -18,9 +18,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libltlf.so")
 
-OK, NOT_FOUND, CAPACITY = 0, 1, 2
+OK, NOT_FOUND, CAPACITY, PENDING = 0, 1, 2, 3
 EINVAL, ENOMEM, EDEVICE, EBUFSZ, ESTATE = -1, -2, -3, -4, -5
-STATUS_NAMES = {0: "OK", 1: "NOT_FOUND", 2: "CAPACITY", -1: "EINVAL", -2: "ENOMEM",
+STATUS_NAMES = {0: "OK", 1: "NOT_FOUND", 2: "CAPACITY", 3: "PENDING", -1: "EINVAL", -2: "ENOMEM",
                 -3: "EDEVICE", -4: "EBUFSZ", -5: "ESTATE"}
 FLAG_EXHAUST = 0x1
 FLAG_PROFILE = 0x2
@@ -98,6 +98,21 @@ def load_library() -> ctypes.CDLL:
     L.ltlf_solve_batch.restype = i32
     L.ltlf_solve_batch.argtypes = [vp, u32, ctypes.POINTER(ltlf_spec), ctypes.POINTER(ltlf_costs),
                                    ctypes.POINTER(u32), u32, vp, ctypes.POINTER(ltlf_result)]
+    L.ltlf_server_create.restype = i32
+    L.ltlf_server_create.argtypes = [vp, u32, ctypes.POINTER(vp)]
+    L.ltlf_server_submit.restype = i32
+    L.ltlf_server_submit.argtypes = [vp, ctypes.POINTER(ltlf_spec), ctypes.POINTER(ltlf_costs), u32, u32, u64,
+                                     ctypes.POINTER(u64)]
+    L.ltlf_server_step.restype = i32
+    L.ltlf_server_step.argtypes = [vp, vp, ctypes.POINTER(u32)]
+    L.ltlf_server_poll.restype = i32
+    L.ltlf_server_poll.argtypes = [vp, u64, ctypes.POINTER(ltlf_result)]
+    L.ltlf_server_cancel.restype = i32
+    L.ltlf_server_cancel.argtypes = [vp, u64]
+    L.ltlf_server_load.restype = i32
+    L.ltlf_server_load.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u64)]
+    L.ltlf_server_destroy.restype = None
+    L.ltlf_server_destroy.argtypes = [vp]
     L.ltlf_export_level.restype = i32
     L.ltlf_export_level.argtypes = [vp, u32, u64, u64, vp, u64, ctypes.POINTER(u64),
                                     ctypes.POINTER(u64)]
@@ -186,6 +201,46 @@ def ltlf_solve_batch(ctx, problems, op_cost, atom_cost, bounds, flags, stream, r
     b = (ctypes.c_uint32 * n)(*bounds)
     return load_library().ltlf_solve_batch(ctx, n, specs, ctypes.byref(c), b, flags, ctypes.c_void_p(stream),
                                            results)
+
+
+def ltlf_server_create(ctx, max_resident: int):
+    h = ctypes.c_void_p()
+    st = load_library().ltlf_server_create(ctx, max_resident, ctypes.byref(h))
+    return st, h
+
+
+def ltlf_server_submit(srv, n_props, lengths, letters, positive, op_cost, atom_cost, cost_bound, flags,
+                       reserve_bytes: int = 0):
+    sp, keep = _spec(n_props, lengths, letters, positive)
+    c = _costs(op_cost, atom_cost)
+    t = ctypes.c_uint64()
+    st = load_library().ltlf_server_submit(srv, ctypes.byref(sp), ctypes.byref(c), cost_bound, flags,
+                                           reserve_bytes, ctypes.byref(t))
+    return st, t.value
+
+
+def ltlf_server_step(srv, stream: int = 0):
+    n = ctypes.c_uint32()
+    st = load_library().ltlf_server_step(srv, ctypes.c_void_p(stream), ctypes.byref(n))
+    return st, n.value
+
+
+def ltlf_server_poll(srv, ticket: int, res: ltlf_result) -> int:
+    return load_library().ltlf_server_poll(srv, ticket, ctypes.byref(res))
+
+
+def ltlf_server_cancel(srv, ticket: int) -> int:
+    return load_library().ltlf_server_cancel(srv, ticket)
+
+
+def ltlf_server_load(srv):
+    q, r, f = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()
+    st = load_library().ltlf_server_load(srv, ctypes.byref(q), ctypes.byref(r), ctypes.byref(f))
+    return st, q.value, r.value, f.value
+
+
+def ltlf_server_destroy(srv) -> None:
+    load_library().ltlf_server_destroy(srv)
 
 
 def ltlf_export_level(ctx, cost: int, first: int = 0, count: int = (1 << 64) - 1):
@@ -354,3 +409,79 @@ class Synthesizer:
         if st != OK:
             raise LtlfError(st, "ltlf_formula_of")
         return f
+
+
+class Server:
+    """A request loop on a Synthesizer's context (see ltlf_server_* in
+    include/ltlf.h): submit, step, poll.  The Synthesizer must not be used for
+    anything else while the server exists."""
+
+    def __init__(self, synth: "Synthesizer", max_resident: int = 256):
+        self._synth = synth
+        st, self._srv = ltlf_server_create(synth._ctx, max_resident)
+        if st != OK:
+            raise LtlfError(st, "ltlf_server_create", ltlf_ctx_last_error(synth._ctx))
+        self._bounds = {}
+
+    def submit(self, problem, cost_bound: Optional[int] = None, op_cost=UNIT_ALL, atom_cost: int = 1,
+               flags: int = 0, reserve_bytes: int = 0) -> int:
+        b = int(cost_bound if cost_bound is not None else problem.cost_bound)
+        lengths, letters, positive = problem.arrays()
+        st, t = ltlf_server_submit(self._srv, problem.n_props, lengths, letters, positive, op_cost, atom_cost,
+                                   b, flags, reserve_bytes)
+        if st != OK:
+            raise LtlfError(st, "ltlf_server_submit")
+        self._bounds[t] = b
+        return t
+
+    def step(self) -> int:
+        st, n = ltlf_server_step(self._srv, self._synth._stream())
+        if st != OK:
+            raise LtlfError(st, "ltlf_server_step", ltlf_ctx_last_error(self._synth._ctx))
+        return n
+
+    def poll(self, ticket: int) -> Optional[Result]:
+        """The result if the request finished (the ticket is then released), else None."""
+        b = self._bounds.get(ticket, 0)
+        counts = (ctypes.c_uint64 * (b + 1))()
+        fbuf = ctypes.create_string_buffer(8192)
+        res = ltlf_result()
+        res.level_counts = counts
+        res.level_counts_len = b + 1
+        res.formula = ctypes.cast(fbuf, ctypes.c_char_p)
+        res.formula_cap = len(fbuf)
+        st = ltlf_server_poll(self._srv, ticket, res)
+        if st == PENDING:
+            return None
+        if st < 0:
+            raise LtlfError(st, "ltlf_server_poll")
+        del self._bounds[ticket]
+        return Result(status=st, min_cost=res.min_cost, levels_done=res.levels_done,
+                      overflow_level=res.overflow_level, level_counts=list(counts),
+                      formula=fbuf.value.decode(), candidates=res.candidates, unique_total=res.unique_total,
+                      enum_ms=res.enum_ms, deferred=res.deferred, row_bytes=res.row_bytes,
+                      gen_launches=res.gen_launches, verify_launches=res.verify_launches)
+
+    def cancel(self, ticket: int) -> None:
+        st = ltlf_server_cancel(self._srv, ticket)
+        if st != OK:
+            raise LtlfError(st, "ltlf_server_cancel")
+        self._bounds.pop(ticket, None)
+
+    def load(self):
+        """(queued, resident, free workspace bytes)."""
+        st, q, r, f = ltlf_server_load(self._srv)
+        if st != OK:
+            raise LtlfError(st, "ltlf_server_load")
+        return q, r, f
+
+    def close(self) -> None:
+        if getattr(self, "_srv", None):
+            ltlf_server_destroy(self._srv)
+            self._srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,139 @@
+"""GPU tests of the request server (ltlf_server_*): results equal solving
+each request alone (and the oracle), whatever arrives while others run.
+
+Bar: per request, status, minimal cost, levels_done and |U_c| of every
+stored level identical to ltlf_solve on the same problem and to the oracle;
+the witness separates and costs the minimal cost.
+"""
+from __future__ import annotations
+
+import pytest
+
+import oracle
+import paper_2504_18943_amd as m
+import workload
+from oracle import evaluator as ev
+
+pytestmark = pytest.mark.gpu
+
+
+def same(r, a, p):
+    assert (r.status, r.min_cost, r.levels_done, r.overflow_level, r.level_counts) == \
+        (a.status, a.min_cost, a.levels_done, a.overflow_level, a.level_counts), p.name
+    if r.status == m.ltlf.OK:
+        assert ev.separates(r.formula, p.traces, p.positive), (p.name, r.formula)
+        assert ev.cost(r.formula) == r.min_cost, (p.name, r.formula)
+
+
+def drain(srv, tickets, limit=10000):
+    out = {}
+    for _ in range(limit):
+        for t in list(tickets):
+            if t in out:
+                continue
+            r = srv.poll(t)
+            if r is not None:
+                out[t] = r
+        if len(out) == len(tickets):
+            return out
+        srv.step()
+    raise AssertionError("requests did not finish")
+
+
+def test_arrivals_while_running_match_alone_and_oracle():
+    s = m.Synthesizer(device=0, workspace_bytes=4 << 30)
+    ps = [workload.medium(1), workload.tiny(1), workload.medium(2), workload.tiny(2),
+          workload.large(1), workload.tiny(3), workload.medium(3), workload.tiny(4)]
+    bounds = [p.cost_bound for p in ps]
+    bounds[4] = 5  # the large problem: its oracle is cheap to this bound
+    alone = [s.solve(p, cost_bound=b) for p, b in zip(ps, bounds)]
+    srv = m.Server(s, max_resident=8)
+    print("[server] staggered arrivals", flush=True)
+    tickets = [srv.submit(ps[0], bounds[0]), srv.submit(ps[1], bounds[1])]
+    srv.step()
+    tickets += [srv.submit(ps[2], bounds[2]), srv.submit(ps[3], bounds[3])]
+    srv.step()
+    srv.step()
+    tickets += [srv.submit(p, b) for p, b in zip(ps[4:], bounds[4:])]
+    got = drain(srv, tickets)
+    srv.close()
+    for p, b, t, a in zip(ps, bounds, tickets, alone):
+        same(got[t], a, p)
+        o = oracle.solve(p, cost_bound=b)
+        assert (got[t].status, got[t].min_cost, got[t].level_counts[: o.levels_done + 1]) == \
+            (o.status, o.min_cost, o.level_counts[: o.levels_done + 1]), p.name
+    s.close()
+
+
+def test_large_levels_move_to_the_large_region():
+    """A request given the minimum reservation reaches levels over 2^20
+    candidates: it is restarted in the large region and still reports
+    exactly the oracle's levels, while a small request runs beside it."""
+    s = m.Synthesizer(device=0, workspace_bytes=2 << 30)
+    p = workload.medium(1)
+    srv = m.Server(s, max_resident=4)
+    print("[server] large region", flush=True)
+    t = srv.submit(p, 9, flags=m.FLAG_EXHAUST, reserve_bytes=16 << 20)
+    t2 = srv.submit(workload.tiny(5), 8, flags=m.FLAG_EXHAUST)
+    got = drain(srv, [t, t2])
+    srv.close()
+    o = oracle.solve(p, cost_bound=9, exhaust=True)
+    assert (got[t].status, got[t].min_cost, got[t].levels_done) == (o.status, o.min_cost, o.levels_done)
+    assert got[t].level_counts == o.level_counts
+    o2 = oracle.solve(workload.tiny(5), cost_bound=8, exhaust=True)
+    assert got[t2].level_counts == o2.level_counts
+    s.close()
+
+
+def test_overflow_of_the_large_region_is_exact():
+    """A request larger than the large region: its stored levels, minimal
+    cost and the overflow are reported exactly (the oracle's counts for
+    every stored level)."""
+    s = m.Synthesizer(device=0, workspace_bytes=256 << 20)
+    p = workload.medium(1)
+    srv = m.Server(s, max_resident=2)
+    print("[server] overflow of the large region", flush=True)
+    t = srv.submit(p, 11, flags=m.FLAG_EXHAUST)
+    t2 = srv.submit(workload.tiny(6), 7)
+    got = drain(srv, [t, t2])
+    srv.close()
+    r = got[t]
+    assert r.overflow_level > 0 and r.levels_done == r.overflow_level - 1
+    assert r.status == m.ltlf.OK and r.min_cost == 6
+    o = oracle.solve(p, cost_bound=min(r.levels_done, 9), exhaust=True)
+    assert r.level_counts[: o.levels_done + 1] == o.level_counts[: o.levels_done + 1]
+    o2 = oracle.solve(workload.tiny(6), cost_bound=7)
+    assert (got[t2].status, got[t2].min_cost) == (o2.status, o2.min_cost)
+    s.close()
+
+
+def test_cancel_pending_invalid():
+    s = m.Synthesizer(device=0, workspace_bytes=1 << 30)
+    srv = m.Server(s, max_resident=2)
+    print("[server] cancel / pending / invalid", flush=True)
+    ps = [workload.medium(1), workload.tiny(1), workload.tiny(2), workload.tiny(3)]
+    ts = [srv.submit(p, 9 if i == 0 else None, flags=m.FLAG_EXHAUST if i == 0 else 0) for i, p in enumerate(ps)]
+    assert srv.poll(ts[0]) is None  # nothing has run yet
+    srv.cancel(ts[3])  # still queued (two resident at most)
+    srv.step()
+    srv.cancel(ts[0])  # resident
+    with pytest.raises(m.LtlfError) as e:
+        srv.poll(ts[0])
+    assert e.value.status == m.ltlf.EINVAL
+    bad = workload.Problem(n_props=2, traces=[[1], []], positive=[1, 0], cost_bound=4)
+    with pytest.raises(m.LtlfError) as e:
+        srv.submit(bad)
+    assert e.value.status == m.ltlf.EINVAL
+    got = drain(srv, ts[1:3])
+    q, r, free = srv.load()
+    assert (q, r) == (0, 0) and free > 0
+    srv.close()
+    for p, t in zip(ps[1:3], ts[1:3]):
+        o = oracle.solve(p)
+        assert (got[t].status, got[t].min_cost, got[t].level_counts[: o.levels_done + 1]) == \
+            (o.status, o.min_cost, o.level_counts[: o.levels_done + 1])
+    # the context works normally afterwards
+    p = workload.tiny(7)
+    r = s.solve(p, cost_bound=7, flags=m.FLAG_EXHAUST)
+    assert r.level_counts[:8] == oracle.solve(p, cost_bound=7, exhaust=True).level_counts[:8]
+    s.close()

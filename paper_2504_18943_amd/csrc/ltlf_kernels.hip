@@ -284,7 +284,8 @@ __device__ __forceinline__ uint32_t check_vec(const Masks& m, uint32_t w, uint4 
 }
 
 __device__ __forceinline__ void report_found(const Store& s, uint32_t op, uint32_t L, uint32_t R) {
-    if (atomicCAS(&s.ctr[C_FOUND], 0ull, 1ull) == 0ull) {
+    if (__hip_atomic_load(&s.ctr[C_FOUND], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0ull &&
+        atomicCAS(&s.ctr[C_FOUND], 0ull, 1ull) == 0ull) {
         atomicExch(&s.ctr[C_WIT_OP], (unsigned long long)op);
         atomicExch(&s.ctr[C_WIT_A], (unsigned long long)L);
         atomicExch(&s.ctr[C_WIT_B], (unsigned long long)R);
@@ -326,12 +327,17 @@ enum : uint32_t { P_SKIP = 0, P_DUP = 1, P_DEFER = 2, P_WON = 3, P_FULL = 4 };
 // an equal stored row is found (DUP), a matching slot of the running launch is
 // met (DEFER; pos = that slot), or an empty slot is reserved (WON; pos = that
 // slot).  FULL: no free slot in the whole table, or the store has already
-// overflowed (full_store: no more slots are reserved; the caller only checks
-// the candidate).  Rows with index >= snap were allocated by the running
-// launch and are not read.
+// overflowed (full_store: the table is not probed at all and the caller only
+// checks the candidate against the spec).  An overflowed level is never
+// stored, so all it still decides is whether some candidate of the level meets
+// the spec; a duplicate of a row of a cheaper level cannot (that level would
+// have ended the search), and one of a row of this level has the same answer
+// as that row, so skipping the duplicate test changes no outcome.  Rows with
+// index >= snap were allocated by the running launch and are not read.
 template <class Emit>
 __device__ uint32_t probe_reserve(const Store& s, uint64_t h, uint64_t& pos, uint64_t cur0,
                                   uint64_t snap, bool full_store, const Emit& e) {
+    if (full_store) return P_FULL;
     const uint32_t tag = tag_of(h);
     const uint64_t hi = (uint64_t)tag << 32;
     uint64_t cur = cur0;
@@ -339,7 +345,6 @@ __device__ uint32_t probe_reserve(const Store& s, uint64_t h, uint64_t& pos, uin
         if (steps > s.tsize) return P_FULL;
         if (steps) cur = slot_load(&s.table[pos]);
         if (cur == kEmpty) {
-            if (full_store) return P_FULL;
             const uint64_t old = slot_cas(&s.table[pos], kEmpty, hi | kPending);
             if (old == kEmpty) return P_WON;
             cur = old;
@@ -390,13 +395,14 @@ __device__ __forceinline__ void write_defer(const Store& s, unsigned long long d
 template <class Emit>
 __device__ void insert_emit(const Store& s, const Masks& m, uint32_t op, uint32_t L, uint32_t R,
                             uint64_t h, uint64_t pos, uint64_t cur0, uint64_t snap, const Emit& e) {
-    const uint32_t o = probe_reserve(s, h, pos, cur0, snap, store_full(s), e);
+    const bool full = store_full(s);
+    const uint32_t o = probe_reserve(s, h, pos, cur0, snap, full, e);
     if (o == P_WON) {
         write_row(s, m, op, L, R, h, pos, wave_alloc(&s.ctr[C_ROWS]), e);
     } else if (o == P_DEFER) {
         write_defer(s, wave_alloc(&s.ctr[C_DEF0]), op, L, R, pos);
     } else if (o == P_FULL) {
-        atomicExch(&s.ctr[C_OVERFLOW], 1ull);
+        if (!full) atomicExch(&s.ctr[C_OVERFLOW], 1ull);
         emit_check_only(s, m, op, L, R, e);
     }
 }
@@ -599,13 +605,14 @@ struct Cand {
     uint32_t out;
 };
 
-// Hash pass of one candidate: records the hash and issues the first probe,
+// Hash pass of one candidate: records the hash and issues the first probe
+// (none once the store has overflowed),
 // unless the candidate is disabled or its CM equals one of its operands
 // (A, or B if given) -- a stored, cheaper CM, so a sure duplicate.  P_WON
 // here only marks "still to probe".
 template <class Emit>
 __device__ __forceinline__ void cand_begin(const Store& s, Cand& c, bool enabled, bool check_eq,
-                                           const uint4* A, const uint4* B, const Emit& e) {
+                                           bool full_store, const uint4* A, const uint4* B, const Emit& e) {
     c.out = P_SKIP;
     if (!enabled) return;
     Hash hs;
@@ -619,7 +626,7 @@ __device__ __forceinline__ void cand_begin(const Store& s, Cand& c, bool enabled
     if (check_eq && (ea == 0 || eb == 0)) return;
     c.h = hs.fin() & s.hmask;
     c.pos = slot_of(s, c.h);
-    c.cur = slot_load(&s.table[c.pos]);
+    c.cur = full_store ? kEmpty : slot_load(&s.table[c.pos]);
     c.out = P_WON;
 }
 
@@ -633,13 +640,13 @@ template <class Emit>
 __device__ __forceinline__ void cand_finish(const Store& s, const Masks& m, const Cand& c,
                                             uint32_t op, uint32_t L, uint32_t R,
                                             unsigned long long& rb, unsigned long long& db,
-                                            const Emit& e) {
+                                            bool full_store, const Emit& e) {
     if (c.out == P_WON) {
         write_row(s, m, op, L, R, c.h, c.pos, rb++, e);
     } else if (c.out == P_DEFER) {
         write_defer(s, db++, op, L, R, c.pos);
     } else if (c.out == P_FULL) {
-        atomicExch(&s.ctr[C_OVERFLOW], 1ull);
+        if (!full_store) atomicExch(&s.ctr[C_OVERFLOW], 1ull);
         emit_check_only(s, m, op, L, R, e);
     }
 }
@@ -708,7 +715,7 @@ __global__ __launch_bounds__(kLanes) void k_generate_lds(Store s, SegTable t) {
             for (int jj = 0; jj < BATCH; ++jj) {
                 const int j = j0 + jj;
                 const bool en = ok && (g.opmask & bits[j]) && (j == 1 || vop != ops[j]);
-                cand_begin(s, c[jj], en, j != 0, mine, mine, LdsUnaryEmit{mine, sh_v, NQ, ops[j]});
+                cand_begin(s, c[jj], en, j != 0, full_store, mine, mine, LdsUnaryEmit{mine, sh_v, NQ, ops[j]});
                 count += en;
             }
             uint32_t nrow = 0, ndef = 0;
@@ -722,7 +729,7 @@ __global__ __launch_bounds__(kLanes) void k_generate_lds(Store s, SegTable t) {
             wave_alloc2(s, nrow, ndef, rb, db);
 #pragma unroll
             for (int jj = 0; jj < BATCH; ++jj)
-                cand_finish(s, m, c[jj], ops[j0 + jj], vi, 0, rb, db,
+                cand_finish(s, m, c[jj], ops[j0 + jj], vi, 0, rb, db, full_store,
                             LdsUnaryEmit{mine, sh_v, NQ, ops[j0 + jj]});
         }
     } else {
@@ -760,7 +767,7 @@ __global__ __launch_bounds__(kLanes) void k_generate_lds(Store s, SegTable t) {
                     const int j = j0 + jj;
                     const bool en = ok && (g.opmask & bits[j]);
                     const LdsPairEmit e{j == 3 ? mine : arow, j == 3 ? arow : mine, NQ, ops[j]};
-                    cand_begin(s, c[jj], en, true, arow, mine, e);
+                    cand_begin(s, c[jj], en, true, full_store, arow, mine, e);
                     count += en;
                 }
                 uint32_t nrow = 0, ndef = 0;
@@ -777,7 +784,7 @@ __global__ __launch_bounds__(kLanes) void k_generate_lds(Store s, SegTable t) {
 #pragma unroll
                 for (int jj = 0; jj < BATCH; ++jj) {
                     const int j = j0 + jj;
-                    cand_finish(s, m, c[jj], ops[j], j == 3 ? bi : ai, j == 3 ? ai : bi, rb, db,
+                    cand_finish(s, m, c[jj], ops[j], j == 3 ? bi : ai, j == 3 ? ai : bi, rb, db, full_store,
                                 LdsPairEmit{j == 3 ? mine : arow, j == 3 ? arow : mine, NQ, ops[j]});
                 }
             }
@@ -874,9 +881,9 @@ __device__ __forceinline__ void group_insert(const Store& s, WaveAlloc& wa, uint
                                              bool sep, uint4 r0, uint4 r1, uint4 r2, uint4 r3) {
     const uint4* rows4 = reinterpret_cast<const uint4*>(s.rows);
     const uint32_t tag = tag_of(h);
-    uint32_t st = active ? S_PROBE : S_DONE;
+    uint32_t st = active ? (full_store ? S_FULL : S_PROBE) : S_DONE;
     uint64_t pos = 0, cur = 0, steps = 0;
-    if (active) {
+    if (st == S_PROBE) {
         pos = slot_of(s, h);
         cur = slot_load(&s.table[pos]);
     }
@@ -886,13 +893,9 @@ __device__ __forceinline__ void group_insert(const Store& s, WaveAlloc& wa, uint
         if (st == S_PROBE) {
             if (steps++ >= s.tsize) st = S_FULL;
             if (st == S_PROBE && cur == kEmpty) {
-                if (full_store) {
-                    st = S_FULL;
-                } else {
-                    const uint64_t old = slot_cas(&s.table[pos], kEmpty, ((uint64_t)tag << 32) | kPending);
-                    if (old == kEmpty) st = S_WON;
-                    else cur = old;
-                }
+                const uint64_t old = slot_cas(&s.table[pos], kEmpty, ((uint64_t)tag << 32) | kPending);
+                if (old == kEmpty) st = S_WON;
+                else cur = old;
             }
             if (st == S_PROBE) {
                 const uint32_t cidx = (uint32_t)cur;
@@ -953,7 +956,7 @@ __device__ __forceinline__ void group_insert(const Store& s, WaveAlloc& wa, uint
     } else if (st == S_DEFER) {
         write_defer(s, db, op, L, R, pos);
     } else if (st == S_FULL) {
-        atomicExch(&s.ctr[C_OVERFLOW], 1ull);
+        if (!full_store) atomicExch(&s.ctr[C_OVERFLOW], 1ull);
         if (sep) report_found(s, op, L, R);
     }
 }
@@ -1290,9 +1293,9 @@ __device__ __forceinline__ void wave_item(const Store& s, WaveAlloc& wa, bool un
     const bool mine = lane < 4 && (lane == 0 ? act[0] : lane == 1 ? act[1] : lane == 2 ? act[2] : act[3]);
     const uint64_t hh = lane_pick4(lane & 3u, hj[0], hj[1], hj[2], hj[3]);
     const uint32_t tag = tag_of(hh);
-    uint32_t st = mine ? S_PROBE : S_DONE;
+    uint32_t st = mine ? (full_store ? S_FULL : S_PROBE) : S_DONE;
     uint64_t pos = 0, cur = 0, steps = 0;
-    if (mine) {
+    if (st == S_PROBE) {
         pos = slot_of(s, hh);
         cur = slot_load(&s.table[pos]);
     }
@@ -1302,13 +1305,9 @@ __device__ __forceinline__ void wave_item(const Store& s, WaveAlloc& wa, bool un
         if (st == S_PROBE) {
             if (steps++ >= s.tsize) st = S_FULL;
             if (st == S_PROBE && cur == kEmpty) {
-                if (full_store) {
-                    st = S_FULL;
-                } else {
-                    const uint64_t old = slot_cas(&s.table[pos], kEmpty, ((uint64_t)tag << 32) | kPending);
-                    if (old == kEmpty) st = S_WON;
-                    else cur = old;
-                }
+                const uint64_t old = slot_cas(&s.table[pos], kEmpty, ((uint64_t)tag << 32) | kPending);
+                if (old == kEmpty) st = S_WON;
+                else cur = old;
             }
             if (st == S_PROBE) {
                 const uint32_t cidx = (uint32_t)cur;
@@ -1388,7 +1387,7 @@ __device__ __forceinline__ void wave_item(const Store& s, WaveAlloc& wa, bool un
         } else if (st == S_DEFER) {
             write_defer(s, dbase, opj, Lj, Rj, pos);
         } else if (st == S_FULL) {
-            atomicExch(&s.ctr[C_OVERFLOW], 1ull);
+            if (!full_store) atomicExch(&s.ctr[C_OVERFLOW], 1ull);
             if (sepj) report_found(s, opj, Lj, Rj);
         }
     }

@@ -53,6 +53,7 @@ class _Deriv(ctypes.Structure):
 class _Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("min_cost", ctypes.c_uint32),
                 ("levels_done", ctypes.c_uint32), ("overflow_level", ctypes.c_uint32),
+                ("checked_level", ctypes.c_uint32), ("witness_outer", ctypes.c_uint32),
                 ("witness_kind", ctypes.c_uint64), ("witness_id", ctypes.c_uint64),
                 ("witness_der", _Deriv), ("candidates", ctypes.c_uint64),
                 ("seconds", ctypes.c_double)]
@@ -99,6 +100,7 @@ class OracleResult:
     min_cost: int
     levels_done: int
     overflow_level: int
+    checked_level: int
     level_counts: List[int]
     witness: str
     candidates: int
@@ -135,7 +137,10 @@ class Oracle:
 
     def solve(self, problem, op_cost=UNIT_ALL, atom_cost: int = 1,
               cost_bound: Optional[int] = None, max_rows: int = 0,
-              exhaust: bool = False) -> OracleResult:
+              exhaust: bool = False, lookahead: bool = True) -> OracleResult:
+        """lookahead: after a level that overflowed max_rows with no
+        separating candidate, test the next level too (the library's
+        default)."""
         lengths, letters, positive = problem.arrays()
         bound = int(cost_bound if cost_bound is not None else problem.cost_bound)
         oc = np.array(op_cost, dtype=np.uint32)
@@ -143,7 +148,8 @@ class Oracle:
         st = self._L.oracle_solve(self._h, problem.n_props, len(problem.traces),
                                   lengths.ctypes.data, letters.ctypes.data, positive.ctypes.data,
                                   atom_cost, oc.ctypes.data, bound, max_rows,
-                                  1 if exhaust else 0, ctypes.byref(self._res))
+                                  (1 if exhaust else 0) | (2 if lookahead else 0),
+                                  ctypes.byref(self._res))
         counts = [int(self._L.oracle_level_count(self._h, c)) for c in range(bound + 1)] \
             if st >= 0 else []
         buf = ctypes.create_string_buffer(1 << 16)
@@ -151,7 +157,7 @@ class Oracle:
         r = self._res
         return OracleResult(status=int(r.status), min_cost=int(r.min_cost),
                             levels_done=int(r.levels_done), overflow_level=int(r.overflow_level),
-                            level_counts=counts, witness=buf.value.decode(),
+                            checked_level=int(r.checked_level), level_counts=counts, witness=buf.value.decode(),
                             candidates=int(r.candidates), seconds=float(r.seconds), _handle=self)
 
     def export_level(self, c: int) -> np.ndarray:
@@ -175,6 +181,6 @@ class Oracle:
 
 
 def solve(problem, op_cost=UNIT_ALL, atom_cost: int = 1, cost_bound: Optional[int] = None,
-          max_rows: int = 0, exhaust: bool = False) -> OracleResult:
+          max_rows: int = 0, exhaust: bool = False, lookahead: bool = True) -> OracleResult:
     return Oracle().solve(problem, op_cost=op_cost, atom_cost=atom_cost, cost_bound=cost_bound,
-                          max_rows=max_rows, exhaust=exhaust)
+                          max_rows=max_rows, exhaust=exhaust, lookahead=lookahead)

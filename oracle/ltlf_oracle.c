@@ -41,7 +41,10 @@
  *
  * Capacity: when storing one more CM would exceed max_rows, the level is
  * finished check-only (candidates not already known are still tested for
- * separation but not stored) and the search stops after that level.
+ * separation but not stored) and the search stops after that level.  With
+ * the look-ahead flag, the level after it is then checked too, without
+ * storing anything (see lookahead()).  The paper assumes the levels fit;
+ * this capacity behaviour is the library's contract, restated here.
  */
 #define _POSIX_C_SOURCE 199309L
 #include <stdint.h>
@@ -231,9 +234,12 @@ typedef struct {
     uint32_t min_cost;
     uint32_t levels_done;
     uint32_t overflow_level; /* 0 if none */
-    uint64_t witness_kind;   /* 0 none, 1 stored id, 2 unstored candidate */
+    uint32_t checked_level;  /* every candidate of every level <= this was tested */
+    uint32_t witness_outer;  /* unary operator over witness_der (kind 3) */
+    uint64_t witness_kind;   /* 0 none, 1 stored id, 2 unstored candidate,
+                                3 unary operator over an unstored candidate */
     uint64_t witness_id;     /* stored id (kind 1) */
-    orc_deriv witness_der;   /* derivation (kind 2) */
+    orc_deriv witness_der;   /* derivation (kinds 2 and 3) */
     uint64_t candidates;
     double seconds;
 } orc_result;
@@ -256,10 +262,116 @@ static int add_row(orc_ctx *o, const uint64_t *cm, uint64_t h, int op, uint32_t 
 }
 
 /*
+ * Look-ahead past level c, which did not fit the store and has no separating
+ * candidate: level c + 1 is tested without storing it.  Levels below c are
+ * complete.  A candidate of level c + 1 is either
+ *   (a) an operator over stored levels: a unary operator of cost >= 2, or a
+ *       binary operator (each of its operands costs at most c - 1), or
+ *   (b) a unary operator of cost 1 over a formula of cost c.  Level c is not
+ *       stored, so every candidate of level c is generated again from the
+ *       stored levels (atoms, unary and binary operators, as in the main
+ *       loop) and the operator is applied to it.  Candidates of level c that
+ *       equal a cheaper CM give an image equal to a cheaper formula's, which
+ *       does not separate, so testing them all is exact.
+ * Returns 1 with the witness in res if a candidate separates, else 0.
+ */
+static int lookahead(orc_ctx *o, uint32_t c, const uint32_t *kappa, uint32_t atom_cost,
+                     uint64_t *cand, uint64_t *img, orc_result *res) {
+    const uint32_t d = c + 1;
+    /* (a) unary operators of cost >= 2 over stored levels */
+    for (int op = OP_NOT; op <= OP_G; ++op) {
+        uint32_t k = kappa[op];
+        if (k < 2 || k >= d) continue;
+        uint32_t src = d - k;
+        for (uint64_t q = 0; q < o->lcount[src]; ++q) {
+            uint64_t id = o->lstart[src] + q;
+            eval_op(o, op, row(o, id), NULL, cand);
+            o->candidates++;
+            if (separates(o, cand)) {
+                res->witness_kind = 2;
+                res->witness_der = (orc_deriv){(uint8_t)op, (uint32_t)id, 0};
+                return 1;
+            }
+        }
+    }
+    /* (a) binary operators over stored levels */
+    for (int op = OP_AND; op <= OP_U; ++op) {
+        uint32_t k = kappa[op];
+        if (k == 0 || k + 2 > d) continue;
+        uint32_t rest = d - k;
+        for (uint32_t i = 1; i < rest; ++i) {
+            uint32_t j = rest - i;
+            for (uint64_t qa = 0; qa < o->lcount[i]; ++qa) {
+                for (uint64_t qb = 0; qb < o->lcount[j]; ++qb) {
+                    uint64_t ia = o->lstart[i] + qa, ib = o->lstart[j] + qb;
+                    eval_op(o, op, row(o, ia), row(o, ib), cand);
+                    o->candidates++;
+                    if (separates(o, cand)) {
+                        res->witness_kind = 2;
+                        res->witness_der = (orc_deriv){(uint8_t)op, (uint32_t)ia, (uint32_t)ib};
+                        return 1;
+                    }
+                }
+            }
+        }
+    }
+    /* (b) cost-1 unary operators over every candidate of level c */
+#define OUTER(OPC, L, R)                                                              \
+    do {                                                                              \
+        for (int ou = OP_NOT; ou <= OP_G; ++ou) {                                     \
+            if (kappa[ou] != 1) continue;                                             \
+            eval_op(o, ou, cand, NULL, img);                                          \
+            o->candidates++;                                                          \
+            if (separates(o, img)) {                                                  \
+                res->witness_kind = 3;                                                \
+                res->witness_outer = (uint32_t)ou;                                    \
+                res->witness_der = (orc_deriv){(uint8_t)(OPC), (L), (R)};             \
+                return 1;                                                             \
+            }                                                                         \
+        }                                                                             \
+    } while (0)
+    if (c == atom_cost) {
+        for (uint32_t p = 0; p < o->n_props; ++p) {
+            memcpy(cand, o->atom[p], sizeof(uint64_t) * o->nw);
+            OUTER(OP_ATOM, p, 0);
+        }
+    }
+    for (int op = OP_NOT; op <= OP_G; ++op) {
+        uint32_t k = kappa[op];
+        if (k == 0 || k >= c) continue;
+        uint32_t src = c - k;
+        for (uint64_t q = 0; q < o->lcount[src]; ++q) {
+            uint64_t id = o->lstart[src] + q;
+            eval_op(o, op, row(o, id), NULL, cand);
+            OUTER(op, (uint32_t)id, 0);
+        }
+    }
+    for (int op = OP_AND; op <= OP_U; ++op) {
+        uint32_t k = kappa[op];
+        if (k == 0 || k + 2 > c) continue;
+        uint32_t rest = c - k;
+        for (uint32_t i = 1; i < rest; ++i) {
+            uint32_t j = rest - i;
+            for (uint64_t qa = 0; qa < o->lcount[i]; ++qa) {
+                for (uint64_t qb = 0; qb < o->lcount[j]; ++qb) {
+                    uint64_t ia = o->lstart[i] + qa, ib = o->lstart[j] + qb;
+                    eval_op(o, op, row(o, ia), row(o, ib), cand);
+                    OUTER(op, (uint32_t)ia, (uint32_t)ib);
+                }
+            }
+        }
+    }
+#undef OUTER
+    return 0;
+}
+
+/*
  * Solve.  op_cost[0..6] are the costs of not, X, F, G, and, or, U; 0 disables
  * the operator.  max_rows = 0 means unlimited.  flags bit 0 (exhaust): keep
  * enumerating complete levels up to the bound after the first separating
- * level (the reported minimum cost and witness are unchanged).
+ * level (the reported minimum cost and witness are unchanged).  flags bit 1
+ * (look-ahead): after a level that overflowed with no separating candidate,
+ * test the next level too (lookahead()).
  */
 int oracle_solve(orc_ctx *o, uint32_t n_props, uint32_t n_traces, const uint32_t *lengths,
                  const uint32_t *letters, const uint8_t *positive, uint32_t atom_cost,
@@ -394,9 +506,22 @@ int oracle_solve(orc_ctx *o, uint32_t n_props, uint32_t n_traces, const uint32_t
             if (status != ORC_OK) status = ORC_CAPACITY;
             res->levels_done = c - 1;
             res->overflow_level = c;
+            res->checked_level = c;
+            if (status != ORC_OK && (flags & 2u) && c < cost_bound) {
+                uint64_t *img = (uint64_t *)malloc(sizeof(uint64_t) * o->nw);
+                if (!img) { free(cand); return ORC_ENOMEM; }
+                int found = lookahead(o, c, kappa, atom_cost, cand, img, res);
+                free(img);
+                res->checked_level = c + 1;
+                if (found) {
+                    status = ORC_OK;
+                    res->min_cost = c + 1;
+                }
+            }
             break;
         }
         res->levels_done = c;
+        res->checked_level = c;
         if (status == ORC_OK && !(flags & 1u)) break;
     }
     free(cand);
@@ -488,6 +613,7 @@ uint64_t oracle_witness(const orc_ctx *o, const orc_result *res, char *buf, uint
         return 1;
     }
     orc_deriv d = res->witness_kind == 1 ? o->der[res->witness_id] : res->witness_der;
+    if (res->witness_kind == 3) emit(buf, (size_t)cap, &at, tok((int)res->witness_outer));
     print_der(o, d, buf, (size_t)cap, &at);
     if (cap) buf[at < cap ? at : cap - 1] = 0;
     return (uint64_t)at + 1;

@@ -224,10 +224,11 @@ def test_capacity_levels_below_overflow_are_exact(oracle_lib):
     assert r.overflow_level == 5
     assert r.levels_done == 4
     assert r.level_counts[:5] == full.level_counts[:5]
-    if full.min_cost and full.min_cost <= 5:
+    # level 5 is checked without storing it, level 6 by the look-ahead
+    if full.min_cost and full.min_cost <= 6:
         assert r.status == oracle.OK and r.min_cost == full.min_cost
     else:
-        assert r.status == oracle.CAPACITY
+        assert r.status == oracle.CAPACITY and r.checked_level == 6
 
 
 def test_capacity_still_finds_min_cost_in_overflow_level(oracle_lib):
@@ -257,3 +258,61 @@ def test_contradictory_spec_not_found(oracle_lib):
     p = workload.custom(2, [tr, [1]], [tr], 6)
     r = oracle.solve(p)
     assert r.status == oracle.NOT_FOUND and r.levels_done == 6
+
+
+def _kappa(ops):
+    return {k: ops[i] for i, k in enumerate(("!", "X", "F", "G", "&", "|", "U"))}
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"case{c[0]}" for c in CASES])
+def test_lookahead_past_overflow_equals_brute_force(oracle_lib, case):
+    """Overflow forced at every level c in turn: the result must be the
+    brute-force minimum whenever it is at most c + 1 (level c checked
+    without storing, level c + 1 by the look-ahead), else CAPACITY with
+    every candidate up to c + 1 tested."""
+    seed, props, nt, lo, hi, K, ops, ac = case
+    p = workload.random_small(seed, props, nt, lo, hi)
+    full = oracle.solve(p, op_cost=ops, atom_cost=ac, cost_bound=K, exhaust=True)
+    want = brute.min_separating_cost(p.n_props, p.traces, p.positive, K, op_cost=ops, atom_cost=ac)
+    outer_found = 0
+    for c in range(1, K):
+        if full.level_counts[c] == 0 or (want is not None and want < c):
+            continue
+        cap = sum(full.level_counts[1:c]) + full.level_counts[c] - 1
+        if cap == 0:  # 0 means no limit
+            continue
+        r = oracle.solve(p, op_cost=ops, atom_cost=ac, cost_bound=K, max_rows=cap)
+        assert r.overflow_level == c and r.levels_done == c - 1, (c, r)
+        assert r.checked_level == c + 1 or (want == c and r.checked_level == c), (c, r)
+        if want is not None and want <= c + 1:
+            assert r.status == oracle.OK and r.min_cost == want, (c, r)
+            assert ev.separates(r.witness, p.traces, p.positive), r.witness
+            assert ev.cost(r.witness, ac, _kappa(ops)) == want, r.witness
+            outer_found += want == c + 1
+            # without the look-ahead the same run stops at the overflowed level
+            plain = oracle.solve(p, op_cost=ops, atom_cost=ac, cost_bound=K, max_rows=cap, lookahead=False)
+            assert plain.checked_level == c
+            assert plain.status == (oracle.OK if want == c else oracle.CAPACITY)
+        else:
+            assert r.status == oracle.CAPACITY, (c, r)
+    if want is not None and want >= 2 and full.level_counts[want - 1] > 0:
+        assert outer_found == 1
+
+
+def test_lookahead_finds_unary_root_over_unstored_level(oracle_lib):
+    """A minimal formula whose root is a cost-1 unary operator over a formula
+    of the overflowed level (the regenerated-operand path)."""
+    # one positive trace where p0 and p1 never hold together; negatives where
+    # they do at the first position or later: ! F & p0 p1 costs 5
+    p = workload.custom(2, [[1, 2, 1], [2, 0]], [[3, 0], [0, 3], [1, 3]], 6)
+    want = brute.min_separating_cost(p.n_props, p.traces, p.positive, 6)
+    full = oracle.solve(p, cost_bound=6, exhaust=True)
+    assert full.min_cost == want
+    c = want - 1
+    cap = sum(full.level_counts[1:c]) + full.level_counts[c] - 1
+    r = oracle.solve(p, cost_bound=6, max_rows=cap)
+    assert r.status == oracle.OK and r.min_cost == want and r.overflow_level == c
+    assert ev.separates(r.witness, p.traces, p.positive)
+    assert ev.cost(r.witness) == want
+    root, rest = r.witness.split(" ", 1)
+    assert root in ("!", "X", "F", "G") and ev.cost(rest) == c, r.witness

@@ -109,6 +109,15 @@ typedef struct {
                                   (the default for rows over 64 chunks).
                                   Results never depend on the kernel: these
                                   three flags exist for testing and tuning */
+#define LTLF_FLAG_NO_LOOKAHEAD 0x20u /* stop at a level that overflows the store.
+                                  By default, when a level overflows and none
+                                  of its candidates separates, the next level
+                                  is checked too, without storing it: its
+                                  candidates over stored levels directly, and
+                                  the cost-1 unary operators over every
+                                  candidate of the overflowed level, generated
+                                  again.  min_cost is then exact up to
+                                  overflow_level + 1 (checked_level) */
 #define LTLF_FLAG_DEBUG_WEAK_HASH 0x100u /* test hook: keep 6 bits of every hash,
                                   so all candidates share a few slots and one
                                   tag; exercises the verify/defer paths */
@@ -133,7 +142,12 @@ typedef struct {
     uint32_t row_bytes;       /* out: bytes of one stored CM (4 * words) */
     uint32_t gen_launches;    /* out: generation kernel launches */
     uint32_t verify_launches; /* out: verification kernel launches */
-    uint32_t pad;
+    uint32_t checked_level;   /* out: every candidate of every level up to this
+                                 one was checked against the specification, so
+                                 no formula of this cost or less separates
+                                 unless status == OK (then min_cost <= it):
+                                 levels_done, overflow_level, or
+                                 overflow_level + 1 after the look-ahead */
     double enum_ms;           /* out: stream time of the whole run (events) */
     double gen_ms;            /* out: summed generation kernel time (PROFILE) */
     double verify_ms;         /* out: summed verification kernel time (PROFILE) */

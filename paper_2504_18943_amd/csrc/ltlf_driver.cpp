@@ -30,6 +30,7 @@ constexpr uint32_t kMaxBound = 1024;
 constexpr uint32_t kMaxTokens = kMaxBound + 1;
 constexpr uint64_t kStagingBytes = 8ull << 20;
 constexpr uint64_t kMinTableSlots = 1ull << 12;
+constexpr uint64_t kLookaheadTiles = 1ull << 30;  // tiles per look-ahead launch (grid limit)
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 inline uint64_t pow2_ceil(uint64_t x) {
@@ -209,14 +210,18 @@ const char* op_token(uint32_t op) {
 }
 
 // Runs the formula kernel from a root derivation and renders prefix tokens.
+// Bits 8.. of op name a unary operator applied on top (a look-ahead witness).
 ltlf_status render_formula(ltlf_ctx* c, uint32_t op, uint32_t a, uint32_t b, hipStream_t s,
                            std::string& out) {
+    const uint32_t outer = op >> 8;
+    op &= 0xFFu;
     TRY_HIP(launch_formula(c->st.meta, op, a, b, kMaxTokens, c->d_tokens, s));
     TRY_HIP(hipMemcpyAsync(c->h_tokens, c->d_tokens, 4 * (1 + kMaxTokens), hipMemcpyDeviceToHost, s));
     TRY_HIP(hipStreamSynchronize(s));
     const uint32_t n = c->h_tokens[0];
     if (n > kMaxTokens) return fail(c, LTLF_EDEVICE, "witness formula longer than the token buffer");
     out.clear();
+    if (outer) out = std::string(op_token(outer)) + " ";
     for (uint32_t i = 0; i < n; ++i) {
         const uint32_t t = c->h_tokens[1 + i];
         const uint32_t top = t >> 24;
@@ -388,6 +393,7 @@ void reset_result(ltlf_result* res, uint32_t row_bytes) {
     res->min_cost = 0;
     res->levels_done = 0;
     res->overflow_level = 0;
+    res->checked_level = 0;
     res->formula_len = 0;
     res->candidates = 0;
     res->unique_total = 0;
@@ -408,6 +414,7 @@ ltlf_status finish_result(ltlf_ctx* c, ltlf_result* res, ltlf_status status, uin
     uint64_t uniq = 0;
     for (uint32_t lev = 1; lev <= res->levels_done; ++lev) uniq += c->lcount[lev];
     res->unique_total = uniq;
+    res->checked_level = std::max({res->checked_level, res->levels_done, res->overflow_level});
     if (res->level_counts) {
         for (uint32_t i = 0; i < res->level_counts_len; ++i)
             res->level_counts[i] = (i <= res->levels_done && i < c->lcount.size()) ? c->lcount[i] : 0;
@@ -479,6 +486,79 @@ struct LevelRun {
         status = LTLF_NOT_FOUND;
         stop = false;
         return begin_run(c, bound, flags, shape.kind, s);
+    }
+
+    // The level after `lev`, which overflowed with no separating candidate,
+    // checked without storing anything.  Its candidates over stored levels
+    // (binary operators, unary operators of cost >= 2: every operand level is
+    // below lev) run through the generation kernels with the overflow flag
+    // set, so each is only checked; those over level lev (unary operators of
+    // cost 1) through the look-ahead kernel, which generates every candidate
+    // of lev again and checks the operators' images of it.
+    ltlf_status lookahead(uint32_t lev, hipStream_t s) {
+        const uint32_t next = lev + 1;
+        TRY_HIP(launch_set_counter(c->d_ctr, C_OVERFLOW, 1, s));
+        auto launch_groups = [&](const LevelPlan& p, auto&& launch) -> ltlf_status {
+            for (size_t g0 = 0; g0 < p.segs.size(); g0 += kMaxSegs) {
+                const size_t g1 = std::min(p.segs.size(), g0 + kMaxSegs);
+                SegTable t{};
+                t.n = (uint32_t)(g1 - g0);
+                for (size_t q = g0; q < g1; ++q) {
+                    t.seg[q - g0] = p.segs[q];
+                    t.first[q - g0 + 1] = t.first[q - g0] + p.segs[q].tiles;
+                }
+                TRY(launch(t, t.first[t.n]));
+            }
+            return LTLF_OK;
+        };
+        // lcount[lev] is 0 now: the plan of the next level has no operand in lev
+        const LevelPlan p = plan_level(c, k, next, shape);
+        TRY(launch_groups(p, [&](SegTable& t, uint64_t total) -> ltlf_status {
+            if (shape.kind == KERNEL_GROUP || shape.kind == KERNEL_WAVE) {
+                uint64_t blocks = 0;
+                TRY_HIP(generate_blocks(c->st, total, blocks));
+                t.tile_begin = 0;
+                t.tile_end = total;
+                t.def_margin = t.row_margin = 0;
+                t.row_budget = ~0ull;
+                TRY_HIP(launch_set_counter(c->d_ctr, C_TILE, 0, s));
+                TRY_HIP(launch_generate(c->st, t, blocks, s));
+                ++res->gen_launches;
+                return LTLF_OK;
+            }
+            for (uint64_t tile = 0; tile < total; tile += kLookaheadTiles) {
+                t.tile_begin = tile;
+                t.tile_end = std::min<uint64_t>(total, tile + kLookaheadTiles);
+                TRY_HIP(launch_generate(c->st, t, 0, s));
+                ++res->gen_launches;
+            }
+            return LTLF_OK;
+        }));
+        uint32_t omask = 0;
+        for (uint32_t o = 0; o < 4; ++o)
+            if (k->op_cost[o] == 1) omask |= 1u << o;
+        if (omask) {
+            const LevelPlan q = plan_level(c, k, lev, tile_shape(c->Wp, c->lds_limit, KERNEL_WAVE));
+            TRY(launch_groups(q, [&](SegTable& t, uint64_t total) -> ltlf_status {
+                for (uint64_t tile = 0; tile < total; tile += kLookaheadTiles) {
+                    t.tile_begin = tile;
+                    t.tile_end = std::min<uint64_t>(total, tile + kLookaheadTiles);
+                    TRY_HIP(launch_lookahead(c->st, t, omask, s));
+                    ++res->gen_launches;
+                }
+                return LTLF_OK;
+            }));
+        }
+        TRY(read_counters(c, s));
+        res->checked_level = next;
+        if (c->h_ctr[C_FOUND]) {
+            status = LTLF_OK;
+            res->min_cost = next;
+            wit_op = (uint32_t)c->h_ctr[C_WIT_OP];
+            wit_a = (uint32_t)c->h_ctr[C_WIT_A];
+            wit_b = (uint32_t)c->h_ctr[C_WIT_B];
+        }
+        return LTLF_OK;
     }
 
     // Level `lev` (levels are run in order from 1): generation, dedup, check,
@@ -673,6 +753,7 @@ struct LevelRun {
             res->overflow_level = lev;
             c->lcount[lev] = 0;
             stop = true;
+            if (status == LTLF_CAPACITY && lev < bound && !(flags & LTLF_FLAG_NO_LOOKAHEAD)) TRY(lookahead(lev, s));
             return LTLF_OK;
         }
         res->levels_done = lev;
@@ -862,6 +943,7 @@ struct Scheduler {
             uniq += sub->lcount[lev];
         }
         r.unique_total = uniq;
+        r.checked_level = std::max({r.checked_level, r.levels_done, r.overflow_level});
         r.status = j->status;
         j->formula.clear();
         if (j->status == LTLF_OK && render_formula(sub, j->wit_op, j->wit_a, j->wit_b, s, j->formula) != LTLF_OK)

@@ -145,6 +145,11 @@ hipError_t generate_blocks(const Store& s, uint64_t n_tiles, uint64_t& blocks);
 hipError_t launch_generate(const Store& s, const SegTable& t, uint64_t blocks, hipStream_t st);
 hipError_t launch_verify_deferred(const Store& s, hipStream_t st);
 // Batched solving (device arrays of per-problem stores and segments).
+// Look-ahead past an overflowed level: tiles [tile_begin, tile_end) of that
+// level's plan (wave-kernel tile shape), each candidate with the cost-1 unary
+// operators of omask (bits: not, X, F, G) applied and checked; one block per
+// tile.
+hipError_t launch_lookahead(const Store& s, const SegTable& t, uint32_t omask, hipStream_t st);
 hipError_t launch_generate_batch(const Store* d_stores, const BSeg* d_segs, uint32_t nsegs, uint64_t tile0,
                                  uint64_t tiles, hipStream_t st);
 hipError_t launch_verify_batch(const Store* d_stores, uint32_t n, hipStream_t st);

@@ -1393,22 +1393,19 @@ __device__ __forceinline__ void wave_item(const Store& s, WaveAlloc& wa, bool un
     }
 }
 
-// One tile of the wave kernel (every thread of the block calls it): atoms,
-// unary operands or pairs of segment g, rows and records taken per wave with
-// `chunk`-sized allocations.  Returns the candidates counted by this thread.
-__device__ __forceinline__ uint32_t wave_tile(const Store& s, const Seg& g, uint64_t lt, WaveAlloc& wa,
-                                              uint64_t snap, bool full_store, uint32_t chunk) {
+// Work items of one wave-kernel tile of a unary or pair segment g (atoms are
+// the caller's): item(unary, A, B, en, op, L, R) runs on every lane of the
+// wave that owns the item, with the item's operand rows and its four
+// candidates (enabled, operator, left, right).  Returns the candidates
+// counted by this thread.
+template <class Item>
+__device__ __forceinline__ uint32_t wave_items(const Store& s, const Seg& g, uint64_t lt, Item&& item) {
     const uint32_t NQ = s.Wp / 4;
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid / 64;
     const uint4* rows4 = reinterpret_cast<const uint4*>(s.rows);
     uint32_t count = 0;
-    if (g.kind == SEG_ATOM) {
-        if (tid < g.nb) {
-            process(s, OP_ATOM, tid, 0, snap);
-            ++count;
-        }
-    } else if (g.kind == SEG_UNARY) {
+    if (g.kind == SEG_UNARY) {
         for (uint32_t iv = wave; iv < kWU; iv += kLanes / 64) {
             const uint64_t vl = lt * kWU + iv;
             if (vl >= g.nb) break;  // uniform over the wave
@@ -1419,7 +1416,7 @@ __device__ __forceinline__ uint32_t wave_tile(const Store& s, const Seg& g, uint
                                 (g.opmask & M_F) && vop != OP_F, (g.opmask & M_G) && vop != OP_G};
             const uint32_t op[4] = {OP_NOT, OP_X, OP_F, OP_G};
             const uint32_t L[4] = {vi, vi, vi, vi}, R[4] = {0, 0, 0, 0};
-            wave_item(s, wa, true, rows4 + (uint64_t)vi * NQ, nullptr, NQ, snap, full_store, en, op, L, R, chunk);
+            item(true, rows4 + (uint64_t)vi * NQ, (const uint4*)nullptr, en, op, L, R);
             if (tid % 64 == 0) count += (uint32_t)en[0] + en[1] + en[2] + en[3];
         }
     } else {
@@ -1443,12 +1440,31 @@ __device__ __forceinline__ uint32_t wave_tile(const Store& s, const Seg& g, uint
             const bool en[4] = {mA, mO, mU, mV};
             const uint32_t op[4] = {OP_AND, OP_OR, OP_U, OP_U};
             const uint32_t L[4] = {ai, ai, ai, bi}, R[4] = {bi, bi, bi, ai};
-            wave_item(s, wa, false, rows4 + (uint64_t)ai * NQ, rows4 + (uint64_t)bi * NQ, NQ, snap, full_store,
-                      en, op, L, R, chunk);
+            item(false, rows4 + (uint64_t)ai * NQ, rows4 + (uint64_t)bi * NQ, en, op, L, R);
             if (tid % 64 == 0) count += (uint32_t)mA + mO + mU + mV;
         }
     }
     return count;
+}
+
+// One tile of the wave kernel (every thread of the block calls it): atoms,
+// unary operands or pairs of segment g, rows and records taken per wave with
+// `chunk`-sized allocations.  Returns the candidates counted by this thread.
+__device__ __forceinline__ uint32_t wave_tile(const Store& s, const Seg& g, uint64_t lt, WaveAlloc& wa,
+                                              uint64_t snap, bool full_store, uint32_t chunk) {
+    if (g.kind == SEG_ATOM) {
+        if (threadIdx.x < g.nb) {
+            process(s, OP_ATOM, threadIdx.x, 0, snap);
+            return 1;
+        }
+        return 0;
+    }
+    const uint32_t NQ = s.Wp / 4;
+    return wave_items(s, g, lt,
+                      [&](bool unary, const uint4* A, const uint4* B, const bool (&en)[4], const uint32_t (&op)[4],
+                          const uint32_t (&L)[4], const uint32_t (&R)[4]) {
+                          wave_item(s, wa, unary, A, B, NQ, snap, full_store, en, op, L, R, chunk);
+                      });
 }
 
 __global__ __launch_bounds__(kLanes) void k_generate_wave(Store s, SegTable t) {
@@ -1506,6 +1522,96 @@ __global__ __launch_bounds__(kLanes) void k_generate_wave_batch(const Store* sto
     WaveAlloc wa;
     const uint32_t count = wave_tile(s, b.seg, b.lt0 + (tile - b.first), wa, snap, full_store, 1);
     wave_count(s, C_CAND, count);
+}
+
+// ----------------------------------------------------------- look-ahead --
+// The level after an overflowed level c holds candidates whose operand lies
+// in level c: the unary operators of cost 1 (omask bits 0..3: not, X, F, G).
+// Level c is not stored, so every candidate z of level c is generated again
+// from the stored levels below it (level c's tiles, one wave per work item)
+// and each such operator is applied to z in the same pass and checked against
+// the spec.  Nothing is stored or probed: a candidate z whose CM equals a
+// cheaper one has images equal to a cheaper formula's, and every cheaper
+// formula has been checked without success, so checking every z is exact.
+// A witness is z's derivation with the outer operator in bits 8.. of its
+// operator code.
+__device__ __forceinline__ void lookahead_item(const Store& s, bool unary, const uint4* A, const uint4* B,
+                                               uint32_t nq, uint32_t omask, const bool (&en)[4],
+                                               const uint32_t (&op)[4], const uint32_t (&L)[4],
+                                               const uint32_t (&R)[4]) {
+    const uint4* P4 = reinterpret_cast<const uint4*>(s.P0);
+    const uint4* S4 = reinterpret_cast<const uint4*>(s.S);
+    const uint4* V4 = reinterpret_cast<const uint4*>(s.V);
+    // not over not, F over F and G over G give cheaper formulas' CMs
+    uint32_t om[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        om[j] = en[j] ? omask & ~(op[j] == OP_NOT ? 1u : op[j] == OP_F ? 4u : op[j] == OP_G ? 8u : 0u) : 0u;
+    uint32_t cx[4] = {0, 0, 0, 0}, cf[4] = {0, 0, 0, 0}, cg[4] = {0, 0, 0, 0};
+    uint32_t ck[4][4] = {};
+    // lanes past the row read zero operands and masks: their chunks are 0
+    wave_pass(s, unary, A, B, nq, [&](uint32_t q, bool in, uint4, uint4, uint4 r0, uint4 r1, uint4 r2, uint4 r3) {
+        const uint4 V = load_if(in, &V4[q]), P = load_if(in, &P4[q]), S = load_if(in, &S4[q]);
+        const uint4 r[4] = {r0, r1, r2, r3};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint4 z = r[j];
+            if (om[j] & 1u)
+                ck[j][0] |= check_chunk(make_uint4(~z.x & V.x, ~z.y & V.y, ~z.z & V.z, ~z.w & V.w), P, S);
+            if (om[j] & 2u) ck[j][1] |= check_chunk(x_chunk(z, wave_shift_in(z, cx[j]), V), P, S);
+            if (om[j] & 4u) {
+                const uint4 sf = wave_add(z, V, cf[j]);
+                ck[j][2] |= check_chunk(make_uint4(z.x | (V.x & (sf.x ^ z.x ^ V.x)), z.y | (V.y & (sf.y ^ z.y ^ V.y)),
+                                                   z.z | (V.z & (sf.z ^ z.z ^ V.z)), z.w | (V.w & (sf.w ^ z.w ^ V.w))),
+                                        P, S);
+            }
+            if (om[j] & 8u) {
+                const uint4 x = make_uint4(V.x & ~z.x, V.y & ~z.y, V.z & ~z.z, V.w & ~z.w);
+                const uint4 sg = wave_add(x, V, cg[j]);
+                ck[j][3] |= check_chunk(make_uint4(V.x & ~(x.x | (V.x & (sg.x ^ x.x ^ V.x))),
+                                                   V.y & ~(x.y | (V.y & (sg.y ^ x.y ^ V.y))),
+                                                   V.z & ~(x.z | (V.z & (sg.z ^ x.z ^ V.z))),
+                                                   V.w & ~(x.w | (V.w & (sg.w ^ x.w ^ V.w)))),
+                                        P, S);
+            }
+        }
+    });
+    constexpr uint32_t outer[4] = {OP_NOT, OP_X, OP_F, OP_G};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+            if ((om[j] >> o) & 1u) {
+                const bool sep = __ballot(ck[j][o] != 0) == 0;
+                if (sep && __lane_id() == 0) report_found(s, op[j] | (outer[o] << 8), L[j], R[j]);
+            }
+}
+
+// One block per tile of level c's plan (wave-kernel tiles), tiles
+// [tile_begin, tile_end) of t.
+__global__ __launch_bounds__(kLanes) void k_lookahead_wave(Store s, SegTable t, uint32_t omask) {
+    const uint64_t tile = t.tile_begin + blockIdx.x;
+    if (tile >= t.tile_end) return;
+    uint32_t si = 0;
+    while (si + 1 < t.n && t.first[si + 1] <= tile) ++si;
+    const Seg& g = t.seg[si];
+    const uint32_t NQ = s.Wp / 4;
+    if (g.kind == SEG_ATOM) {  // level c is the atoms' level: z = p
+        const uint4* atoms4 = reinterpret_cast<const uint4*>(s.atoms);
+        for (uint32_t ia = threadIdx.x / 64; ia < g.nb; ia += kLanes / 64) {
+            const bool en[4] = {true, false, false, false};
+            const uint32_t op[4] = {OP_ATOM, OP_ATOM, OP_ATOM, OP_ATOM};
+            const uint32_t L[4] = {ia, 0, 0, 0}, R[4] = {0, 0, 0, 0};
+            const uint4* a = atoms4 + (uint64_t)ia * NQ;
+            lookahead_item(s, false, a, a, NQ, omask, en, op, L, R);  // a & a = a
+        }
+        return;
+    }
+    wave_items(s, g, tile - t.first[si],
+               [&](bool unary, const uint4* A, const uint4* B, const bool (&en)[4], const uint32_t (&op)[4],
+                   const uint32_t (&L)[4], const uint32_t (&R)[4]) {
+                   lookahead_item(s, unary, A, B, NQ, omask, en, op, L, R);
+               });
 }
 
 // Deferred records of wide rows: one wave per record, recomputing the
@@ -2126,6 +2232,14 @@ hipError_t launch_generate(const Store& s, const SegTable& t, uint64_t blocks, h
     } else {
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_lookahead(const Store& s, const SegTable& t, uint32_t omask, hipStream_t st) {
+    const uint64_t n = t.tile_end - t.tile_begin;
+    if (n == 0) return hipSuccess;
+    if (n > 0x7FFFFFFFull || omask == 0 || omask > 15) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_lookahead_wave, dim3((uint32_t)n), dim3(kLanes), 0, st, s, t, omask);
     return hipGetLastError();
 }
 

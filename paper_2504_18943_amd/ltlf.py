@@ -27,6 +27,7 @@ FLAG_PROFILE = 0x2
 FLAG_KERNEL_LANE = 0x4  # one candidate per lane (default where it fits)
 FLAG_KERNEL_GROUP = 0x8  # one candidate per lane group (rows of 2..64 chunks)
 FLAG_KERNEL_WAVE = 0x10  # one candidate per wavefront (any row width)
+FLAG_NO_LOOKAHEAD = 0x20  # stop at an overflowed level (no check of the next one)
 FLAG_WEAK_HASH = 0x100  # test hook: 6-bit hashes, every probe meets an equal tag
 
 OP_NAMES = ("!", "X", "F", "G", "&", "|", "U")  # index = ltlf_op
@@ -59,7 +60,7 @@ class ltlf_result(ctypes.Structure):
                 ("formula_len", ctypes.c_uint64), ("candidates", ctypes.c_uint64),
                 ("unique_total", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
                 ("row_bytes", ctypes.c_uint32), ("gen_launches", ctypes.c_uint32),
-                ("verify_launches", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("verify_launches", ctypes.c_uint32), ("checked_level", ctypes.c_uint32),
                 ("enum_ms", ctypes.c_double), ("gen_ms", ctypes.c_double),
                 ("verify_ms", ctypes.c_double), ("dead_rows", ctypes.c_uint64)]
 
@@ -286,6 +287,7 @@ class Result:
     gen_ms: float = 0.0
     verify_ms: float = 0.0
     dead_rows: int = 0
+    checked_level: int = 0  # no formula of this cost or less separates unless status is OK
 
     @property
     def status_name(self) -> str:
@@ -360,7 +362,7 @@ class Synthesizer:
                       unique_total=res.unique_total, enum_ms=res.enum_ms, deferred=res.deferred,
                       row_bytes=res.row_bytes, gen_launches=res.gen_launches,
                       verify_launches=res.verify_launches, gen_ms=res.gen_ms,
-                      verify_ms=res.verify_ms, dead_rows=res.dead_rows)
+                      verify_ms=res.verify_ms, dead_rows=res.dead_rows, checked_level=res.checked_level)
 
     def solve(self, problem, cost_bound: Optional[int] = None, op_cost=UNIT_ALL, atom_cost: int = 1,
               flags: int = 0) -> Result:
@@ -395,7 +397,7 @@ class Synthesizer:
                               unique_total=r.unique_total, enum_ms=r.enum_ms, deferred=r.deferred,
                               row_bytes=r.row_bytes, gen_launches=r.gen_launches,
                               verify_launches=r.verify_launches, gen_ms=r.gen_ms, verify_ms=r.verify_ms,
-                              dead_rows=r.dead_rows))
+                              dead_rows=r.dead_rows, checked_level=r.checked_level))
         return out
 
     def export_level(self, cost: int, first: int = 0, count: int = (1 << 64) - 1) -> np.ndarray:
@@ -460,7 +462,8 @@ class Server:
                       overflow_level=res.overflow_level, level_counts=list(counts),
                       formula=fbuf.value.decode(), candidates=res.candidates, unique_total=res.unique_total,
                       enum_ms=res.enum_ms, deferred=res.deferred, row_bytes=res.row_bytes,
-                      gen_launches=res.gen_launches, verify_launches=res.verify_launches)
+                      gen_launches=res.gen_launches, verify_launches=res.verify_launches,
+                      checked_level=res.checked_level)
 
     def cancel(self, ticket: int) -> None:
         st = ltlf_server_cancel(self._srv, ticket)

@@ -37,9 +37,9 @@ def compare(synth, p, bound, op_cost=oracle.UNIT_ALL, atom_cost=1, exhaust=False
     r = synth.solve(p, cost_bound=bound, op_cost=op_cost, atom_cost=atom_cost, flags=fl)
     synth.set_row_limit(0)
     o = oracle.solve(p, op_cost=op_cost, atom_cost=atom_cost, cost_bound=bound, exhaust=exhaust,
-                     max_rows=row_limit)
-    assert (r.status, r.min_cost, r.levels_done, r.overflow_level) == \
-        (o.status, o.min_cost, o.levels_done, o.overflow_level), (r, o)
+                     max_rows=row_limit, lookahead=not (flags & m.FLAG_NO_LOOKAHEAD))
+    assert (r.status, r.min_cost, r.levels_done, r.overflow_level, r.checked_level) == \
+        (o.status, o.min_cost, o.levels_done, o.overflow_level, o.checked_level), (r, o)
     assert r.level_counts[: o.levels_done + 1] == o.level_counts[: o.levels_done + 1]
     if check_sets:
         for c in range(1, o.levels_done + 1):
@@ -149,6 +149,72 @@ def test_row_limit_check_only_level_finds_min(synth):
     cap = sum(full.level_counts[: full.min_cost]) + 5
     r, o = compare(synth, p, p.cost_bound, row_limit=cap)
     assert r.status == m.ltlf.OK and r.min_cost == full.min_cost
+
+
+LOOKAHEAD_CASES = [
+    # (problem, op_cost, atom_cost)
+    ("tiny1", oracle.UNIT_ALL, 1),
+    ("tiny5", oracle.UNIT_ALL, 1),
+    ("unary-root", oracle.UNIT_ALL, 1),
+    ("medium2", oracle.UNIT_ALL, 1),
+    ("tiny2", (2, 1, 3, 1, 2, 2, 3), 1),   # unary operators of cost 2 and 3 over stored levels
+    ("tiny3", (1, 0, 1, 0, 1, 1, 0), 1),   # X, G, U disabled
+    ("tiny14", (1, 1, 1, 1, 1, 1, 1), 2),  # atoms cost 2; minimum X & p1 ! X p1
+]
+
+
+def lookahead_problem(name):
+    if name == "unary-root":  # minimum G ! & p0 p1: a cost-1 operator over the overflowed level
+        return workload.custom(2, [[1, 2, 1], [2, 0]], [[3, 0], [0, 3], [1, 3]], 6, name="unary-root")
+    if name.startswith("medium"):
+        return workload.medium(int(name[6:]))
+    return workload.tiny(int(name[4:]))
+
+
+@pytest.mark.parametrize("case", LOOKAHEAD_CASES, ids=[c[0] + f"-{i}" for i, c in enumerate(LOOKAHEAD_CASES)])
+@pytest.mark.parametrize("kflag", [0, m.FLAG_KERNEL_GROUP, m.FLAG_KERNEL_WAVE], ids=["default", "group", "wave"])
+def test_lookahead_past_overflow(synth, case, kflag):
+    """The level below the minimum overflows: the minimum is still found,
+    in the next level, by the look-ahead (status, cost, checked level equal
+    to the oracle's; the witness separates and costs the minimum)."""
+    name, ops, ac = case
+    p = lookahead_problem(name)
+    full = oracle.solve(p, op_cost=ops, atom_cost=ac, cost_bound=p.cost_bound + 2)  # levels up to the minimum
+    want = full.min_cost
+    assert full.status == oracle.OK and want >= ac + 1
+    c = want - 1
+    if full.level_counts[c] < 2:
+        pytest.skip("the level below the minimum has fewer than two rows")
+    cap = sum(full.level_counts[1:c]) + full.level_counts[c] - 1
+    r, o = compare(synth, p, p.cost_bound + 2, op_cost=ops, atom_cost=ac, row_limit=cap, flags=kflag)
+    assert r.overflow_level == c and r.status == m.ltlf.OK and r.min_cost == want
+    assert r.checked_level == want
+    r, o = compare(synth, p, p.cost_bound + 2, op_cost=ops, atom_cost=ac, row_limit=cap,
+                   flags=kflag | m.FLAG_NO_LOOKAHEAD)
+    assert r.status == m.ltlf.CAPACITY and r.checked_level == c
+
+
+@pytest.mark.parametrize("kflag", [0, m.FLAG_KERNEL_WAVE], ids=["default", "wave"])
+def test_lookahead_without_solution_is_capacity(synth, kflag):
+    """Overflow two levels below the minimum: the look-ahead checks the next
+    level in full and finds nothing, so the run reports CAPACITY with every
+    level up to overflow + 1 checked."""
+    p = workload.tiny(1)
+    full = oracle.solve(p, cost_bound=p.cost_bound)
+    c = full.min_cost - 2
+    cap = sum(full.level_counts[1:c]) + full.level_counts[c] - 1
+    r, o = compare(synth, p, p.cost_bound, row_limit=cap, flags=kflag)
+    assert r.status == m.ltlf.CAPACITY and r.overflow_level == c and r.checked_level == c + 1
+
+
+def test_lookahead_over_the_atoms_level(synth):
+    """The atoms' level itself overflows: the look-ahead's operands are the
+    atoms."""
+    p = workload.custom(2, [[0, 1], [1]], [[2, 1], [3]], 4, name="not-p1")
+    full = oracle.solve(p, cost_bound=4, exhaust=True)
+    assert full.min_cost == 2
+    r, o = compare(synth, p, 4, row_limit=1)
+    assert r.overflow_level == 1 and r.status == m.ltlf.OK and r.min_cost == 2
 
 
 def test_edge_single_position(synth):

@@ -218,8 +218,9 @@ ltlf_status ltlf_solve(ltlf_ctx *ctx, const ltlf_spec *spec, const ltlf_costs *c
  * overflows.
  *   specs[i], bounds[i], results[i]: problem i; results[i] as for ltlf_run
  *     (level_counts and formula are caller buffers, or NULL).
- *   costs: shared by all problems.  flags: LTLF_FLAG_EXHAUST and
- *     LTLF_FLAG_DEBUG_WEAK_HASH as for ltlf_run (others are ignored).
+ *   costs: shared by all problems.  flags: LTLF_FLAG_EXHAUST,
+ *     LTLF_FLAG_NO_LOOKAHEAD and LTLF_FLAG_DEBUG_WEAK_HASH as for ltlf_run
+ *     (others are ignored).
  * The context's row limit applies to every problem as in ltlf_solve.
  * Statistics in results[i]: enum_ms is the whole batch's time.  The
  * context's loaded problem is discarded (call ltlf_load again before
@@ -230,6 +231,48 @@ ltlf_status ltlf_solve_batch(ltlf_ctx *ctx, uint32_t n, const ltlf_spec *specs,
                              const ltlf_costs *costs, const uint32_t *bounds,
                              uint32_t flags, void *hip_stream,
                              ltlf_result *results);
+
+/* Result of ltlf_solve_split.  formula is a caller buffer (host) or NULL. */
+typedef struct {
+    ltlf_status status;      /* OK, or NOT_FOUND / CAPACITY: a part that can no
+                                longer be split (at most one positive and one
+                                negative trace) has no separating formula
+                                within the bound / overflowed the store */
+    uint32_t depth;          /* rounds of solving (one batch each) */
+    uint32_t parts_solved;   /* parts solved by enumeration (leaves) */
+    uint32_t parts_split;    /* parts split */
+    uint32_t max_part_cost;  /* largest minimal cost among the leaves */
+    uint32_t pad;
+    uint64_t cost;           /* cost of formula: separating, not necessarily
+                                minimal */
+    char *formula;           /* in: buffer or NULL; out: prefix tokens */
+    uint64_t formula_cap;    /* in: capacity of formula in bytes */
+    uint64_t formula_len;    /* out: bytes needed including the NUL */
+    double enum_ms;          /* out: summed time of the batches */
+} ltlf_split_result;
+
+/* Divide-and-conquer synthesis (paper, "Parallel enumeration of LTLf formulae
+ * on GPUs", paragraph "Divide-and-conquer"), for specifications too large to
+ * solve in one go.  A part (P', N') of the specification is split into
+ * halves P' = P1 + P2, N' = N1 + N2 (first halves in the caller's trace
+ * order, the larger half first), the parts (Pi, Nj) are solved recursively
+ * and recombined as (phi11 & phi12) | (phi21 & phi22); a side with one trace
+ * is not split (then phi1 & phi2 over the halves of N', or phi1 | phi2 over
+ * the halves of P').  A part is split before it is solved if it has more than
+ * max_traces traces (0: no limit), and after its solve if that found no
+ * formula within cost_bound or overflowed the store.  Each round solves all
+ * of its open parts with one ltlf_solve_batch call (exact minimal formulas
+ * for the parts).  The combined formula separates the specification but is in
+ * general not minimal; & and | are written as their De Morgan forms over the
+ * other one and ! where disabled in costs (EINVAL if neither form exists).
+ *   flags: LTLF_FLAG_NO_LOOKAHEAD and LTLF_FLAG_DEBUG_WEAK_HASH as for
+ *   ltlf_run.  The context's loaded problem is discarded.  Returns the
+ *   result's status, or EINVAL (null pointers, invalid spec, costs or
+ *   bound), EBUFSZ (formula buffer too small; formula_len says what is
+ *   needed), ENOMEM, EDEVICE. */
+ltlf_status ltlf_solve_split(ltlf_ctx *ctx, const ltlf_spec *spec, const ltlf_costs *costs,
+                             uint32_t cost_bound, uint32_t max_traces, uint32_t flags, void *stream,
+                             ltlf_split_result *res);
 
 /* ---------------------------------------------------------------- server --
  * A request loop over one context (continuous batching).  Requests are
@@ -261,7 +304,8 @@ ltlf_status ltlf_server_create(ltlf_ctx *ctx, uint32_t max_resident, ltlf_server
 /* Queue a request; the specification is copied.  reserve_bytes: its
  * reservation in the small pool (0 = room for ~2^18 rows, at most an eighth
  * of the pool; at least 16 MiB).  flags: LTLF_FLAG_EXHAUST,
- * LTLF_FLAG_DEBUG_WEAK_HASH.  *ticket identifies it in poll / cancel.
+ * LTLF_FLAG_NO_LOOKAHEAD, LTLF_FLAG_DEBUG_WEAK_HASH.  *ticket identifies it
+ * in poll / cancel.
  * EINVAL: invalid specification, costs or bound (nothing is queued). */
 ltlf_status ltlf_server_submit(ltlf_server *srv, const ltlf_spec *spec, const ltlf_costs *costs,
                                uint32_t cost_bound, uint32_t flags, uint64_t reserve_bytes,

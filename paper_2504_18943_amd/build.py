@@ -7,7 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libltlf.so")
-SOURCES = [os.path.join(HERE, "csrc", "ltlf_kernels.hip"), os.path.join(HERE, "csrc", "ltlf_driver.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", "ltlf_kernels.hip"), os.path.join(HERE, "csrc", "ltlf_driver.cpp"),
+           os.path.join(HERE, "csrc", "ltlf_split.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -911,7 +911,7 @@ struct Scheduler {
         j->positive.assign(sp->positive, sp->positive + sp->n_traces);
         j->costs = *k;
         j->bound = bound;
-        j->flags = flags & (LTLF_FLAG_EXHAUST | LTLF_FLAG_DEBUG_WEAK_HASH);
+        j->flags = flags & (LTLF_FLAG_EXHAUST | LTLF_FLAG_NO_LOOKAHEAD | LTLF_FLAG_DEBUG_WEAK_HASH);
         j->wp = (uint32_t)align_up((bits + 31) / 32, 4);
         // default reservation: room for ~2^18 rows, at most an eighth of the small pool
         const uint64_t dflt = std::min<uint64_t>((4ull * j->wp + 48) << 18, small_pool() / 8);

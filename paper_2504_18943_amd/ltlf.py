@@ -65,6 +65,15 @@ class ltlf_result(ctypes.Structure):
                 ("verify_ms", ctypes.c_double), ("dead_rows", ctypes.c_uint64)]
 
 
+class ltlf_split_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("depth", ctypes.c_uint32),
+                ("parts_solved", ctypes.c_uint32), ("parts_split", ctypes.c_uint32),
+                ("max_part_cost", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("cost", ctypes.c_uint64), ("formula", ctypes.c_char_p),
+                ("formula_cap", ctypes.c_uint64), ("formula_len", ctypes.c_uint64),
+                ("enum_ms", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -99,6 +108,9 @@ def load_library() -> ctypes.CDLL:
     L.ltlf_solve_batch.restype = i32
     L.ltlf_solve_batch.argtypes = [vp, u32, ctypes.POINTER(ltlf_spec), ctypes.POINTER(ltlf_costs),
                                    ctypes.POINTER(u32), u32, vp, ctypes.POINTER(ltlf_result)]
+    L.ltlf_solve_split.restype = i32
+    L.ltlf_solve_split.argtypes = [vp, ctypes.POINTER(ltlf_spec), ctypes.POINTER(ltlf_costs), u32, u32, u32, vp,
+                                   ctypes.POINTER(ltlf_split_result)]
     L.ltlf_server_create.restype = i32
     L.ltlf_server_create.argtypes = [vp, u32, ctypes.POINTER(vp)]
     L.ltlf_server_submit.restype = i32
@@ -204,6 +216,14 @@ def ltlf_solve_batch(ctx, problems, op_cost, atom_cost, bounds, flags, stream, r
                                            results)
 
 
+def ltlf_solve_split(ctx, n_props, lengths, letters, positive, op_cost, atom_cost, cost_bound, max_traces,
+                     flags, stream, res: ltlf_split_result) -> int:
+    sp, keep = _spec(n_props, lengths, letters, positive)
+    c = _costs(op_cost, atom_cost)
+    return load_library().ltlf_solve_split(ctx, ctypes.byref(sp), ctypes.byref(c), cost_bound, max_traces, flags,
+                                           ctypes.c_void_p(stream), ctypes.byref(res))
+
+
 def ltlf_server_create(ctx, max_resident: int):
     h = ctypes.c_void_p()
     st = load_library().ltlf_server_create(ctx, max_resident, ctypes.byref(h))
@@ -294,6 +314,24 @@ class Result:
         return STATUS_NAMES.get(self.status, str(self.status))
 
 
+@dataclass
+class SplitResult:
+    """Result of divide-and-conquer synthesis: a separating formula, in
+    general not a minimal one."""
+    status: int
+    cost: int
+    formula: str
+    depth: int
+    parts_solved: int
+    parts_split: int
+    max_part_cost: int
+    enum_ms: float
+
+    @property
+    def status_name(self) -> str:
+        return STATUS_NAMES.get(self.status, str(self.status))
+
+
 UNIT_ALL = (1, 1, 1, 1, 1, 1, 1)
 
 
@@ -369,6 +407,23 @@ class Synthesizer:
         self.load(problem)
         return self.run(int(cost_bound if cost_bound is not None else problem.cost_bound),
                         op_cost=op_cost, atom_cost=atom_cost, flags=flags)
+
+    def solve_split(self, problem, cost_bound: Optional[int] = None, max_traces: int = 0,
+                    op_cost=UNIT_ALL, atom_cost: int = 1, flags: int = 0) -> SplitResult:
+        """Divide-and-conquer synthesis (ltlf_solve_split in include/ltlf.h)."""
+        bound = int(cost_bound if cost_bound is not None else problem.cost_bound)
+        res = ltlf_split_result()
+        fbuf = ctypes.create_string_buffer(1 << 20)
+        res.formula = ctypes.cast(fbuf, ctypes.c_char_p)
+        res.formula_cap = len(fbuf)
+        lengths, letters, positive = problem.arrays()
+        st = ltlf_solve_split(self._ctx, problem.n_props, lengths, letters, positive, op_cost, atom_cost, bound,
+                              max_traces, flags, self._stream(), res)
+        if st < 0:
+            raise LtlfError(st, "ltlf_solve_split", ltlf_ctx_last_error(self._ctx))
+        return SplitResult(status=st, cost=res.cost, formula=fbuf.value.decode(), depth=res.depth,
+                           parts_solved=res.parts_solved, parts_split=res.parts_split,
+                           max_part_cost=res.max_part_cost, enum_ms=res.enum_ms)
 
     def solve_batch(self, problems, cost_bounds=None, op_cost=UNIT_ALL, atom_cost: int = 1,
                     flags: int = 0) -> List[Result]:

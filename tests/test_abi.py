@@ -3,6 +3,7 @@ point, and rejects bad arguments before touching a device."""
 from __future__ import annotations
 
 import ctypes
+import subprocess
 import os
 import re
 
@@ -57,6 +58,8 @@ def test_null_arguments_rejected_without_device():
     assert lib.ltlf_ctx_set_row_limit(None, 5) == L.EINVAL
     n, cw = ctypes.c_uint64(), ctypes.c_uint64()
     assert lib.ltlf_export_level(None, 1, 0, 1, None, 0, ctypes.byref(n), ctypes.byref(cw)) == L.EINVAL
+    sres = L.ltlf_split_result()
+    assert lib.ltlf_solve_split(None, None, ctypes.byref(c), 5, 0, 0, None, ctypes.byref(sres)) == L.EINVAL
     lib.ltlf_ctx_destroy(None)  # no-op
 
 
@@ -65,6 +68,29 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.ltlf_costs) == 32
     assert ctypes.sizeof(L.ltlf_spec) == 8 + 3 * ctypes.sizeof(ctypes.c_void_p)
     assert ctypes.sizeof(L.ltlf_result) == 4 * 4 + 8 * 8 + 4 * 4 + 3 * 8 + 8
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """Sizes and field offsets of the result structs as gcc lays them out
+    from the header, against the binding's ctypes declarations."""
+    fields = {"ltlf_result": [f for f, _ in L.ltlf_result._fields_],
+              "ltlf_split_result": [f for f, _ in L.ltlf_split_result._fields_]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ltlf.h"', "int main(void) {"]
+    for st, fs in fields.items():
+        lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    for st, fs in fields.items():
+        cls = getattr(L, st)
+        assert int(got[st]) == ctypes.sizeof(cls), st
+        for f in fs:
+            assert int(got[f"{st}.{f}"]) == getattr(cls, f).offset, f"{st}.{f}"
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -8,13 +8,18 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/ltlf.h"
@@ -465,6 +470,7 @@ struct LevelRun {
     ltlf_status status = LTLF_NOT_FOUND;
     uint32_t wit_op = 0, wit_a = 0, wit_b = 0;
     bool stop = false;  // the run ended: a separating level without EXHAUST, or an overflow
+    uint32_t grid_eighths = 8;  // share of the resident blocks a persistent launch takes
 
     ltlf_status begin(ltlf_ctx* ctx, const ltlf_costs* costs, uint32_t cost_bound, uint32_t run_flags,
                       ltlf_result* result, hipStream_t s) {
@@ -614,6 +620,7 @@ struct LevelRun {
                 const uint64_t per_block = per_tile + (kLanes / 64) * kAllocChunk;
                 uint64_t blocks = 0;
                 TRY_HIP(generate_blocks(c->st, total, blocks));
+                blocks = std::max<uint64_t>(1, blocks * grid_eighths / 8);
                 blocks = std::max<uint64_t>(1, std::min<uint64_t>(blocks, c->st.def0_cap / (2 * per_block)));
                 const uint64_t margin = blocks * per_block;
                 t.tile_begin = 0;
@@ -818,12 +825,73 @@ struct Scheduler {
     BSeg* d_segs = nullptr;
     unsigned long long* d_gather = nullptr;
     uint32_t launches = 0;
+    // The large region's levels run on a worker thread with a stream of its
+    // own, so the small pool keeps stepping while a large level runs; the
+    // worker owns `big` (its job, LevelRun and sub-context) until joined.
+    std::thread worker;
+    hipStream_t big_stream = nullptr;
+    std::mutex mu;
+    std::condition_variable cv;
+    bool big_running = false;          // guarded by mu
+    bool big_cancel = false;           // guarded by mu
+    ltlf_status big_status = LTLF_OK;  // the worker's, read after the join
+    std::atomic<bool> small_busy{false};  // small problems resident or waiting (main thread sets it)
     static constexpr uint64_t kSegs = 1ull << 16;
     static constexpr uint64_t kMinSlice = 16ull << 20;
     static constexpr uint64_t kBigLevel = 1ull << 20;  // candidates of a level that runs on its own
 
     ~Scheduler() {
+        stop_worker();
+        if (big_stream) {
+            (void)hipStreamSynchronize(big_stream);
+            (void)hipStreamDestroy(big_stream);
+        }
         for (auto& kv : jobs) delete kv.second;
+    }
+
+    // asks the worker to stop after its current level and waits for it
+    void stop_worker() {
+        if (!worker.joinable()) return;
+        {
+            std::lock_guard<std::mutex> g(mu);
+            big_cancel = true;
+        }
+        worker.join();
+    }
+
+    // the large problem, level after level, on the worker thread
+    void big_loop(Job* j) {
+        ltlf_status st = hipSetDevice(c->device) == hipSuccess ? LTLF_OK : LTLF_EDEVICE;
+        LevelRun& r = *j->run;
+        while (st == LTLF_OK) {
+            {
+                std::lock_guard<std::mutex> g(mu);
+                if (big_cancel) break;
+            }
+            const uint32_t lev = j->lev + 1;
+            // persistent launches leave block slots to the small pool's
+            // launches while it has work
+            r.grid_eighths = small_busy.load(std::memory_order_relaxed) ? 7 : 8;
+            st = r.level(lev, big_stream);
+            if (st != LTLF_OK) break;
+            j->lev = lev;
+            j->res.candidates = r.candidates;
+            j->rows = r.rows;
+            j->status = r.status;
+            j->wit_op = r.wit_op;
+            j->wit_a = r.wit_a;
+            j->wit_b = r.wit_b;
+            if (r.stop || lev == j->bound) break;
+        }
+        // a level can end with work still queued (the compaction of its dead
+        // rows); the main thread reads the sub-context (witness formula) and
+        // hands the large region to the next job on its own stream, so the
+        // worker's stream must be drained first
+        if (hipStreamSynchronize(big_stream) != hipSuccess && st == LTLF_OK) st = LTLF_EDEVICE;
+        std::lock_guard<std::mutex> g(mu);
+        big_status = st;
+        big_running = false;
+        cv.notify_all();
     }
 
     ltlf_status init(ltlf_ctx* ctx, uint32_t max_res) {
@@ -1028,6 +1096,18 @@ struct Scheduler {
         j->lev = 0;
         const ltlf_status st = j->run->begin(sub, &j->costs, j->bound, j->flags, &j->res, s);
         if (st != LTLF_OK) return fail(c, st, sub->err.c_str());
+        if (!big_stream) TRY_HIP(hipStreamCreateWithFlags(&big_stream, hipStreamNonBlocking));
+        TRY_HIP(hipStreamSynchronize(s));  // the load and the run's set-up precede its levels
+        big_running = true;
+        big_cancel = false;
+        big_status = LTLF_OK;
+        small_busy.store(!resident.empty() || !queue.empty(), std::memory_order_relaxed);
+        try {
+            worker = std::thread([this, j] { big_loop(j); });
+        } catch (...) {  // no thread: nothing runs it
+            big_running = false;
+            return fail(c, LTLF_EDEVICE, "cannot start the large region's worker thread");
+        }
         return LTLF_OK;
     }
 
@@ -1204,21 +1284,22 @@ struct Scheduler {
                 ++finished;
             }
         }
-        // the large problem: one level with the single-problem kernels
+        small_busy.store(!resident.empty() || !queue.empty(), std::memory_order_relaxed);
+        // the large problem runs on the worker (single-problem kernels); with
+        // nothing else to step, wait for it a little instead of returning at once
         if (big) {
-            Job* j = big;
-            LevelRun& r = *j->run;
-            const uint32_t lev = j->lev + 1;
-            TRY(r.level(lev, s));
-            j->lev = lev;
-            j->res.candidates = r.candidates;
-            j->rows = r.rows;
-            j->status = r.status;
-            j->wit_op = r.wit_op;
-            j->wit_a = r.wit_a;
-            j->wit_b = r.wit_b;
-            // an overflow here is final: the large region is the request's capacity
-            if (r.stop || lev == j->bound) {
+            bool running;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                if (big_running && live.empty())
+                    cv.wait_for(lk, std::chrono::milliseconds(2), [this] { return !big_running; });
+                running = big_running;
+            }
+            if (!running) {
+                worker.join();
+                Job* j = big;
+                if (big_status != LTLF_OK) return fail(c, big_status, j->sub->err.c_str());
+                // an overflow here is final: the large region is the request's capacity
                 if (j->status != LTLF_OK && j->res.overflow_level) j->status = LTLF_CAPACITY;
                 TRY(finish(j, s));
                 ++finished;
@@ -1260,6 +1341,7 @@ struct Scheduler {
         auto it = jobs.find(ticket);
         if (it == jobs.end()) return LTLF_EINVAL;
         Job* j = it->second;
+        if (j == big) stop_worker();
         drop(j);
         for (std::deque<Job*>* q : {&queue, &big_queue, &solo_queue}) {
             auto f = std::find(q->begin(), q->end(), j);

@@ -111,3 +111,27 @@ def test_context_usable_after_batch(big):
     r = big.solve(p, cost_bound=7, flags=m.FLAG_EXHAUST)
     check(r, oracle.solve(p, cost_bound=7, exhaust=True), p)
     assert len(big.export_level(3)) == r.level_counts[3]
+
+
+def test_large_region_jobs_in_sequence():
+    """Several problems whose levels run in the large region one after the
+    other, with the group kernel (47..56-chunk rows) and the wave kernel
+    (102-chunk rows); their persistent launches leave dead rows, so every
+    level ends with a compaction before the region passes to the next job.
+    Results equal the problems solved alone (status, cost, levels, counts),
+    and every witness separates."""
+    ps = workload.batched(1, 222)
+    ps = [ps[i] for i in (128, 164, 221, 81)] + [workload.tiny(s) for s in (1, 2, 3)]
+    s = m.Synthesizer(device=0, workspace_bytes=32 << 30)
+    try:
+        print("[batch] large-region jobs in sequence", flush=True)
+        mix = s.solve_batch(ps)
+        for p, r in zip(ps, mix):
+            a = s.solve(p)
+            assert (a.status, a.min_cost, a.levels_done, a.overflow_level, a.level_counts) == \
+                (r.status, r.min_cost, r.levels_done, r.overflow_level, r.level_counts), p.name
+            if r.status == m.ltlf.OK:
+                assert ev.separates(r.formula, p.traces, p.positive), (p.name, r.formula)
+                assert ev.cost(r.formula) == r.min_cost, (p.name, r.formula)
+    finally:
+        s.close()

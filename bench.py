@@ -209,6 +209,8 @@ def main() -> int:
     ap.add_argument("--batched", type=int, default=256,
                     help="problems of the batched configuration solved one by one and with "
                          "ltlf_solve_batch (0 = skip)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run the batched and served legs with the built-in kernel choice")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (for scaling "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -302,6 +304,17 @@ def main() -> int:
         ttf = {"median_ms": round(statistics.median(v["ms"] for v in per_seed.values()), 3),
                "per_seed": per_seed, "includes": "host-to-device upload of the specification"}
 
+    # measured kernel choice per row width; the batched and served legs (both
+    # modes) run with it, the headline above with the built-in choice
+    tuning = None
+    if not args.no_autotune and (args.batched > 0 or args.served > 0):
+        a = time.perf_counter()
+        table = synth.autotune()
+        tuning = {"seconds": round(time.perf_counter() - a, 2),
+                  "classes": [{"chunks": e["chunks"], "kernel": e["kernel"], "ns_per_candidate": e["ns_per_candidate"]}
+                              for e in table]}
+        log(f"[bench] autotune {tuning}")
+
     batched = None
     if args.batched > 0:
         batched = batched_compare(synth, args.batched)
@@ -334,6 +347,7 @@ def main() -> int:
                    "candidates": last.candidates, "deferred": last.deferred,
                    "status": last.status_name, "min_cost": last.min_cost},
         "time_to_formula": ttf,
+        "autotune": tuning,
         "batched": batched,
         "served": served,
         "roofline": roof,

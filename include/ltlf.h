@@ -232,6 +232,41 @@ ltlf_status ltlf_solve_batch(ltlf_ctx *ctx, uint32_t n, const ltlf_spec *specs,
                              uint32_t flags, void *hip_stream,
                              ltlf_result *results);
 
+/* Generation-kernel tuning: for each class of row widths, the word tile that
+ * generates fastest on this device (one candidate per lane with operands in
+ * LDS, per group of lanes with one 16-byte chunk each, or per wavefront with
+ * the row streamed 64 chunks at a time; each kernel has its own pair-grid
+ * tile).  Results never depend on the choice, only the speed. */
+#define LTLF_TUNE_CLASSES 16
+typedef struct {
+    uint32_t n_classes;                    /* classes filled */
+    uint32_t chunks[LTLF_TUNE_CLASSES];    /* row width of the class, 16-byte chunks */
+    uint32_t kernel[LTLF_TUNE_CLASSES];    /* choice: LTLF_FLAG_KERNEL_LANE, _GROUP or _WAVE */
+    uint32_t bound[LTLF_TUNE_CLASSES];     /* cost bound of the timed runs */
+    uint64_t candidates[LTLF_TUNE_CLASSES];  /* candidates of one timed run */
+    double ns_per_candidate[LTLF_TUNE_CLASSES][3];  /* generation + verification time per
+                                                       candidate of lane, group, wave
+                                                       (0: not applicable at this width) */
+} ltlf_tuning;
+
+/* Measures every applicable generation kernel on a synthetic problem per
+ * width class (3 propositions, 8 x chunks traces of length 15, letters and
+ * labels from a fixed seed; cost bound raised until a run has about 2e10
+ * bytes of candidate rows (5e6 .. 1e8 candidates) or reaches 12; every level
+ * enumerated) and keeps the fastest
+ * per class in the context: later runs without an LTLF_FLAG_KERNEL_* flag use
+ * the class nearest to their row width (log scale).  The large region of a
+ * batch or server created on the context inherits it.  The context's loaded
+ * problem is discarded.  out may be NULL.  Returns OK, EINVAL, ENOMEM,
+ * EDEVICE. */
+ltlf_status ltlf_autotune(ltlf_ctx *ctx, void *stream, ltlf_tuning *out);
+
+/* Installs a tuning table (e.g. one measured earlier on another context);
+ * NULL restores the built-in choice (lane where its tile fits the LDS, else
+ * group up to 64 chunks, else wave).  EINVAL: n_classes > LTLF_TUNE_CLASSES,
+ * a chunks entry of 0 or a kernel entry that is not one of the three flags. */
+ltlf_status ltlf_ctx_set_tuning(ltlf_ctx *ctx, const ltlf_tuning *tuning);
+
 /* Result of ltlf_solve_split.  formula is a caller buffer (host) or NULL. */
 typedef struct {
     ltlf_status status;      /* OK, or NOT_FOUND / CAPACITY: a part that can no

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdio>
 #include <cstring>
@@ -92,6 +93,10 @@ struct ltlf_ctx {
     std::vector<ltlf_ctx*> subs;
     unsigned long long* h_batch = nullptr;  // pinned, h_batch_cap counters
     uint64_t h_batch_cap = 0;
+
+    // measured kernel choice per row-width class: (chunks, KERNEL_*); empty =
+    // the built-in rule
+    std::vector<std::pair<uint32_t, uint32_t>> tune;
 };
 
 namespace {
@@ -455,6 +460,23 @@ ltlf_status validate_spec(const ltlf_spec* sp) {
 }
 
 
+// The measured kernel for the loaded row width: the tuning class nearest to
+// it on a log scale; KERNEL_AUTO (the built-in rule) without a table.
+uint32_t tuned_kernel(const ltlf_ctx* c) {
+    if (c->tune.empty()) return KERNEL_AUTO;
+    const double w = std::log((double)std::max<uint32_t>(1, c->Wp / 4));
+    double best = 1e300;
+    uint32_t kind = KERNEL_AUTO;
+    for (const auto& t : c->tune) {
+        const double d = std::fabs(std::log((double)t.first) - w);
+        if (d < best) {
+            best = d;
+            kind = t.second;
+        }
+    }
+    return kind;
+}
+
 // One single-problem run, level by level: the level loop of ltlf_run, also
 // used by the scheduler for resident problems whose levels are large (they
 // keep the single-problem kernels and table sizing).
@@ -485,7 +507,7 @@ struct LevelRun {
         const uint32_t pref = (flags & LTLF_FLAG_KERNEL_WAVE)    ? KERNEL_WAVE
                               : (flags & LTLF_FLAG_KERNEL_GROUP) ? KERNEL_GROUP
                               : (flags & LTLF_FLAG_KERNEL_LANE)  ? KERNEL_LANE
-                                                                 : KERNEL_AUTO;
+                                                                 : tuned_kernel(c);
         shape = tile_shape(c->Wp, c->lds_limit, pref);
         rows = 0;
         candidates = 0;
@@ -1082,6 +1104,7 @@ struct Scheduler {
         sub->ws_bytes = large_region() / 256 * 256;
         sub->own_ws = false;
         sub->row_limit = c->row_limit;
+        sub->tune = c->tune;
         const ltlf_spec sp = j->spec();
         const ltlf_status ls = ltlf_load(sub, &sp, s);
         if (ls == LTLF_ENOMEM) {  // not even the large region: the whole workspace
@@ -1511,6 +1534,99 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
     c->ran = true;
     TRY(finish_result(c, res, run.status, run.wit_op, run.wit_a, run.wit_b, s));
     return run.status;
+}
+
+ltlf_status ltlf_ctx_set_tuning(ltlf_ctx* c, const ltlf_tuning* t) {
+    if (!c) return LTLF_EINVAL;
+    if (!t) {
+        c->tune.clear();
+        return LTLF_OK;
+    }
+    if (t->n_classes > LTLF_TUNE_CLASSES) return LTLF_EINVAL;
+    std::vector<std::pair<uint32_t, uint32_t>> tune;
+    for (uint32_t i = 0; i < t->n_classes; ++i) {
+        const uint32_t f = t->kernel[i];
+        const uint32_t kind = f == LTLF_FLAG_KERNEL_LANE    ? KERNEL_LANE
+                              : f == LTLF_FLAG_KERNEL_GROUP ? KERNEL_GROUP
+                              : f == LTLF_FLAG_KERNEL_WAVE  ? KERNEL_WAVE
+                                                            : 0u;
+        if (!kind || t->chunks[i] == 0) return LTLF_EINVAL;
+        tune.emplace_back(t->chunks[i], kind);
+    }
+    c->tune = tune;
+    return LTLF_OK;
+}
+
+ltlf_status ltlf_autotune(ltlf_ctx* c, void* stream, ltlf_tuning* out) {
+    if (!c) return LTLF_EINVAL;
+    c->err.clear();
+    TRY_HIP(hipSetDevice(c->device));
+    TRY(ensure_workspace(c));
+    static const uint32_t kClasses[] = {1, 2, 4, 8, 10, 16, 24, 32, 38, 48, 64, 96, 128, 256, 328};
+    static_assert(sizeof(kClasses) / sizeof(kClasses[0]) <= LTLF_TUNE_CLASSES, "tuning classes");
+    constexpr uint32_t kLen = 15;  // 16 bits per trace with the guard bit
+    // a timed run has levels of the size real runs spend their time in: about
+    // 2e10 bytes of candidate rows (5e6 .. 1e8 candidates)
+    const ltlf_costs k{1, {1, 1, 1, 1, 1, 1, 1}};
+    const uint32_t flag_of[3] = {LTLF_FLAG_KERNEL_LANE, LTLF_FLAG_KERNEL_GROUP, LTLF_FLAG_KERNEL_WAVE};
+    const uint32_t kind_of[3] = {KERNEL_LANE, KERNEL_GROUP, KERNEL_WAVE};
+    ltlf_tuning t{};
+    std::vector<std::pair<uint32_t, uint32_t>> tune;
+    c->tune.clear();  // the timed runs name their kernel; the search runs use the built-in rule
+    uint64_t rng = 0x2504189430ull;
+    auto next = [&rng]() {  // splitmix64
+        uint64_t z = (rng += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    for (uint32_t ci = 0; ci < sizeof(kClasses) / sizeof(kClasses[0]); ++ci) {
+        const uint32_t chunks = kClasses[ci], T = 8 * chunks;
+        std::vector<uint32_t> lengths(T, kLen), letters((uint64_t)T * kLen);
+        std::vector<uint8_t> positive(T);
+        for (auto& l : letters) l = (uint32_t)(next() & 7u);
+        for (uint32_t i = 0; i < T; ++i) positive[i] = (uint8_t)(next() & 1u);
+        const ltlf_spec sp{3, T, lengths.data(), letters.data(), positive.data()};
+        TRY(ltlf_load(c, &sp, stream));
+        const uint64_t want = std::min<uint64_t>(100000000ull,
+                                                 std::max<uint64_t>(5000000ull, 20000000000ull / (16ull * chunks)));
+        // the smallest bound whose run has enough candidates to time
+        ltlf_result r{};
+        uint32_t bound = 4;
+        for (;; ++bound) {
+            r = ltlf_result{};
+            const ltlf_status st = ltlf_run(c, &k, bound, LTLF_FLAG_EXHAUST, stream, &r);
+            if (st < 0) return st;
+            if (r.candidates >= want || bound >= 12 || st == LTLF_CAPACITY) break;
+        }
+        double best = 0;
+        uint32_t best_i = 2;
+        for (uint32_t i = 0; i < 3; ++i) {
+            t.ns_per_candidate[ci][i] = 0;
+            if (tile_shape(c->Wp, c->lds_limit, kind_of[i]).kind != kind_of[i]) continue;  // does not apply
+            r = ltlf_result{};
+            const ltlf_status st =
+                ltlf_run(c, &k, bound, LTLF_FLAG_EXHAUST | LTLF_FLAG_PROFILE | flag_of[i], stream, &r);
+            if (st < 0) return st;
+            const double ns = 1e6 * (r.gen_ms + r.verify_ms) / (double)std::max<uint64_t>(1, r.candidates);
+            t.ns_per_candidate[ci][i] = ns;
+            t.candidates[ci] = r.candidates;
+            if (best == 0 || ns < best) {
+                best = ns;
+                best_i = i;
+            }
+        }
+        t.chunks[ci] = chunks;
+        t.kernel[ci] = flag_of[best_i];
+        t.bound[ci] = bound;
+        t.n_classes = ci + 1;
+        tune.emplace_back(chunks, kind_of[best_i]);
+    }
+    c->tune = tune;
+    c->loaded = false;
+    c->ran = false;
+    if (out) *out = t;
+    return LTLF_OK;
 }
 
 ltlf_status ltlf_solve(ltlf_ctx* c, const ltlf_spec* sp, const ltlf_costs* k, uint32_t bound,

@@ -65,6 +65,16 @@ class ltlf_result(ctypes.Structure):
                 ("verify_ms", ctypes.c_double), ("dead_rows", ctypes.c_uint64)]
 
 
+TUNE_CLASSES = 16
+
+
+class ltlf_tuning(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_uint32), ("chunks", ctypes.c_uint32 * TUNE_CLASSES),
+                ("kernel", ctypes.c_uint32 * TUNE_CLASSES), ("bound", ctypes.c_uint32 * TUNE_CLASSES),
+                ("candidates", ctypes.c_uint64 * TUNE_CLASSES),
+                ("ns_per_candidate", (ctypes.c_double * 3) * TUNE_CLASSES)]
+
+
 class ltlf_split_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("depth", ctypes.c_uint32),
                 ("parts_solved", ctypes.c_uint32), ("parts_split", ctypes.c_uint32),
@@ -108,6 +118,10 @@ def load_library() -> ctypes.CDLL:
     L.ltlf_solve_batch.restype = i32
     L.ltlf_solve_batch.argtypes = [vp, u32, ctypes.POINTER(ltlf_spec), ctypes.POINTER(ltlf_costs),
                                    ctypes.POINTER(u32), u32, vp, ctypes.POINTER(ltlf_result)]
+    L.ltlf_autotune.restype = i32
+    L.ltlf_autotune.argtypes = [vp, vp, ctypes.POINTER(ltlf_tuning)]
+    L.ltlf_ctx_set_tuning.restype = i32
+    L.ltlf_ctx_set_tuning.argtypes = [vp, ctypes.POINTER(ltlf_tuning)]
     L.ltlf_solve_split.restype = i32
     L.ltlf_solve_split.argtypes = [vp, ctypes.POINTER(ltlf_spec), ctypes.POINTER(ltlf_costs), u32, u32, u32, vp,
                                    ctypes.POINTER(ltlf_split_result)]
@@ -214,6 +228,14 @@ def ltlf_solve_batch(ctx, problems, op_cost, atom_cost, bounds, flags, stream, r
     b = (ctypes.c_uint32 * n)(*bounds)
     return load_library().ltlf_solve_batch(ctx, n, specs, ctypes.byref(c), b, flags, ctypes.c_void_p(stream),
                                            results)
+
+
+def ltlf_autotune(ctx, stream, out) -> int:
+    return load_library().ltlf_autotune(ctx, ctypes.c_void_p(stream), ctypes.byref(out) if out is not None else None)
+
+
+def ltlf_ctx_set_tuning(ctx, tuning) -> int:
+    return load_library().ltlf_ctx_set_tuning(ctx, ctypes.byref(tuning) if tuning is not None else None)
 
 
 def ltlf_solve_split(ctx, n_props, lengths, letters, positive, op_cost, atom_cost, cost_bound, max_traces,
@@ -407,6 +429,30 @@ class Synthesizer:
         self.load(problem)
         return self.run(int(cost_bound if cost_bound is not None else problem.cost_bound),
                         op_cost=op_cost, atom_cost=atom_cost, flags=flags)
+
+    def autotune(self) -> List[dict]:
+        """Measures the generation kernels per row-width class and keeps the
+        fastest in the context (ltlf_autotune in include/ltlf.h).  Returns one
+        entry per class: chunks, chosen kernel, cost bound and candidates of
+        the timed runs, ns per candidate of lane / group / wave (None where a
+        kernel does not apply)."""
+        t = ltlf_tuning()
+        st = ltlf_autotune(self._ctx, self._stream(), t)
+        if st != OK:
+            raise LtlfError(st, "ltlf_autotune", ltlf_ctx_last_error(self._ctx))
+        self._tuning = t
+        names = {FLAG_KERNEL_LANE: "lane", FLAG_KERNEL_GROUP: "group", FLAG_KERNEL_WAVE: "wave"}
+        return [{"chunks": t.chunks[i], "kernel": names[t.kernel[i]], "bound": t.bound[i],
+                 "candidates": t.candidates[i],
+                 "ns_per_candidate": {n: (round(t.ns_per_candidate[i][j], 4) if t.ns_per_candidate[i][j] else None)
+                                      for j, n in enumerate(("lane", "group", "wave"))}}
+                for i in range(t.n_classes)]
+
+    def set_tuning(self, tuning: Optional["ltlf_tuning"]) -> None:
+        """Installs a tuning table (None: the built-in kernel choice)."""
+        st = ltlf_ctx_set_tuning(self._ctx, tuning)
+        if st != OK:
+            raise LtlfError(st, "ltlf_ctx_set_tuning")
 
     def solve_split(self, problem, cost_bound: Optional[int] = None, max_traces: int = 0,
                     op_cost=UNIT_ALL, atom_cost: int = 1, flags: int = 0) -> SplitResult:

@@ -60,6 +60,8 @@ def test_null_arguments_rejected_without_device():
     assert lib.ltlf_export_level(None, 1, 0, 1, None, 0, ctypes.byref(n), ctypes.byref(cw)) == L.EINVAL
     sres = L.ltlf_split_result()
     assert lib.ltlf_solve_split(None, None, ctypes.byref(c), 5, 0, 0, None, ctypes.byref(sres)) == L.EINVAL
+    assert lib.ltlf_autotune(None, None, None) == L.EINVAL
+    assert lib.ltlf_ctx_set_tuning(None, None) == L.EINVAL
     lib.ltlf_ctx_destroy(None)  # no-op
 
 
@@ -74,7 +76,8 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     """Sizes and field offsets of the result structs as gcc lays them out
     from the header, against the binding's ctypes declarations."""
     fields = {"ltlf_result": [f for f, _ in L.ltlf_result._fields_],
-              "ltlf_split_result": [f for f, _ in L.ltlf_split_result._fields_]}
+              "ltlf_split_result": [f for f, _ in L.ltlf_split_result._fields_],
+              "ltlf_tuning": [f for f, _ in L.ltlf_tuning._fields_]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ltlf.h"', "int main(void) {"]
     for st, fs in fields.items():
         lines.append(f'printf("{st} %zu\\n", sizeof({st}));')

@@ -116,7 +116,7 @@ def batched_compare(synth, count: int):
                       "bound planted+3, master seed 1"}
 
 
-def served_compare(synth, count: int):
+def served_compare(synth, count: int, outliers: float = 0.0):
     """Served stream: requests drawn from the batched configuration's shape
     mix (master seed 2) arrive as a Poisson process at 1.5 x the rate one at
     a time solving sustains; the request server (continuous batching) and a
@@ -128,12 +128,14 @@ def served_compare(synth, count: int):
 
     import paper_2504_18943_amd as m
 
-    ps = workload.batched(2, count)
+    ps = workload.served(2, count, outliers)
     synth.solve(ps[0])  # warm-up
     torch.cuda.synchronize()
     a = time.perf_counter()
     for p in ps:
         synth.solve(p)
+        if "outlier" in p.name:
+            log(f"[bench] served calibration: {p.name} done")
     torch.cuda.synchronize()
     solo_rate = count / (time.perf_counter() - a)
     rate = 1.5 * solo_rate
@@ -153,6 +155,8 @@ def served_compare(synth, count: int):
             time.sleep(arrive[i] - now)
         res_solo.append(synth.solve(p))
         done_solo.append(time.perf_counter() - t0)
+        if "outlier" in p.name:
+            log(f"[bench] served one at a time: {p.name} done")
     ttf_solo = [(d - arr) * 1e3 for d, arr in zip(done_solo, arrive)]
     span_solo = done_solo[-1]
     # the request server
@@ -174,6 +178,8 @@ def served_compare(synth, count: int):
                 i = tickets.pop(t)
                 done_srv[i] = time.perf_counter() - t0
                 res_srv[i] = r
+                if "outlier" in ps[i].name:
+                    log(f"[bench] served server: {ps[i].name} done")
     srv.close()
     ttf_srv = [(d - arr) * 1e3 for d, arr in zip(done_srv, arrive)]
     span_srv = max(done_srv)
@@ -189,7 +195,9 @@ def served_compare(synth, count: int):
                        "problems_per_s": round(count / span_srv, 2)},
             "results_identical": True,
             "config": "Poisson arrivals at 1.5x the one-at-a-time rate; shapes of the batched configuration "
-                      "(master seed 2), bound planted+3"}
+                      "(master seed 2), bound planted+3"
+                      + (f"; {int(round(count * outliers))} outliers of the large configuration's size "
+                         f"(5 props, 512+512 traces, lengths 16-64, same cost law)" if outliers else "")}
 
 
 def main() -> int:
@@ -206,6 +214,9 @@ def main() -> int:
     ap.add_argument("--served", type=int, default=128,
                     help="requests of the served stream (Poisson arrivals), server vs one at a "
                          "time (0 = skip)")
+    ap.add_argument("--served-outliers", type=float, default=0.05,
+                    help="fraction of served requests replaced by problems of the large "
+                         "configuration's size")
     ap.add_argument("--batched", type=int, default=256,
                     help="problems of the batched configuration solved one by one and with "
                          "ltlf_solve_batch (0 = skip)")
@@ -320,7 +331,7 @@ def main() -> int:
         batched = batched_compare(synth, args.batched)
     served = None
     if args.served > 0:
-        served = served_compare(synth, args.served)
+        served = served_compare(synth, args.served, args.served_outliers)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.seed, args.cpu_bound)
     if cpu:

@@ -232,6 +232,24 @@ def batched(master_seed: int = 1, count: int = 256) -> List[Problem]:
     return out
 
 
+def served(master_seed: int = 2, count: int = 128, outlier_frac: float = 0.0) -> List[Problem]:
+    """Served stream: the batched mix (master seed) with round(count x
+    outlier_frac) requests, at positions drawn from the master seed, replaced
+    by outliers of the large configuration's size (5 props, 512+512 traces,
+    lengths 16..64) with the mix's cost law (planted U{6..12}, bound
+    planted+3); outlier k uses seed 5000+k."""
+    out = batched(master_seed, count)
+    n_out = int(round(count * outlier_frac))
+    if n_out:
+        rng = np.random.Generator(np.random.PCG64(master_seed + 7))
+        where = sorted(int(i) for i in rng.choice(count, size=n_out, replace=False))
+        for k, i in enumerate(where):
+            pc = int(rng.integers(6, 13))
+            out[i] = make_problem(5000 + k, 5, 512, 512, 16, 64, pc, pc + 3, q_range=(0.3, 0.7),
+                                  name=f"served/{i}-outlier")
+    return out
+
+
 def custom(n_props: int, traces_pos: Sequence[Sequence[int]], traces_neg: Sequence[Sequence[int]],
            cost_bound: int, name: str = "") -> Problem:
     return Problem(n_props=n_props, traces=[list(t) for t in traces_pos] + [list(t) for t in traces_neg],

@@ -253,8 +253,9 @@ typedef struct {
  * width class (3 propositions, 8 x chunks traces of length 15, letters and
  * labels from a fixed seed; cost bound raised until a run has about 2e10
  * bytes of candidate rows (5e6 .. 1e8 candidates) or reaches 12; every level
- * enumerated) and keeps the fastest
- * per class in the context: later runs without an LTLF_FLAG_KERNEL_* flag use
+ * enumerated) and keeps, per class in the context, the fastest (the built-in
+ * choice unless another kernel is more than 5% faster): later runs without an
+ * LTLF_FLAG_KERNEL_* flag use
  * the class nearest to their row width (log scale).  The large region of a
  * batch or server created on the context inherits it.  The context's loaded
  * problem is discarded.  out may be NULL.  Returns OK, EINVAL, ENOMEM,

@@ -1616,6 +1616,12 @@ ltlf_status ltlf_autotune(ltlf_ctx* c, void* stream, ltlf_tuning* out) {
                 best_i = i;
             }
         }
+        // the built-in choice stays unless another kernel is clearly faster
+        // (measurements of near-equal kernels vary by a few percent)
+        const uint32_t builtin = tile_shape(c->Wp, c->lds_limit, KERNEL_AUTO).kind;
+        for (uint32_t i = 0; i < 3; ++i)
+            if (kind_of[i] == builtin && t.ns_per_candidate[ci][i] > 0 && t.ns_per_candidate[ci][i] <= 1.05 * best)
+                best_i = i;
         t.chunks[ci] = chunks;
         t.kernel[ci] = flag_of[best_i];
         t.bound[ci] = bound;

@@ -606,7 +606,7 @@ struct Cand {
 };
 
 // Hash pass of one candidate: records the hash and issues the first probe
-// (none once the store has overflowed),
+// (once the store has overflowed: neither, the candidate is only checked),
 // unless the candidate is disabled or its CM equals one of its operands
 // (A, or B if given) -- a stored, cheaper CM, so a sure duplicate.  P_WON
 // here only marks "still to probe".
@@ -615,6 +615,10 @@ __device__ __forceinline__ void cand_begin(const Store& s, Cand& c, bool enabled
                                            bool full_store, const uint4* A, const uint4* B, const Emit& e) {
     c.out = P_SKIP;
     if (!enabled) return;
+    if (full_store) {  // only checked: no hash, no duplicate test
+        c.out = P_FULL;
+        return;
+    }
     Hash hs;
     uint32_t ea = 0, eb = 0;
     e([&](uint32_t w, uint4 r) {
@@ -626,7 +630,7 @@ __device__ __forceinline__ void cand_begin(const Store& s, Cand& c, bool enabled
     if (check_eq && (ea == 0 || eb == 0)) return;
     c.h = hs.fin() & s.hmask;
     c.pos = slot_of(s, c.h);
-    c.cur = full_store ? kEmpty : slot_load(&s.table[c.pos]);
+    c.cur = slot_load(&s.table[c.pos]);
     c.out = P_WON;
 }
 
@@ -1056,13 +1060,19 @@ __global__ __launch_bounds__(kLanes) void k_generate_grp(Store s, SegTable t) {
                                         V.z & ~(x.z | (V.z & (sg.z ^ x.z ^ V.z))),
                                         V.w & ~(x.w | (V.w & (sg.w ^ x.w ^ V.w))));
             const bool in = k < NQ;
-            const uint64_t hn = hash_fin(group_xor<G>(in ? chunk_hash(k, rn) : 0));
-            const uint64_t hx = hash_fin(group_xor<G>(in ? chunk_hash(k, rx) : 0));
-            const uint64_t hf = hash_fin(group_xor<G>(in ? chunk_hash(k, rf) : 0));
-            const uint64_t hg = hash_fin(group_xor<G>(in ? chunk_hash(k, rg) : 0));
-            const bool ex = group_none<G>(in && diff4(rx, a) != 0, base);
-            const bool ef = group_none<G>(in && diff4(rf, a) != 0, base);
-            const bool eg = group_none<G>(in && diff4(rg, a) != 0, base);
+            // once the store has overflowed, candidates are only checked (the
+            // flag is uniform over the block: the group reductions stay whole)
+            uint64_t hn = 0, hx = 0, hf = 0, hg = 0;
+            bool ex = false, ef = false, eg = false;
+            if (!full_store) {
+                hn = hash_fin(group_xor<G>(in ? chunk_hash(k, rn) : 0));
+                hx = hash_fin(group_xor<G>(in ? chunk_hash(k, rx) : 0));
+                hf = hash_fin(group_xor<G>(in ? chunk_hash(k, rf) : 0));
+                hg = hash_fin(group_xor<G>(in ? chunk_hash(k, rg) : 0));
+                ex = group_none<G>(in && diff4(rx, a) != 0, base);
+                ef = group_none<G>(in && diff4(rf, a) != 0, base);
+                eg = group_none<G>(in && diff4(rg, a) != 0, base);
+            }
             const bool sn = group_none<G>(in && ((rn.x ^ P.x) & S.x | (rn.y ^ P.y) & S.y | (rn.z ^ P.z) & S.z | (rn.w ^ P.w) & S.w) != 0, base);
             const bool sx = group_none<G>(in && ((rx.x ^ P.x) & S.x | (rx.y ^ P.y) & S.y | (rx.z ^ P.z) & S.z | (rx.w ^ P.w) & S.w) != 0, base);
             const bool sf2 = group_none<G>(in && ((rf.x ^ P.x) & S.x | (rf.y ^ P.y) & S.y | (rf.z ^ P.z) & S.z | (rf.w ^ P.w) & S.w) != 0, base);
@@ -1121,15 +1131,20 @@ __global__ __launch_bounds__(kLanes) void k_generate_grp(Store s, SegTable t) {
             const uint4 s2 = group_add<G>(a, o, base, k);
             const uint4 rV = make_uint4(a.x | (b.x & (s2.x ^ a.x ^ o.x)), a.y | (b.y & (s2.y ^ a.y ^ o.y)),
                                         a.z | (b.z & (s2.z ^ a.z ^ o.z)), a.w | (b.w & (s2.w ^ a.w ^ o.w)));
-            const uint64_t hA = hash_fin(group_xor<G>(in ? chunk_hash(k, rA) : 0));
-            const uint64_t hO = hash_fin(group_xor<G>(in ? chunk_hash(k, o) : 0));
-            const uint64_t hU = hash_fin(group_xor<G>(in ? chunk_hash(k, rU) : 0));
-            const uint64_t hV = hash_fin(group_xor<G>(in ? chunk_hash(k, rV) : 0));
-            // a result equal to an operand is a stored, cheaper CM
-            const bool eA = group_none<G>(in && diff4(rA, a) != 0, base) || group_none<G>(in && diff4(rA, b) != 0, base);
-            const bool eO = group_none<G>(in && diff4(o, a) != 0, base) || group_none<G>(in && diff4(o, b) != 0, base);
-            const bool eU = group_none<G>(in && diff4(rU, a) != 0, base) || group_none<G>(in && diff4(rU, b) != 0, base);
-            const bool eV = group_none<G>(in && diff4(rV, a) != 0, base) || group_none<G>(in && diff4(rV, b) != 0, base);
+            uint64_t hA = 0, hO = 0, hU = 0, hV = 0;
+            bool eA = false, eO = false, eU = false, eV = false;
+            if (!full_store) {  // after an overflow candidates are only checked
+                hA = hash_fin(group_xor<G>(in ? chunk_hash(k, rA) : 0));
+                hO = hash_fin(group_xor<G>(in ? chunk_hash(k, o) : 0));
+                hU = hash_fin(group_xor<G>(in ? chunk_hash(k, rU) : 0));
+                hV = hash_fin(group_xor<G>(in ? chunk_hash(k, rV) : 0));
+                // a result equal to an operand is a stored, cheaper CM (the
+                // second test runs on whole groups: the first is group-uniform)
+                eA = group_none<G>(in && diff4(rA, a) != 0, base) || group_none<G>(in && diff4(rA, b) != 0, base);
+                eO = group_none<G>(in && diff4(o, a) != 0, base) || group_none<G>(in && diff4(o, b) != 0, base);
+                eU = group_none<G>(in && diff4(rU, a) != 0, base) || group_none<G>(in && diff4(rU, b) != 0, base);
+                eV = group_none<G>(in && diff4(rV, a) != 0, base) || group_none<G>(in && diff4(rV, b) != 0, base);
+            }
             const bool sA = group_none<G>(in && ((rA.x ^ P.x) & S.x | (rA.y ^ P.y) & S.y | (rA.z ^ P.z) & S.z | (rA.w ^ P.w) & S.w) != 0, base);
             const bool sO = group_none<G>(in && ((o.x ^ P.x) & S.x | (o.y ^ P.y) & S.y | (o.z ^ P.z) & S.z | (o.w ^ P.w) & S.w) != 0, base);
             const bool sU = group_none<G>(in && ((rU.x ^ P.x) & S.x | (rU.y ^ P.y) & S.y | (rU.z ^ P.z) & S.z | (rU.w ^ P.w) & S.w) != 0, base);
@@ -1267,25 +1282,34 @@ __device__ __forceinline__ void wave_item(const Store& s, WaveAlloc& wa, bool un
     const uint32_t lane = __lane_id();
     uint64_t h[4] = {0, 0, 0, 0};
     uint32_t da[4] = {0, 0, 0, 0}, db[4] = {0, 0, 0, 0}, ck[4] = {0, 0, 0, 0};
+    // once the store has overflowed (uniform over the wave) candidates are
+    // only checked: no hash, no operand-equality test
     wave_pass(s, unary, A, B, nq, [&](uint32_t q, bool in, uint4 a, uint4 b, uint4 r0, uint4 r1, uint4 r2, uint4 r3) {
         if (!in) return;
         const uint4 P = P4[q], S = S4[q];
         const uint4 r[4] = {r0, r1, r2, r3};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            h[j] ^= chunk_hash(q, r[j]);
-            da[j] |= diff4(r[j], a);
-            db[j] |= diff4(r[j], b);
+            if (!full_store) {
+                h[j] ^= chunk_hash(q, r[j]);
+                da[j] |= diff4(r[j], a);
+                db[j] |= diff4(r[j], b);
+            }
             ck[j] |= check_chunk(r[j], P, S);
         }
     });
     bool act[4], sep[4];
-    uint64_t hj[4];
+    uint64_t hj[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        hj[j] = hash_fin(group_xor<64>(h[j])) & s.hmask;
-        // a result equal to an operand is a stored, cheaper CM
-        const bool eq = __ballot(da[j] != 0) == 0 || __ballot(db[j] != 0) == 0;
+        bool eq = false;
+        if (!full_store) {
+            hj[j] = hash_fin(group_xor<64>(h[j])) & s.hmask;
+            // a result equal to an operand is a stored, cheaper CM
+            const bool ea = __ballot(da[j] != 0) == 0;
+            const bool eb = __ballot(db[j] != 0) == 0;
+            eq = ea || eb;
+        }
         act[j] = en[j] && !eq;
         sep[j] = __ballot(ck[j] != 0) == 0;
     }

@@ -43,7 +43,8 @@ def test_autotune_table_and_parity(synth):
     for e in table:
         ns = e["ns_per_candidate"]
         assert ns[e["kernel"]] is not None and ns[e["kernel"]] > 0, e
-        assert ns[e["kernel"]] == min(v for v in ns.values() if v is not None), e
+        # the fastest, or the built-in choice within 5% of it
+        assert ns[e["kernel"]] <= 1.05 * min(v for v in ns.values() if v is not None), e
         assert e["candidates"] > 0
         if e["chunks"] == 1:
             assert ns["group"] is None  # groups need two chunks or more

@@ -107,6 +107,39 @@ def test_overflow_of_the_large_region_is_exact():
     s.close()
 
 
+def test_lookahead_in_the_large_region():
+    """A row limit overflows the level below the minimum: in the server the
+    request moves to the large region, whose look-ahead finds the minimum one
+    level past the overflow, as a solo run and the oracle do (and stops at
+    the overflow with LTLF_FLAG_NO_LOOKAHEAD)."""
+    p = workload.tiny(1)
+    full = oracle.solve(p)
+    c = full.min_cost - 1
+    cap = sum(full.level_counts[1:c]) + full.level_counts[c] - 1
+    s = m.Synthesizer(device=0, workspace_bytes=1 << 30)
+    s.set_row_limit(cap)
+    try:
+        print(f"[server] look-ahead in the large region, row limit {cap}", flush=True)
+        srv = m.Server(s, max_resident=4)
+        t1 = srv.submit(p)
+        t2 = srv.submit(p, flags=m.FLAG_NO_LOOKAHEAD)
+        t3 = srv.submit(workload.tiny(2), 7)
+        got = drain(srv, [t1, t2, t3])
+        srv.close()
+        for t, fl in ((t1, 0), (t2, m.FLAG_NO_LOOKAHEAD)):
+            a = s.solve(p, flags=fl)
+            o = oracle.solve(p, max_rows=cap, lookahead=not fl)
+            r = got[t]
+            key = lambda x: (x.status, x.min_cost, x.levels_done, x.overflow_level, x.checked_level)  # noqa: E731
+            assert key(r) == key(a) == key(o), (fl, r, a, o)
+        assert got[t1].status == m.ltlf.OK and got[t1].min_cost == full.min_cost
+        assert got[t2].status == m.ltlf.CAPACITY
+        assert ev.separates(got[t1].formula, p.traces, p.positive) and ev.cost(got[t1].formula) == full.min_cost
+    finally:
+        s.set_row_limit(0)
+        s.close()
+
+
 def test_cancel_pending_invalid():
     s = m.Synthesizer(device=0, workspace_bytes=1 << 30)
     srv = m.Server(s, max_resident=2)

@@ -303,9 +303,9 @@ LevelPlan plan_level(const ltlf_ctx* c, const ltlf_costs* k, uint32_t lev, const
                 if (ts.square_tri) {
                     const uint64_t T = ceil_div(n, ts.ta);
                     g.tiles = T * (T + 1) / 2;
-                } else {
+                } else {  // b-tile column k holds R(k+1) a-tiles, R = tb / ta
                     const uint64_t K = ceil_div(n, ts.tb);
-                    g.tiles = 8ull * (K - 1) * K + ceil_div(n, ts.ta);
+                    g.tiles = (uint64_t)(ts.tb / ts.ta / 2) * (K - 1) * K + ceil_div(n, ts.ta);
                 }
             } else {
                 // lanes (the right operand) take the larger level
@@ -1601,9 +1601,11 @@ ltlf_status ltlf_autotune(ltlf_ctx* c, void* stream, ltlf_tuning* out) {
         }
         double best = 0;
         uint32_t best_i = 2;
+        // the lane kernel's family: 256-lane tiles, or 128-lane tiles where only those fit
+        auto family = [](uint32_t kind) { return kind == KERNEL_LANE_HALF ? (uint32_t)KERNEL_LANE : kind; };
         for (uint32_t i = 0; i < 3; ++i) {
             t.ns_per_candidate[ci][i] = 0;
-            if (tile_shape(c->Wp, c->lds_limit, kind_of[i]).kind != kind_of[i]) continue;  // does not apply
+            if (family(tile_shape(c->Wp, c->lds_limit, kind_of[i]).kind) != kind_of[i]) continue;  // does not apply
             r = ltlf_result{};
             const ltlf_status st =
                 ltlf_run(c, &k, bound, LTLF_FLAG_EXHAUST | LTLF_FLAG_PROFILE | flag_of[i], stream, &r);
@@ -1618,7 +1620,7 @@ ltlf_status ltlf_autotune(ltlf_ctx* c, void* stream, ltlf_tuning* out) {
         }
         // the built-in choice stays unless another kernel is clearly faster
         // (measurements of near-equal kernels vary by a few percent)
-        const uint32_t builtin = tile_shape(c->Wp, c->lds_limit, KERNEL_AUTO).kind;
+        const uint32_t builtin = family(tile_shape(c->Wp, c->lds_limit, KERNEL_AUTO).kind);
         for (uint32_t i = 0; i < 3; ++i)
             if (kind_of[i] == builtin && t.ns_per_candidate[ci][i] > 0 && t.ns_per_candidate[ci][i] <= 1.05 * best)
                 best_i = i;

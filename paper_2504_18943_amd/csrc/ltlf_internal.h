@@ -129,16 +129,18 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st);
 // tiles of ta left x tb right operands, unary tiles of tu operands; triangular
 // (same-level) pair segments use square tiles if square_tri, else columns of
 // 16(k+1) left tiles per right tile k.
-enum : uint32_t { KERNEL_LANE = 1, KERNEL_GROUP = 2, KERNEL_AUTO = 3, KERNEL_WAVE = 4 };
+enum : uint32_t { KERNEL_LANE = 1, KERNEL_GROUP = 2, KERNEL_AUTO = 3, KERNEL_WAVE = 4, KERNEL_LANE_HALF = 5 };
 struct TileShape {
     uint32_t kind, ta, tb, tu, square_tri;
 };
 // Generation kernel and tile for rows of Wp words.  pref: KERNEL_LANE or
-// KERNEL_GROUP asks for that kernel where it fits, KERNEL_WAVE for the wave
-// kernel, anything else is the default (lane kernel where its tile fits the
-// LDS, else the group kernel for rows of 2..64 chunks, else the wave kernel).
+// KERNEL_GROUP asks for that kernel where it fits (the lane kernel on
+// 128-lane tiles, KERNEL_LANE_HALF, where only those fit), KERNEL_WAVE for
+// the wave kernel, anything else is the default (lane kernel where its
+// 256-lane tile fits the LDS, else the group kernel for rows of 2..64 chunks,
+// else the wave kernel).
 TileShape tile_shape(uint32_t Wp, uint64_t lds_limit, uint32_t pref);
-uint64_t lds_bytes(uint32_t Wp);
+uint64_t lds_bytes(uint32_t Wp, uint32_t lanes);
 // Grid of the generation launch: the tile count, or for the persistent group
 // kernel the resident block count (at most the tile count).
 hipError_t generate_blocks(const Store& s, uint64_t n_tiles, uint64_t& blocks);

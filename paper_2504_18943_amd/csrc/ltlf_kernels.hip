@@ -485,13 +485,16 @@ struct LdsPairEmit {
 };
 
 // ------------------------------------------------------------ tile mapping --
+// Triangular pair grid with b-tiles R times as wide as a-tiles (R even): b-tile
+// column k holds a-tiles [0, R(k+1)) and starts at tile (R/2)k(k+1).
+template <uint32_t R>
 __device__ __forceinline__ void tri_tile(uint64_t lt, uint64_t& ta, uint64_t& tb) {
-    // b-tile column k holds a-tiles [0, 16(k+1)); column k starts at 8k(k+1).
-    uint64_t k = (uint64_t)((sqrt(1.0 + (double)lt * 0.5) - 1.0) * 0.5);
-    while (8ull * (k + 1) * (k + 2) <= lt) ++k;
-    while (k > 0 && 8ull * k * (k + 1) > lt) --k;
+    constexpr uint64_t H = R / 2;
+    uint64_t k = (uint64_t)((sqrt(1.0 + (double)lt * (8.0 / R)) - 1.0) * 0.5);
+    while (H * (k + 1) * (k + 2) <= lt) ++k;
+    while (k > 0 && H * k * (k + 1) > lt) --k;
     tb = k;
-    ta = lt - 8ull * k * (k + 1);
+    ta = lt - H * k * (k + 1);
 }
 
 // ------------------------------------------------------------------ kernels --
@@ -666,13 +669,15 @@ __host__ __device__ __forceinline__ uint32_t lds_stride(uint32_t nq) { return nq
 // hash it and to test it against both operands, the first probes of all
 // operators are issued before any is waited on, and rows and deferral records
 // are allocated with one atomic per counter, wave and pair.  Unary tiles do
-// the same for not, X, F, G over the lane's operand.
-template <int BATCH>
-__global__ __launch_bounds__(kLanes) void k_generate_lds(Store s, SegTable t) {
+// the same for not, X, F, G over the lane's operand.  LANES (256, or 128 for
+// rows whose 256-lane tile does not fit the LDS) is both the workgroup size
+// and the width of a pair tile.
+template <int BATCH, int LANES>
+__global__ __launch_bounds__(LANES) void k_generate_lds(Store s, SegTable t) {
     extern __shared__ uint4 dyn[];
     const uint32_t NQ = s.Wp / 4, SB = lds_stride(NQ);
     uint4* sh_b = dyn;
-    uint4* sh_a = sh_b + kLanes * SB;
+    uint4* sh_a = sh_b + LANES * SB;
     uint4* sh_v = sh_a + kTileA * NQ;
     uint4* sh_s = sh_v + NQ;
     uint4* sh_p = sh_s + NQ;
@@ -686,7 +691,7 @@ __global__ __launch_bounds__(kLanes) void k_generate_lds(Store s, SegTable t) {
     const uint64_t lt = tile - t.first[si];
     const uint32_t tid = threadIdx.x;
     const uint4* rows4 = reinterpret_cast<const uint4*>(s.rows);
-    for (uint32_t q = tid; q < NQ; q += kLanes) {
+    for (uint32_t q = tid; q < NQ; q += LANES) {
         sh_v[q] = reinterpret_cast<const uint4*>(s.V)[q];
         sh_s[q] = reinterpret_cast<const uint4*>(s.S)[q];
         sh_p[q] = reinterpret_cast<const uint4*>(s.P0)[q];
@@ -702,7 +707,7 @@ __global__ __launch_bounds__(kLanes) void k_generate_lds(Store s, SegTable t) {
             ++count;
         }
     } else if (g.kind == SEG_UNARY) {
-        const uint64_t vl = lt * kLanes + tid;
+        const uint64_t vl = lt * LANES + tid;
         const bool ok = vl < g.nb;
         const uint32_t vi = (uint32_t)(g.b0 + (ok ? vl : 0));
         for (uint32_t q = 0; q < NQ; ++q) mine[q] = ok ? rows4[(uint64_t)vi * NQ + q] : make_uint4(0, 0, 0, 0);
@@ -739,17 +744,17 @@ __global__ __launch_bounds__(kLanes) void k_generate_lds(Store s, SegTable t) {
     } else {
         uint64_t ta, tb;
         if (g.tri) {
-            tri_tile(lt, ta, tb);
+            tri_tile<LANES / kTileA>(lt, ta, tb);
         } else {
-            const uint64_t tiles_b = (g.nb + kLanes - 1) / kLanes;
+            const uint64_t tiles_b = (g.nb + LANES - 1) / LANES;
             ta = lt / tiles_b;
             tb = lt % tiles_b;
         }
-        for (uint32_t idx = tid; idx < kTileA * NQ; idx += kLanes) {
+        for (uint32_t idx = tid; idx < kTileA * NQ; idx += LANES) {
             const uint64_t al = ta * kTileA + idx / NQ;
             sh_a[idx] = al < g.na ? rows4[(g.a0 + al) * NQ + idx % NQ] : make_uint4(0, 0, 0, 0);
         }
-        const uint64_t bl = tb * kLanes + tid;
+        const uint64_t bl = tb * LANES + tid;
         const bool valid = bl < g.nb;
         const uint32_t bi = (uint32_t)(g.b0 + (valid ? bl : 0));
         for (uint32_t q = 0; q < NQ; ++q) mine[q] = valid ? rows4[(uint64_t)bi * NQ + q] : make_uint4(0, 0, 0, 0);
@@ -2157,9 +2162,9 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st) 
 #endif
 constexpr int kBatch = LTLF_BATCH;
 
-uint64_t lds_bytes(uint32_t Wp) {
+uint64_t lds_bytes(uint32_t Wp, uint32_t lanes) {
     const uint32_t nq = Wp / 4;
-    return 16ull * (kLanes * lds_stride(nq) + kTileA * nq + 3ull * nq);
+    return 16ull * ((uint64_t)lanes * lds_stride(nq) + kTileA * nq + 3ull * nq);
 }
 
 static uint64_t grp_lds_bytes(uint32_t Wp) {
@@ -2176,12 +2181,15 @@ static uint32_t group_size(uint32_t nq) {
 TileShape tile_shape(uint32_t Wp, uint64_t lds_limit, uint32_t pref) {
     const uint32_t nq = Wp / 4;
     const bool group_fits = nq >= 2 && nq <= 64 && grp_lds_bytes(Wp) <= lds_limit;
-    const bool lane_fits = lds_bytes(Wp) <= lds_limit;
+    const bool lane_fits = lds_bytes(Wp, kLanes) <= lds_limit;
+    const bool half_fits = lds_bytes(Wp, kLanes / 2) <= lds_limit;
     const TileShape group{KERNEL_GROUP, kGA, kGB, kGU, 1}, lane{KERNEL_LANE, kTileA, kLanes, kLanes, 0};
+    const TileShape half{KERNEL_LANE_HALF, kTileA, kLanes / 2, kLanes / 2, 0};
     const TileShape wave{KERNEL_WAVE, kWA, kWB, kWU, 1};
     if (pref == KERNEL_WAVE) return wave;
     if (pref == KERNEL_GROUP && group_fits) return group;
     if (lane_fits) return lane;
+    if (pref == KERNEL_LANE && half_fits) return half;  // the lane kernel on half-width tiles
     if (group_fits) return group;
     return wave;
 }
@@ -2249,10 +2257,15 @@ hipError_t launch_generate(const Store& s, const SegTable& t, uint64_t blocks, h
         if (blocks == 0 || blocks > n) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_generate_wave, dim3((uint32_t)blocks), block, 0, st, s, t);
     } else if (s.kernel == KERNEL_LANE) {
-        const uint64_t lds = lds_bytes(s.Wp);
-        e = raise_lds(k_generate_lds<kBatch>, lds);
+        const uint64_t lds = lds_bytes(s.Wp, kLanes);
+        e = raise_lds(k_generate_lds<kBatch, kLanes>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_generate_lds<kBatch>, grid, block, (uint32_t)lds, st, s, t);
+        hipLaunchKernelGGL((k_generate_lds<kBatch, kLanes>), grid, block, (uint32_t)lds, st, s, t);
+    } else if (s.kernel == KERNEL_LANE_HALF) {
+        const uint64_t lds = lds_bytes(s.Wp, kLanes / 2);
+        e = raise_lds(k_generate_lds<kBatch, kLanes / 2>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_generate_lds<kBatch, kLanes / 2>), grid, dim3(kLanes / 2), (uint32_t)lds, st, s, t);
     } else {
         return hipErrorInvalidValue;
     }

@@ -252,13 +252,14 @@ def test_edge_long_traces_cross_words(synth):
 
 
 @pytest.mark.parametrize("shape", [(8, 8, 2, 6), (16, 16, 3, 9), (20, 20, 8, 16), (30, 30, 16, 24),
-                                   (40, 40, 40, 64), (60, 60, 60, 64), (90, 90, 60, 64)],
-                         ids=["rows-1q", "rows-2q", "rows-5q", "rows-16q", "rows-33q", "rows-60q",
+                                   (40, 40, 40, 64), (48, 48, 40, 64), (60, 60, 60, 64), (90, 90, 60, 64)],
+                         ids=["rows-1q", "rows-2q", "rows-5q", "rows-16q", "rows-33q", "rows-40q", "rows-60q",
                               "rows-90q"])
-@pytest.mark.parametrize("kflag", [0, m.FLAG_KERNEL_GROUP, m.FLAG_KERNEL_WAVE], ids=["default", "group", "wave"])
+@KERNELS
 def test_edge_row_widths(synth, shape, kflag):
-    """Row widths across the lane kernel's LDS limit, the group sizes (4..64
-    lanes per candidate) and past them (wave kernel)."""
+    """Row widths across the lane kernel's LDS limits (256-lane tiles up to
+    ~37 chunks, 128-lane tiles up to ~67 under the lane flag), the group
+    sizes (4..64 lanes per candidate) and past them (wave kernel)."""
     npos, nneg, lo, hi = shape
     p = workload.make_problem(21, 3, npos, nneg, lo, hi, 5, 5, q_range=(0.3, 0.7), name=f"wide{hi}")
     compare(synth, p, 4, exhaust=True, flags=kflag)

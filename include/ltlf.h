@@ -98,8 +98,9 @@ typedef struct {
                                   with HIP events on the run's stream and
                                   report the sums (gen_ms, verify_ms) */
 #define LTLF_FLAG_KERNEL_LANE 0x4u /* generation with one candidate per lane where
-                                  its operand tile fits the LDS (the default
-                                  choice wherever it fits) */
+                                  its operand tile (256 or 128 lanes wide) fits
+                                  the LDS (the default choice wherever it
+                                  fits) */
 #define LTLF_FLAG_KERNEL_GROUP 0x8u /* generation with one candidate per group
                                   of lanes (one 16-byte chunk per lane) where
                                   rows have 2..64 chunks;
@@ -263,8 +264,9 @@ typedef struct {
 ltlf_status ltlf_autotune(ltlf_ctx *ctx, void *stream, ltlf_tuning *out);
 
 /* Installs a tuning table (e.g. one measured earlier on another context);
- * NULL restores the built-in choice (lane where its tile fits the LDS, else
- * group up to 64 chunks, else wave).  EINVAL: n_classes > LTLF_TUNE_CLASSES,
+ * NULL restores the built-in choice (lane where its 256- or 128-lane tile
+ * fits the LDS, up to about 67 chunks, else group up to 64 chunks, else
+ * wave).  EINVAL: n_classes > LTLF_TUNE_CLASSES,
  * a chunks entry of 0 or a kernel entry that is not one of the three flags. */
 ltlf_status ltlf_ctx_set_tuning(ltlf_ctx *ctx, const ltlf_tuning *tuning);
 

@@ -460,13 +460,19 @@ ltlf_status validate_spec(const ltlf_spec* sp) {
 }
 
 
+// Built-in choice: the lane kernel wherever one of its tiles (256 or 128
+// lanes) fits the LDS, else the group kernel up to 64 chunks, else the wave
+// kernel (measured: the 128-lane form beats group and wave by 1.5..2x at
+// 38..64 chunks).
+constexpr uint32_t kBuiltinPref = KERNEL_LANE;
+
 // The measured kernel for the loaded row width: the tuning class nearest to
-// it on a log scale; KERNEL_AUTO (the built-in rule) without a table.
+// it on a log scale; the built-in choice without a table.
 uint32_t tuned_kernel(const ltlf_ctx* c) {
-    if (c->tune.empty()) return KERNEL_AUTO;
+    if (c->tune.empty()) return kBuiltinPref;
     const double w = std::log((double)std::max<uint32_t>(1, c->Wp / 4));
     double best = 1e300;
-    uint32_t kind = KERNEL_AUTO;
+    uint32_t kind = kBuiltinPref;
     for (const auto& t : c->tune) {
         const double d = std::fabs(std::log((double)t.first) - w);
         if (d < best) {
@@ -1620,7 +1626,7 @@ ltlf_status ltlf_autotune(ltlf_ctx* c, void* stream, ltlf_tuning* out) {
         }
         // the built-in choice stays unless another kernel is clearly faster
         // (measurements of near-equal kernels vary by a few percent)
-        const uint32_t builtin = family(tile_shape(c->Wp, c->lds_limit, KERNEL_AUTO).kind);
+        const uint32_t builtin = family(tile_shape(c->Wp, c->lds_limit, kBuiltinPref).kind);
         for (uint32_t i = 0; i < 3; ++i)
             if (kind_of[i] == builtin && t.ns_per_candidate[ci][i] > 0 && t.ns_per_candidate[ci][i] <= 1.05 * best)
                 best_i = i;

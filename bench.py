@@ -59,6 +59,27 @@ def profiled_traffic(kernel_prefix: str, workload_tag: str):
     return None, None
 
 
+def profiled_counters(kernel_prefix: str, workload_tag: str):
+    """Per-launch hardware counters (atomics, L2 requests, hits, misses) of
+    the dominant kernel from a committed rocprofv3 summary taken on the
+    current kernel source and workload; else None."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2504_18943_amd", "csrc", "ltlf_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
+        fields = {}
+        for line in open(path):
+            if ":" in line:
+                key, _, val = line.partition(":")
+                fields[key.strip()] = val.strip()
+        if (fields.get("kernel_source_sha256") == sha and workload_tag in fields.get("command", "")
+                and fields.get("dominant_kernel", "").startswith(kernel_prefix)
+                and "TCC_ATOMIC_sum_per_launch" in fields):
+            return {k: float(v) for k, v in fields.items() if k.endswith("_per_launch")}, os.path.basename(path)
+    return None, None
+
+
 def cpu_baseline(seed: int, bound: int):
     import oracle
     import workload
@@ -297,6 +318,20 @@ def main() -> int:
             "kernel": "generation (k_generate*)", "launches_per_step": launches,
             "avg_launch_ms": round(gen_ms / max(launches, 1), 4),
             "bytes_per_candidate": last.row_bytes + 8}
+    # hash-probe and atomic rates: every candidate that differs from its
+    # operands probes at least one slot; atomics and L2 requests per launch
+    # from the committed counter summary, over the live launch time
+    counters, ctr_file = profiled_counters("ltlf::k_generate", f"--bound {args.bound} ")
+    launch_s = gen_ms / max(launches, 1) / 1e3
+    roof["rates"] = {
+        "candidates_per_s": round(last.candidates / (gen_ms / 1e3)) if gen_ms > 0 else None,
+        "atomics_per_s": round(counters["TCC_ATOMIC_sum_per_launch"] / launch_s) if counters else None,
+        "atomics_to_memory_per_s": round(counters["TCC_EA0_ATOMIC_sum_per_launch"] / launch_s) if counters else None,
+        "l2_requests_per_s": round(counters["TCC_REQ_sum_per_launch"] / launch_s) if counters else None,
+        "l2_hit_rate": round(counters["TCC_HIT_sum_per_launch"] / (counters["TCC_HIT_sum_per_launch"]
+                                                                   + counters["TCC_MISS_sum_per_launch"]), 4)
+        if counters else None,
+        "counters_source": ctr_file}
 
     ttf = None
     if not args.no_ttf:

@@ -59,6 +59,31 @@ def profiled_traffic(kernel_prefix: str, workload_tag: str):
     return None, None
 
 
+def large_config(synth, bound: int):
+    """Large configuration (5 props, 512+512 traces, lengths 16-64, seed 1):
+    every level to `bound` (its 328-chunk rows run on the wave kernel);
+    unique semantics per second and the generation kernels' algorithmic
+    GB/s, (row bytes + 8) per candidate over their summed launch time."""
+    import torch
+    import workload
+
+    p = workload.large(1)
+    synth.load(p)
+    synth.run(bound, flags=0x1)  # warm-up
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    r = synth.run(bound, flags=0x1 | 0x2)  # EXHAUST | PROFILE
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - a) * 1e3
+    gbs = r.candidates * (r.row_bytes + 8) / (r.gen_ms / 1e3) / 1e9 if r.gen_ms > 0 else 0.0
+    log(f"[bench] large config to cost {bound}: {ms:.1f} ms, {gbs:.0f} GB/s")
+    return {"workload": "large synthesis problem (5 props, 512+512 traces, lengths 16-64, planted cost 13, seed 1)",
+            "cost_bound": bound, "row_bytes": r.row_bytes, "ms": round(ms, 2),
+            "unique_per_s": round(r.unique_total / (ms / 1e3), 1), "unique_per_level": r.level_counts[1:bound + 1],
+            "candidates": r.candidates, "gen_ms": round(r.gen_ms, 3), "kernel_bound": "hbm",
+            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def profiled_counters(kernel_prefix: str, workload_tag: str):
     """Per-launch hardware counters (atomics, L2 requests, hits, misses) of
     the dominant kernel from a committed rocprofv3 summary taken on the
@@ -241,6 +266,8 @@ def main() -> int:
     ap.add_argument("--batched", type=int, default=256,
                     help="problems of the batched configuration solved one by one and with "
                          "ltlf_solve_batch (0 = skip)")
+    ap.add_argument("--large-bound", type=int, default=9,
+                    help="enumerate the large configuration to this cost (0 = skip)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="run the batched and served legs with the built-in kernel choice")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
@@ -368,6 +395,8 @@ def main() -> int:
     if args.served > 0:
         served = served_compare(synth, args.served, args.served_outliers)
 
+    large = large_config(synth, args.large_bound) if args.large_bound > 0 else None
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.seed, args.cpu_bound)
     if cpu:
         log(f"[bench] cpu baseline {cpu['value']:.0f} unique/s")
@@ -393,6 +422,7 @@ def main() -> int:
                    "candidates": last.candidates, "deferred": last.deferred,
                    "status": last.status_name, "min_cost": last.min_cost},
         "time_to_formula": ttf,
+        "large": large,
         "autotune": tuning,
         "batched": batched,
         "served": served,

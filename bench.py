@@ -288,7 +288,7 @@ def main() -> int:
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); independent problems "
-              "shard across GPUs without communication, which this build does not launch.",
+              "would shard across GPUs without communication, and no multi-GPU path is implemented.",
               file=sys.stderr)
         return 2
 

@@ -77,11 +77,20 @@ def large_config(synth, bound: int):
     ms = (time.perf_counter() - a) * 1e3
     gbs = r.candidates * (r.row_bytes + 8) / (r.gen_ms / 1e3) / 1e9 if r.gen_ms > 0 else 0.0
     log(f"[bench] large config to cost {bound}: {ms:.1f} ms, {gbs:.0f} GB/s")
+    # the configuration's own solve: bound 16, stop at the first separating level
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    sol = synth.solve(p)
+    torch.cuda.synchronize()
+    ttf = (time.perf_counter() - a) * 1e3
     return {"workload": "large synthesis problem (5 props, 512+512 traces, lengths 16-64, planted cost 13, seed 1)",
             "cost_bound": bound, "row_bytes": r.row_bytes, "ms": round(ms, 2),
             "unique_per_s": round(r.unique_total / (ms / 1e3), 1), "unique_per_level": r.level_counts[1:bound + 1],
             "candidates": r.candidates, "gen_ms": round(r.gen_ms, 3), "kernel_bound": "hbm",
-            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "solve": {"cost_bound": p.cost_bound, "status": sol.status_name, "min_cost": sol.min_cost,
+                      "formula": sol.formula, "time_to_formula_ms": round(ttf, 2),
+                      "includes": "host-to-device upload of the specification"}}
 
 
 def profiled_counters(kernel_prefix: str, workload_tag: str):

@@ -1237,12 +1237,22 @@ __device__ __forceinline__ void wave_pass(const Store& s, bool unary, const uint
     const uint4* V4 = reinterpret_cast<const uint4*>(s.V);
     uint32_t c0 = 0, c1 = 0, c2 = 0;
     const uint32_t steps = (nq + 63) / 64;
+    // the next step's operand chunks are loaded while this step computes
+    const uint32_t lane = __lane_id();
+    uint4 a_nx = load_if(lane < nq, &A[lane]);
+    uint4 b_nx = load_if(lane < nq && !unary, &B[lane]);
+    uint4 v_nx = load_if(lane < nq && unary, &V4[lane]);
     for (uint32_t st = 0; st < steps; ++st) {
-        const uint32_t q = st * 64 + __lane_id();
+        const uint32_t q = st * 64 + lane;
         const bool in = q < nq;
-        const uint4 a = load_if(in, &A[q]);
+        const uint4 a = a_nx, b_cur = b_nx, v_cur = v_nx;
+        const uint32_t qn = q + 64;
+        const bool in_nx = st + 1 < steps && qn < nq;
+        a_nx = load_if(in_nx, &A[qn]);
+        b_nx = load_if(in_nx && !unary, &B[qn]);
+        v_nx = load_if(in_nx && unary, &V4[qn]);
         if (unary) {
-            const uint4 V = load_if(in, &V4[q]);
+            const uint4 V = v_cur;
             const uint4 rn = make_uint4(~a.x & V.x, ~a.y & V.y, ~a.z & V.z, ~a.w & V.w);
             const uint4 rx = x_chunk(a, wave_shift_in(a, c0), V);
             const uint4 sf = wave_add(a, V, c1);
@@ -1256,7 +1266,7 @@ __device__ __forceinline__ void wave_pass(const Store& s, bool unary, const uint
                                         V.w & ~(x.w | (V.w & (sg.w ^ x.w ^ V.w))));
             body(q, in, a, a, rn, rx, rf, rg);
         } else {
-            const uint4 b = load_if(in, &B[q]);
+            const uint4 b = b_cur;
             const uint4 o = make_uint4(a.x | b.x, a.y | b.y, a.z | b.z, a.w | b.w);
             const uint4 rA = make_uint4(a.x & b.x, a.y & b.y, a.z & b.z, a.w & b.w);
             const uint4 s1 = wave_add(b, o, c1);

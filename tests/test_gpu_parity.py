@@ -319,3 +319,31 @@ def test_formula_buffer_too_small(synth):
     st = L.ltlf_run(synth._ctx, oracle.UNIT_ALL, 1, 10, 0, synth._stream(), res)
     assert st == L.EBUFSZ
     assert res.formula_len > 3 and res.min_cost == 7
+
+
+def test_wide_rows_kernels_agree_beyond_the_oracle():
+    """40-chunk rows (the lane kernel's 128-lane tiles by default): up to cost
+    11 (~6e6 CMs at the top level) the lane, group and wave kernels, three
+    independent generators, must give identical level counts, and identical
+    CM sets for every level up to 9; levels up to 7 also equal the oracle."""
+    p = workload.make_problem(22, 3, 48, 48, 40, 64, 9, 9, q_range=(0.3, 0.7), name="wide40")
+    s = m.Synthesizer(device=0, workspace_bytes=16 << 30)
+    try:
+        runs = {}
+        for name, fl in (("lane", m.FLAG_KERNEL_LANE), ("group", m.FLAG_KERNEL_GROUP), ("wave", m.FLAG_KERNEL_WAVE)):
+            print(f"[parity] wide40 bound 11 kernel {name}", flush=True)
+            r = s.solve(p, cost_bound=11, flags=m.FLAG_EXHAUST | fl)
+            assert r.levels_done == 11 and r.overflow_level == 0, (name, r)
+            runs[name] = (r, [sorted_rows(s.export_level(c)) for c in range(1, 10)])
+        base_r, base_sets = runs["lane"]
+        assert base_r.level_counts[11] > 1_000_000
+        for name, (r, sets) in runs.items():
+            assert (r.status, r.min_cost, r.level_counts) == (base_r.status, base_r.min_cost, base_r.level_counts), name
+            for c, (a, b) in enumerate(zip(sets, base_sets), start=1):
+                assert np.array_equal(a, b), (name, c)
+        o = oracle.solve(p, cost_bound=7, exhaust=True)
+        assert base_r.level_counts[:8] == o.level_counts[:8]
+        for c in range(1, 8):
+            assert np.array_equal(base_sets[c - 1], sorted_rows(o.export_level(c))), c
+    finally:
+        s.close()

@@ -110,7 +110,8 @@ def profiled_counters(kernel_prefix: str, workload_tag: str):
         if (fields.get("kernel_source_sha256") == sha and workload_tag in fields.get("command", "")
                 and fields.get("dominant_kernel", "").startswith(kernel_prefix)
                 and "TCC_ATOMIC_sum_per_launch" in fields):
-            return {k: float(v) for k, v in fields.items() if k.endswith("_per_launch")}, os.path.basename(path)
+            return ({k: float(v) for k, v in fields.items() if k.endswith("_per_launch") or k.endswith("_weighted")},
+                    os.path.basename(path))
     return None, None
 
 
@@ -367,6 +368,8 @@ def main() -> int:
         "l2_hit_rate": round(counters["TCC_HIT_sum_per_launch"] / (counters["TCC_HIT_sum_per_launch"]
                                                                    + counters["TCC_MISS_sum_per_launch"]), 4)
         if counters else None,
+        "valu_busy_pct": counters.get("VALUBusy_pct_time_weighted") if counters else None,
+        "valu_utilization_pct": counters.get("VALUUtilization_pct_time_weighted") if counters else None,
         "counters_source": ctr_file}
 
     ttf = None

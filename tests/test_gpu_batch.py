@@ -28,8 +28,8 @@ def big():
 
 
 def check(r, o, p):
-    assert (r.status, r.min_cost, r.levels_done, r.overflow_level) == \
-        (o.status, o.min_cost, o.levels_done, o.overflow_level), (p.name, r, o)
+    assert (r.status, r.min_cost, r.levels_done, r.overflow_level, r.checked_level) == \
+        (o.status, o.min_cost, o.levels_done, o.overflow_level, o.checked_level), (p.name, r, o)
     assert r.level_counts[: o.levels_done + 1] == o.level_counts[: o.levels_done + 1], p.name
     if r.status == m.ltlf.OK:
         assert ev.separates(r.formula, p.traces, p.positive), (p.name, r.formula)

@@ -117,3 +117,15 @@ def test_split_rejects_grammar_without_conjunction(synth):
     p = workload.tiny(1)
     with pytest.raises(m.LtlfError):
         synth.solve_split(p, op_cost=(0, 1, 1, 1, 0, 1, 1))
+
+
+def test_no_split_needed_is_the_minimal_solve(synth):
+    """Without a trace limit and with a solvable part, the recursion ends at
+    the root: one part, no split, the minimal cost of the plain solve."""
+    p = workload.tiny(4)
+    print(f"[split] {p.name} unsplit", flush=True)
+    r = synth.solve_split(p)
+    o = oracle.solve(p)
+    assert (r.parts_solved, r.parts_split, r.depth) == (1, 0, 1)
+    assert r.cost == o.min_cost and r.max_part_cost == o.min_cost
+    check_formula(p, r)

@@ -37,6 +37,19 @@ constexpr uint32_t kMaxTokens = kMaxBound + 1;
 constexpr uint64_t kStagingBytes = 8ull << 20;
 constexpr uint64_t kMinTableSlots = 1ull << 12;
 constexpr uint64_t kLookaheadTiles = 1ull << 30;  // tiles per look-ahead launch (grid limit)
+// Candidates per launch of the one-block-per-tile kernels (at most the
+// deferral list): a candidate that meets a row of its own launch is
+// deferred and verified afterwards, so smaller launches defer fewer.
+#ifndef LTLF_LAUNCH_CANDIDATES
+#define LTLF_LAUNCH_CANDIDATES (1ull << 27)
+#endif
+constexpr uint64_t kLaunchCandidates = LTLF_LAUNCH_CANDIDATES;
+// Largest deferral list 0 (records of 16 bytes; the list gets 1/1024 of the
+// workspace up to this)
+#ifndef LTLF_DEFER_MAX
+#define LTLF_DEFER_MAX (1ull << 27)
+#endif
+constexpr uint64_t kDeferMax = LTLF_DEFER_MAX;
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 inline uint64_t pow2_ceil(uint64_t x) {
@@ -157,7 +170,7 @@ ltlf_status plan_memory_impl(ltlf_ctx* c) {
     if (off >= c->ws_bytes) return LTLF_ENOMEM;
     uint64_t rest = c->ws_bytes - off;
 
-    uint64_t d0 = std::min<uint64_t>(std::max<uint64_t>(rest / 64 / 16, 1ull << 16), 1ull << 26);
+    uint64_t d0 = std::min<uint64_t>(std::max<uint64_t>(rest / 64 / 16, 1ull << 16), kDeferMax);
     uint64_t d1 = std::max<uint64_t>(d0 / 16, 4096);
     if ((d0 + d1) * 16 + 4096 >= rest) return LTLF_ENOMEM;
     c->st.def0 = reinterpret_cast<uint4*>(take(16 * d0));
@@ -697,7 +710,8 @@ struct LevelRun {
             // the deferral list
             uint64_t tile = 0;
             while (tile < total) {
-                uint64_t budget = c->st.def0_cap, end = tile;
+                const uint64_t launch_cap = std::min<uint64_t>(c->st.def0_cap, kLaunchCandidates);
+                uint64_t budget = launch_cap, end = tile;
                 uint32_t si = 0;
                 while (end < total) {
                     while (t.first[si + 1] <= end) ++si;
@@ -710,7 +724,7 @@ struct LevelRun {
                     budget -= take * per;
                 }
                 if (end == tile) return fail(c, LTLF_EDEVICE, "a tile exceeds the deferral list");
-                const uint64_t chunk = c->st.def0_cap - budget;  // candidates, upper bound
+                const uint64_t chunk = launch_cap - budget;  // candidates, upper bound
                 if (2 * (rows_ub + chunk) > c->st.tsize) {
                     TRY(read_counters(c, s));
                     rows_ub = std::min<uint64_t>(c->h_ctr[C_ROWS], c->st.cap);

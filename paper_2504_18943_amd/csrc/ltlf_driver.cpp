@@ -50,6 +50,12 @@ constexpr uint64_t kLaunchCandidates = LTLF_LAUNCH_CANDIDATES;
 #define LTLF_DEFER_MAX (1ull << 27)
 #endif
 constexpr uint64_t kDeferMax = LTLF_DEFER_MAX;
+// Share of the resident block slots (eighths) the large region's persistent
+// launches take while small problems are on the device
+#ifndef LTLF_BUSY_EIGHTHS
+#define LTLF_BUSY_EIGHTHS 7
+#endif
+constexpr uint32_t kBusyEighths = LTLF_BUSY_EIGHTHS;
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 inline uint64_t pow2_ceil(uint64_t x) {
@@ -913,7 +919,7 @@ struct Scheduler {
             const uint32_t lev = j->lev + 1;
             // persistent launches leave block slots to the small pool's
             // launches while it has work
-            r.grid_eighths = small_busy.load(std::memory_order_relaxed) ? 7 : 8;
+            r.grid_eighths = small_busy.load(std::memory_order_relaxed) ? kBusyEighths : 8;
             st = r.level(lev, big_stream);
             if (st != LTLF_OK) break;
             j->lev = lev;

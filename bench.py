@@ -131,14 +131,33 @@ def cpu_baseline(seed: int, bound: int):
 
 
 def compare_results(ps, xs, ys):
-    """Per problem, status, minimal cost, levels done and level counts must
-    agree; a pair where either side overflowed its store may differ (the
-    scheduler's large region is smaller than the whole workspace: results
-    are identical unless the store overflows).  Returns the names of those."""
+    """Exactness of two solves of the same problems (one by one against
+    batched or served).  Per problem, every level both sides stored has the
+    same count and the same digest (the set of CMs); with no overflow on
+    either side, status, minimal cost, levels_done and every count and
+    digest are identical.  A side whose store overflowed (the scheduler's
+    large region is smaller than the whole workspace) may differ only as an
+    overflow allows: counts and digests of the levels both stored are equal;
+    if both found a formula the minimal costs are equal; a CAPACITY side
+    rules out every formula up to its checked_level, so the other side's
+    minimal cost, if any, lies above it.  Returns the names of the problems
+    that differ by capacity; any other difference raises."""
     capacity = []
     for p, a, b in zip(ps, xs, ys):
-        if (a.status, a.min_cost, a.levels_done, a.level_counts) != (b.status, b.min_cost, b.levels_done, b.level_counts):
-            assert a.overflow_level or b.overflow_level, p.name
+        both = min(a.levels_done, b.levels_done)
+        assert a.level_counts[: both + 1] == b.level_counts[: both + 1], p.name
+        assert a.level_digests[: both + 1] == b.level_digests[: both + 1], p.name
+        if not a.overflow_level and not b.overflow_level:
+            assert (a.status, a.min_cost, a.levels_done, a.level_counts, a.level_digests) == \
+                (b.status, b.min_cost, b.levels_done, b.level_counts, b.level_digests), p.name
+            continue
+        if a.status == 0 and b.status == 0:  # OK on both sides
+            assert a.min_cost == b.min_cost, p.name
+        for x, y in ((a, b), (b, a)):
+            if x.status == 2:  # CAPACITY: nothing of cost <= checked_level separates
+                assert y.status != 0 or y.min_cost > x.checked_level, p.name
+        if (a.status, a.min_cost, a.levels_done, a.overflow_level, a.level_counts) != \
+                (b.status, b.min_cost, b.levels_done, b.overflow_level, b.level_counts):
             capacity.append(p.name)
     return capacity
 

@@ -48,6 +48,8 @@ typedef enum {
     LTLF_NOT_FOUND = 1,  /* no separating formula of cost <= bound */
     LTLF_CAPACITY = 2,   /* the store filled before the bound; levels_done is exact */
     LTLF_PENDING = 3,    /* server: the request has not finished yet */
+    LTLF_CANCELLED = 4,  /* stopped between levels by ltlf_ctx_cancel; levels_done,
+                            the level counts and checked_level are exact */
     LTLF_EINVAL = -1,    /* invalid argument (see each call) */
     LTLF_ENOMEM = -2,    /* device memory could not be obtained */
     LTLF_EDEVICE = -3,   /* a HIP runtime call failed */
@@ -119,14 +121,20 @@ typedef struct {
                                   candidate of the overflowed level, generated
                                   again.  min_cost is then exact up to
                                   overflow_level + 1 (checked_level) */
+#define LTLF_FLAG_DIGEST 0x40u /* compute each stored level's digest (a
+                                  fingerprint of the level's set of CMs,
+                                  independent of their order; defined at
+                                  ltlf_result.level_digests) when the level
+                                  closes: one extra read of its rows */
 #define LTLF_FLAG_DEBUG_WEAK_HASH 0x100u /* test hook: keep 6 bits of every hash,
                                   so all candidates share a few slots and one
                                   tag; exercises the verify/defer paths */
 
 /* Result of a run.  level_counts and formula are caller buffers (host). */
 typedef struct {
-    ltlf_status status;       /* OK, NOT_FOUND or CAPACITY */
-    uint32_t min_cost;        /* valid iff status == OK */
+    ltlf_status status;       /* OK, NOT_FOUND, CAPACITY or CANCELLED */
+    uint32_t min_cost;        /* valid iff status == OK (or CANCELLED after a
+                                 completed level that separates) */
     uint32_t levels_done;     /* highest completely enumerated and stored level */
     uint32_t overflow_level;  /* level that did not fit the store, 0 if none */
     uint64_t *level_counts;   /* in: buffer of level_counts_len entries or NULL;
@@ -155,6 +163,27 @@ typedef struct {
     uint64_t dead_rows;       /* out: row indices taken but left unused (the
                                  allocation tails of the persistent kernels);
                                  each level is compacted at its end (statistics) */
+    uint64_t *level_digests;  /* in: buffer of level_counts_len entries or NULL;
+                                 out: with LTLF_FLAG_DIGEST, entry c = digest of
+                                 U_c for 1 <= c <= levels_done, 0 elsewhere (all
+                                 0 without the flag).  digest(U_c) = sum mod 2^64
+                                 over the CMs of U_c of D(row), where row is the
+                                 CM in the packed layout below, cut into 16-byte
+                                 chunks k = 0, 1, ... (little-endian 64-bit
+                                 halves a = bytes 0..7, b = bytes 8..15):
+                                   m_k = (a ^ (k+1) * 0x9E3779B97F4A7C15) * 0xBF58476D1CE4E5B9
+                                   m_k ^= (b + (m_k >> 31)) * 0x94D049BB133111EB
+                                   m_k ^= m_k >> 29
+                                   D = fmix64(m_0 ^ m_1 ^ ...)  (MurmurHash3's
+                                 64-bit finaliser; all arithmetic mod 2^64).
+                                 Packed layout: trace t of length n_t occupies
+                                 bits o_t .. o_t + n_t of a little-endian bit
+                                 string (o_0 = 0, o_{t+1} = o_t + n_t + 1);
+                                 position k of trace t is bit o_t + n_t - 1 - k,
+                                 bit o_t + n_t is 0; the string is zero-padded
+                                 to W = 4 * ceil(ceil(o_T / 32) / 4) 32-bit
+                                 words (row_bytes = 4 W).  Equal sets have equal
+                                 digests, on any path (single, batched, served) */
 } ltlf_result;
 
 typedef struct ltlf_ctx ltlf_ctx;
@@ -180,6 +209,20 @@ ltlf_status ltlf_ctx_set_workspace(ltlf_ctx *ctx, void *dev_ptr, uint64_t bytes)
  * run ends there (status CAPACITY unless a separating formula was found).
  * Takes effect at the next ltlf_run.  EINVAL: ctx == NULL. */
 ltlf_status ltlf_ctx_set_row_limit(ltlf_ctx *ctx, uint64_t max_rows);
+
+/* Ask the context's running (or next) ltlf_run / ltlf_solve /
+ * ltlf_solve_batch to stop.  The only call that may be made from another
+ * thread while the context is in use.  The level loop takes the request
+ * between two levels (a level that has started is completed): the run then
+ * returns LTLF_CANCELLED with levels_done, level_counts and checked_level
+ * exact for the levels it completed, and min_cost and formula filled if one
+ * of them already separates (as for LTLF_OK).  A batch ends every problem
+ * that has not finished as LTLF_CANCELLED with the levels it completed
+ * (problems that had finished keep their results).  A request that finds no
+ * run between levels stays pending for the context's next run, which then
+ * stops before its first level; each request stops one run.
+ * EINVAL: ctx == NULL. */
+ltlf_status ltlf_ctx_cancel(ltlf_ctx *ctx);
 
 /* Destroy a context and free the memory it allocated.  NULL is ignored. */
 void ltlf_ctx_destroy(ltlf_ctx *ctx);

@@ -86,6 +86,7 @@ struct ltlf_ctx {
     uint32_t* d_canon = nullptr;
     uint32_t *d_V = nullptr, *d_S = nullptr, *d_P0 = nullptr, *d_atoms = nullptr;
     unsigned long long* d_ctr = nullptr;
+    unsigned long long* d_digest = nullptr;  // level digests, kMaxBound + 1 entries
     uint32_t* d_tokens = nullptr;
     uint64_t* d_stage = nullptr;
     Store st{};
@@ -105,6 +106,10 @@ struct ltlf_ctx {
 
     // description of the last failure (empty after a successful call)
     std::string err;
+
+    // set by ltlf_ctx_cancel from any thread; taken (and cleared) by the
+    // level loop of ltlf_run / ltlf_solve_batch between levels
+    std::atomic<bool> cancel{false};
 
     // batched solving: export staging of this context (sub-contexts of a
     // batch need none), and the pooled sub-contexts with their pinned mirror
@@ -170,6 +175,7 @@ ltlf_status plan_memory_impl(ltlf_ctx* c) {
     c->d_P0 = reinterpret_cast<uint32_t*>(take(4 * Wp));
     c->d_atoms = reinterpret_cast<uint32_t*>(take(4 * Wp * c->n_props));
     c->d_ctr = reinterpret_cast<unsigned long long*>(take(8 * C_NUM));
+    c->d_digest = reinterpret_cast<unsigned long long*>(take(8 * (kMaxBound + 1)));
     c->d_tokens = reinterpret_cast<uint32_t*>(take(4 * (1 + kMaxTokens + 3 * (kMaxTokens + 1))));
     c->d_stage = reinterpret_cast<uint64_t*>(take(c->staging_bytes));
     off = align_up(off, 256);
@@ -410,6 +416,8 @@ ltlf_status begin_run(ltlf_ctx* c, uint32_t bound, uint32_t flags, uint32_t kern
     TRY_HIP(launch_encode(c->d_letters, c->d_lengths, c->d_pos_off, c->d_seg_off, c->d_positive,
                           c->n_traces, c->n_props, c->Wp, c->d_V, c->d_S, c->d_P0, c->d_atoms, s));
     TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(c->d_ctr), C_NUM, 0, s));
+    if (flags & LTLF_FLAG_DIGEST)
+        TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(c->d_digest), kMaxBound + 1, 0, s));
     const uint64_t slots0 = std::min<uint64_t>(pow2_ceil(std::max<uint64_t>(4ull * c->n_props, kMinTableSlots)),
                                                c->table_max);
     c->st.tsize = slots0;
@@ -438,8 +446,21 @@ void reset_result(ltlf_result* res, uint32_t row_bytes) {
 
 // Copies the witness formula (or an empty string) and the level counts of a
 // finished run into the caller's buffers.
+// Level digests of levels 1..levels_done into out[0..len) (0 elsewhere);
+// zeros when they were not computed.
+ltlf_status copy_digests(ltlf_ctx* c, uint32_t levels_done, bool computed, uint64_t* out, uint32_t len,
+                         hipStream_t s) {
+    std::vector<uint64_t> d(kMaxBound + 1, 0);
+    if (computed) {
+        TRY_HIP(hipMemcpyAsync(d.data(), c->d_digest, 8 * (kMaxBound + 1), hipMemcpyDeviceToHost, s));
+        TRY_HIP(hipStreamSynchronize(s));
+    }
+    for (uint32_t i = 0; i < len; ++i) out[i] = (i >= 1 && i <= levels_done && i <= kMaxBound) ? d[i] : 0;
+    return LTLF_OK;
+}
+
 ltlf_status finish_result(ltlf_ctx* c, ltlf_result* res, ltlf_status status, uint32_t wit_op, uint32_t wit_a,
-                          uint32_t wit_b, hipStream_t s) {
+                          uint32_t wit_b, bool digests, hipStream_t s) {
     uint64_t uniq = 0;
     for (uint32_t lev = 1; lev <= res->levels_done; ++lev) uniq += c->lcount[lev];
     res->unique_total = uniq;
@@ -448,6 +469,8 @@ ltlf_status finish_result(ltlf_ctx* c, ltlf_result* res, ltlf_status status, uin
         for (uint32_t i = 0; i < res->level_counts_len; ++i)
             res->level_counts[i] = (i <= res->levels_done && i < c->lcount.size()) ? c->lcount[i] : 0;
     }
+    if (res->level_digests) TRY(copy_digests(c, res->levels_done, digests, res->level_digests,
+                                            res->level_counts_len, s));
     res->status = status;
     if (status == LTLF_OK) {
         std::string f;
@@ -795,6 +818,8 @@ struct LevelRun {
             TRY_HIP(launch_set_counter(c->d_ctr, C_SNAP, live_end, s));
         }
         c->lcount[lev] = live_end - rows;
+        if (!overflow && (flags & LTLF_FLAG_DIGEST))
+            TRY_HIP(launch_digest(c->st.rows, c->Wp, rows, live_end - rows, c->d_digest + lev, s));
         rows = live_end;
         if (c->h_ctr[C_FOUND] && status != LTLF_OK) {
             status = LTLF_OK;
@@ -849,7 +874,7 @@ struct Job {
     ltlf_status status = LTLF_NOT_FOUND;
     uint32_t wit_op = 0, wit_a = 0, wit_b = 0;
     ltlf_result res{};
-    std::vector<uint64_t> counts;
+    std::vector<uint64_t> counts, digests;
     std::string formula;
     std::unique_ptr<LevelRun> run;  // set once its levels are large (single-problem kernels)
     ltlf_spec spec() const {
@@ -1027,7 +1052,7 @@ struct Scheduler {
         j->positive.assign(sp->positive, sp->positive + sp->n_traces);
         j->costs = *k;
         j->bound = bound;
-        j->flags = flags & (LTLF_FLAG_EXHAUST | LTLF_FLAG_NO_LOOKAHEAD | LTLF_FLAG_DEBUG_WEAK_HASH);
+        j->flags = flags & (LTLF_FLAG_EXHAUST | LTLF_FLAG_NO_LOOKAHEAD | LTLF_FLAG_DEBUG_WEAK_HASH | LTLF_FLAG_DIGEST);
         j->wp = (uint32_t)align_up((bits + 31) / 32, 4);
         // default reservation: room for ~2^18 rows, at most an eighth of the small pool
         const uint64_t dflt = std::min<uint64_t>((4ull * j->wp + 48) << 18, small_pool() / 8);
@@ -1049,7 +1074,8 @@ struct Scheduler {
     }
 
     // a job ends: its result is kept until polled; its memory is returned
-    ltlf_status finish(Job* j, hipStream_t s) {
+    // (cancelled: the levels it completed stand, its status is CANCELLED)
+    ltlf_status finish(Job* j, hipStream_t s, bool cancelled = false) {
         ltlf_ctx* sub = j->sub;
         ltlf_result& r = j->res;
         j->counts.assign(j->bound + 1, 0);
@@ -1061,12 +1087,44 @@ struct Scheduler {
         r.unique_total = uniq;
         r.checked_level = std::max({r.checked_level, r.levels_done, r.overflow_level});
         r.status = j->status;
+        j->digests.assign(j->bound + 1, 0);
+        if (copy_digests(sub, r.levels_done, (j->flags & LTLF_FLAG_DIGEST) != 0, j->digests.data(), j->bound + 1,
+                         s) != LTLF_OK)
+            return fail(c, LTLF_EDEVICE, sub->err.c_str());
         j->formula.clear();
         if (j->status == LTLF_OK && render_formula(sub, j->wit_op, j->wit_a, j->wit_b, s, j->formula) != LTLF_OK)
             return fail(c, LTLF_EDEVICE, sub->err.c_str());
         r.formula_len = j->formula.size() + 1;
+        if (cancelled) r.status = LTLF_CANCELLED;
         j->done = true;
         drop(j);
+        return LTLF_OK;
+    }
+
+    // Every unfinished job ends as CANCELLED with the levels it completed:
+    // the large job after its running level (the worker is stopped between
+    // levels), small-pool jobs at their last closed level, queued ones with
+    // none.
+    ltlf_status cancel_all(hipStream_t s) {
+        if (big) {
+            stop_worker();
+            if (big_status != LTLF_OK) return fail(c, big_status, big->sub->err.c_str());
+            big_running = false;
+            TRY(finish(big, s, true));
+        }
+        for (Job* j : std::vector<Job*>(resident)) TRY(finish(j, s, true));
+        for (std::deque<Job*>* q : {&queue, &big_queue, &solo_queue}) {
+            for (Job* j : *q) {
+                j->counts.assign(j->bound + 1, 0);
+                j->digests.assign(j->bound + 1, 0);
+                reset_result(&j->res, 4 * j->wp);
+                j->res.status = LTLF_CANCELLED;
+                j->formula.clear();
+                j->res.formula_len = 1;
+                j->done = true;
+            }
+            q->clear();
+        }
         return LTLF_OK;
     }
 
@@ -1100,6 +1158,10 @@ struct Scheduler {
         uint64_t off = 0;
         if (!alloc(j->want, off)) return LTLF_OK;
         ltlf_ctx* sub = take_sub();
+        if (!sub) {
+            release(off, j->want);
+            return fail(c, LTLF_EDEVICE, "no sub-context free for the small pool");
+        }
         sub->ws = c->ws + off;
         sub->ws_bytes = align_up(j->want, 256);
         sub->own_ws = false;
@@ -1121,11 +1183,18 @@ struct Scheduler {
         resident.push_back(j);
         placed = true;
         queue.erase(std::find(queue.begin(), queue.end(), j));
-        return begin_run(sub, j->bound, j->flags & LTLF_FLAG_DEBUG_WEAK_HASH, KERNEL_WAVE, s);
+        return begin_run(sub, j->bound, j->flags & (LTLF_FLAG_DEBUG_WEAK_HASH | LTLF_FLAG_DIGEST), KERNEL_WAVE, s);
     }
 
+    // The job takes the large region: load, run set-up, worker thread.  On
+    // any failure the job goes back to the front of the large-region queue
+    // with nothing of it on the device, so a later step can try again.
     ltlf_status start_big(Job* j, hipStream_t s) {
         ltlf_ctx* sub = take_sub();
+        if (!sub) {
+            big_queue.push_front(j);
+            return fail(c, LTLF_EDEVICE, "no sub-context free for the large region");
+        }
         sub->ws = c->ws + small_end;
         sub->ws_bytes = large_region() / 256 * 256;
         sub->own_ws = false;
@@ -1137,16 +1206,30 @@ struct Scheduler {
             solo_queue.push_back(j);
             return LTLF_OK;
         }
-        if (ls != LTLF_OK) return fail(c, ls, sub->err.c_str());
+        auto undo = [&](ltlf_status st, const std::string& what) {
+            sub->loaded = false;
+            j->sub = nullptr;
+            j->resident = false;
+            j->run.reset();
+            big_queue.push_front(j);
+            return fail(c, st, what.c_str());
+        };
+        if (ls != LTLF_OK) return undo(ls, sub->err);
         j->sub = sub;
         j->resident = true;
-        big = j;
-        j->run.reset(new LevelRun());
+        j->run.reset(new (std::nothrow) LevelRun());
+        if (!j->run) return undo(LTLF_ENOMEM, "out of host memory");
         j->lev = 0;
         const ltlf_status st = j->run->begin(sub, &j->costs, j->bound, j->flags, &j->res, s);
-        if (st != LTLF_OK) return fail(c, st, sub->err.c_str());
-        if (!big_stream) TRY_HIP(hipStreamCreateWithFlags(&big_stream, hipStreamNonBlocking));
-        TRY_HIP(hipStreamSynchronize(s));  // the load and the run's set-up precede its levels
+        if (st != LTLF_OK) return undo(st, sub->err);
+        if (!big_stream) {
+            const hipError_t e = hipStreamCreateWithFlags(&big_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) return undo(LTLF_EDEVICE, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
+        }
+        {
+            const hipError_t e = hipStreamSynchronize(s);  // the load and the run's set-up precede its levels
+            if (e != hipSuccess) return undo(LTLF_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+        }
         big_running = true;
         big_cancel = false;
         big_status = LTLF_OK;
@@ -1155,8 +1238,9 @@ struct Scheduler {
             worker = std::thread([this, j] { big_loop(j); });
         } catch (...) {  // no thread: nothing runs it
             big_running = false;
-            return fail(c, LTLF_EDEVICE, "cannot start the large region's worker thread");
+            return undo(LTLF_EDEVICE, "cannot start the large region's worker thread");
         }
+        big = j;  // only now: step() joins the worker of `big`
         return LTLF_OK;
     }
 
@@ -1179,10 +1263,12 @@ struct Scheduler {
     // the whole workspace, through ltlf_solve
     ltlf_status run_solo(Job* j, hipStream_t s) {
         j->counts.assign(j->bound + 1, 0);
+        j->digests.assign(j->bound + 1, 0);
         std::vector<char> fbuf(kMaxTokens * 8);
         ltlf_result r{};
         r.level_counts = j->counts.data();
         r.level_counts_len = j->bound + 1;
+        r.level_digests = j->digests.data();
         r.formula = fbuf.data();
         r.formula_cap = fbuf.size();
         const ltlf_spec sp = j->spec();
@@ -1193,6 +1279,7 @@ struct Scheduler {
         j->formula = st == LTLF_OK ? std::string(fbuf.data()) : std::string();
         j->res.formula = nullptr;
         j->res.level_counts = nullptr;
+        j->res.level_digests = nullptr;
         j->done = true;
         return LTLF_OK;
     }
@@ -1317,6 +1404,8 @@ struct Scheduler {
                 continue;
             }
             sub->lcount[lev] = now - j->rows;
+            if (j->flags & LTLF_FLAG_DIGEST)
+                TRY_HIP(launch_digest(sub->st.rows, sub->Wp, j->rows, now - j->rows, sub->d_digest + lev, s));
             j->rows = now;
             if (sub->h_ctr[C_FOUND] && j->status != LTLF_OK) {
                 j->status = LTLF_OK;
@@ -1345,7 +1434,7 @@ struct Scheduler {
                 running = big_running;
             }
             if (!running) {
-                worker.join();
+                if (worker.joinable()) worker.join();
                 Job* j = big;
                 if (big_status != LTLF_OK) return fail(c, big_status, j->sub->err.c_str());
                 // an overflow here is final: the large region is the request's capacity
@@ -1365,11 +1454,15 @@ struct Scheduler {
         Job* j = it->second;
         if (!j->done) return LTLF_PENDING;
         uint64_t* lc = out->level_counts;
+        uint64_t* ld = out->level_digests;
         const uint32_t lcl = out->level_counts_len;
         char* f = out->formula;
         const uint64_t fc = out->formula_cap;
         *out = j->res;
         out->level_counts = lc;
+        out->level_digests = ld;
+        if (ld)
+            for (uint32_t i = 0; i < lcl; ++i) ld[i] = i < j->digests.size() ? j->digests[i] : 0;
         out->level_counts_len = lcl;
         out->formula = f;
         out->formula_cap = fc;
@@ -1416,6 +1509,7 @@ const char* ltlf_status_str(ltlf_status s) {
     case LTLF_NOT_FOUND: return "no separating formula within the cost bound";
     case LTLF_CAPACITY: return "store full before the cost bound";
     case LTLF_PENDING: return "request not finished";
+    case LTLF_CANCELLED: return "cancelled";
     case LTLF_EINVAL: return "invalid argument";
     case LTLF_ENOMEM: return "out of device memory";
     case LTLF_EDEVICE: return "HIP runtime error";
@@ -1468,6 +1562,12 @@ ltlf_status ltlf_ctx_set_workspace(ltlf_ctx* c, void* dev_ptr, uint64_t bytes) {
 const char* ltlf_ctx_last_error(const ltlf_ctx* c) {
     if (!c) return "null context";
     return c->err.c_str();
+}
+
+ltlf_status ltlf_ctx_cancel(ltlf_ctx* c) {
+    if (!c) return LTLF_EINVAL;
+    c->cancel.store(true, std::memory_order_release);
+    return LTLF_OK;
 }
 
 ltlf_status ltlf_ctx_set_row_limit(ltlf_ctx* c, uint64_t max_rows) {
@@ -1548,7 +1648,14 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
     TRY_HIP(hipEventRecord(e0, s));
     LevelRun run;
     TRY(run.begin(c, k, bound, flags, res, s));
-    for (uint32_t lev = 1; lev <= bound && !run.stop; ++lev) TRY(run.level(lev, s));
+    bool cancelled = false;
+    for (uint32_t lev = 1; lev <= bound && !run.stop; ++lev) {
+        if (c->cancel.exchange(false, std::memory_order_acq_rel)) {
+            cancelled = true;
+            break;
+        }
+        TRY(run.level(lev, s));
+    }
     TRY_HIP(hipEventRecord(e1, s));
     TRY_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -1558,8 +1665,9 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
     res->deferred = c->h_ctr[C_DEFERRED];
     c->levels_done = res->levels_done;
     c->ran = true;
-    TRY(finish_result(c, res, run.status, run.wit_op, run.wit_a, run.wit_b, s));
-    return run.status;
+    TRY(finish_result(c, res, run.status, run.wit_op, run.wit_a, run.wit_b, (flags & LTLF_FLAG_DIGEST) != 0, s));
+    if (cancelled) res->status = LTLF_CANCELLED;
+    return res->status;
 }
 
 ltlf_status ltlf_ctx_set_tuning(ltlf_ctx* c, const ltlf_tuning* t) {
@@ -1711,7 +1819,13 @@ ltlf_status ltlf_solve_batch(ltlf_ctx* c, uint32_t n, const ltlf_spec* specs, co
             return st;
         }
     }
-    while (!sc.idle()) TRY(sc.step(s, nullptr));
+    while (!sc.idle()) {
+        if (c->cancel.exchange(false, std::memory_order_acq_rel)) {
+            TRY(sc.cancel_all(s));
+            break;
+        }
+        TRY(sc.step(s, nullptr));
+    }
     TRY_HIP(hipEventRecord(e1, s));
     TRY_HIP(hipEventSynchronize(e1));
     float ms = 0.f;

@@ -171,6 +171,9 @@ hipError_t launch_compact(const Store& s, uint64_t lo, uint64_t new_end, uint64_
                           uint32_t* movers, uint64_t cap, hipStream_t st);
 hipError_t launch_export(const uint32_t* rows, uint32_t Wp, uint64_t first, uint64_t n,
                          const uint32_t* canon_bit, uint64_t n_bits, uint64_t* out, hipStream_t st);
+// Adds the digest of rows [first, first + n) to *out (see k_digest).
+hipError_t launch_digest(const uint32_t* rows, uint32_t Wp, uint64_t first, uint64_t n,
+                         unsigned long long* out, hipStream_t st);
 // tokens must hold 1 + max_tokens + 3 * (max_tokens + 1) words (list + stack).
 hipError_t launch_formula(const uint4* meta, uint32_t root_op, uint32_t root_a, uint32_t root_b,
                           uint32_t max_tokens, uint32_t* tokens, hipStream_t st);

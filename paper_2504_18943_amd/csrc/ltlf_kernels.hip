@@ -2106,6 +2106,59 @@ __global__ void k_export(const uint32_t* rows, uint32_t Wp, uint64_t first, uint
     out[i] = acc;
 }
 
+// Level digest (a set fingerprint for comparing runs): the sum mod 2^64, over
+// the rows r of a range, of D(r) = dfin(XOR over the row's 16-byte chunks q
+// of dmix(q, chunk q)).  A sum does not depend on the order of the rows.  Its
+// own functions (not the table hash), so that the table hash can change
+// without changing digests.
+__device__ __forceinline__ uint64_t dmix(uint32_t q, uint4 r) {
+    const uint64_t a = ((uint64_t)r.y << 32) | r.x;
+    const uint64_t b = ((uint64_t)r.w << 32) | r.z;
+    uint64_t h = (a ^ ((uint64_t)(q + 1) * 0x9E3779B97F4A7C15ull)) * 0xbf58476d1ce4e5b9ull;
+    h ^= (b + (h >> 31)) * 0x94d049bb133111ebull;
+    return h ^ (h >> 29);
+}
+__device__ __forceinline__ uint64_t dfin(uint64_t k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+// Groups of G lanes (a power of two <= 64) take one row each, lane k of a
+// group the chunks k, k + G, ...; one atomic add per wave.
+__global__ __launch_bounds__(256) void k_digest(const uint4* rows, uint32_t nq, uint64_t first, uint64_t n,
+                                                uint32_t G, unsigned long long* out) {
+    const uint32_t lane = __lane_id();
+    const uint32_t sub = lane & (G - 1);
+    const uint64_t gid = ((uint64_t)blockIdx.x * 256 + threadIdx.x) / G;
+    const uint64_t ngroups = (uint64_t)gridDim.x * (256 / G);
+    const uint64_t iters = (n + ngroups - 1) / ngroups;
+    unsigned long long sum = 0;
+    for (uint64_t it = 0; it < iters; ++it) {  // uniform trip count: every lane reaches the shuffles
+        const uint64_t r = it * ngroups + gid;
+        uint64_t h = 0;
+        if (r < n) {
+            const uint4* M = rows + (first + r) * nq;
+            for (uint32_t q = sub; q < nq; q += G) h ^= dmix(q, M[q]);
+        }
+        for (uint32_t m = 1; m < G; m <<= 1) {
+            const uint32_t lo = __shfl_xor((uint32_t)h, (int)m, 64);
+            const uint32_t hi = __shfl_xor((uint32_t)(h >> 32), (int)m, 64);
+            h ^= ((uint64_t)hi << 32) | lo;
+        }
+        if (sub == 0 && r < n) sum += dfin(h);
+    }
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)sum, m, 64);
+        const uint32_t hi = __shfl_xor((uint32_t)(sum >> 32), m, 64);
+        sum += ((unsigned long long)hi << 32) | lo;
+    }
+    if (lane == 0 && sum) atomicAdd(out, sum);
+}
+
 // Writes the prefix token list of a formula given its root derivation.
 // Token = op code << 24 | payload (atom index for atoms).  tokens[0] holds the
 // count (max_tokens + 1 if the formula does not fit); the words after the
@@ -2382,6 +2435,20 @@ hipError_t launch_export(const uint32_t* rows, uint32_t Wp, uint64_t first, uint
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_export, dim3(blocks_for(total, 256)), dim3(256), 0, st, rows, Wp, first, n,
                        canon_bit, n_bits, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_digest(const uint32_t* rows, uint32_t Wp, uint64_t first, uint64_t n,
+                         unsigned long long* out, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const uint32_t nq = Wp / 4;
+    uint32_t G = 1;
+    while (G < nq && G < 64) G <<= 1;
+    const uint64_t groups = n;  // one row per group per iteration
+    uint64_t blocks = (groups * G + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_digest, dim3((uint32_t)blocks), dim3(256), 0, st,
+                       reinterpret_cast<const uint4*>(rows), nq, first, n, G, out);
     return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -18,9 +18,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libltlf.so")
 
-OK, NOT_FOUND, CAPACITY, PENDING = 0, 1, 2, 3
+OK, NOT_FOUND, CAPACITY, PENDING, CANCELLED = 0, 1, 2, 3, 4
 EINVAL, ENOMEM, EDEVICE, EBUFSZ, ESTATE = -1, -2, -3, -4, -5
-STATUS_NAMES = {0: "OK", 1: "NOT_FOUND", 2: "CAPACITY", 3: "PENDING", -1: "EINVAL", -2: "ENOMEM",
+STATUS_NAMES = {0: "OK", 1: "NOT_FOUND", 2: "CAPACITY", 3: "PENDING", 4: "CANCELLED", -1: "EINVAL", -2: "ENOMEM",
                 -3: "EDEVICE", -4: "EBUFSZ", -5: "ESTATE"}
 FLAG_EXHAUST = 0x1
 FLAG_PROFILE = 0x2
@@ -28,6 +28,7 @@ FLAG_KERNEL_LANE = 0x4  # one candidate per lane (default where it fits)
 FLAG_KERNEL_GROUP = 0x8  # one candidate per lane group (rows of 2..64 chunks)
 FLAG_KERNEL_WAVE = 0x10  # one candidate per wavefront (any row width)
 FLAG_NO_LOOKAHEAD = 0x20  # stop at an overflowed level (no check of the next one)
+FLAG_DIGEST = 0x40  # per-level digests of the stored sets (ltlf_result.level_digests)
 FLAG_WEAK_HASH = 0x100  # test hook: 6-bit hashes, every probe meets an equal tag
 
 OP_NAMES = ("!", "X", "F", "G", "&", "|", "U")  # index = ltlf_op
@@ -62,7 +63,8 @@ class ltlf_result(ctypes.Structure):
                 ("row_bytes", ctypes.c_uint32), ("gen_launches", ctypes.c_uint32),
                 ("verify_launches", ctypes.c_uint32), ("checked_level", ctypes.c_uint32),
                 ("enum_ms", ctypes.c_double), ("gen_ms", ctypes.c_double),
-                ("verify_ms", ctypes.c_double), ("dead_rows", ctypes.c_uint64)]
+                ("verify_ms", ctypes.c_double), ("dead_rows", ctypes.c_uint64),
+                ("level_digests", ctypes.POINTER(ctypes.c_uint64))]
 
 
 TUNE_CLASSES = 16
@@ -104,6 +106,8 @@ def load_library() -> ctypes.CDLL:
     L.ltlf_ctx_create.argtypes = [i32, u64, ctypes.POINTER(vp)]
     L.ltlf_ctx_set_workspace.restype = i32
     L.ltlf_ctx_set_workspace.argtypes = [vp, vp, u64]
+    L.ltlf_ctx_cancel.restype = i32
+    L.ltlf_ctx_cancel.argtypes = [vp]
     L.ltlf_ctx_set_row_limit.restype = i32
     L.ltlf_ctx_set_row_limit.argtypes = [vp, u64]
     L.ltlf_ctx_destroy.restype = None
@@ -166,6 +170,10 @@ def ltlf_ctx_create(device: int, hbm_budget_bytes: int):
 
 def ltlf_ctx_set_workspace(ctx, dev_ptr: int, nbytes: int) -> int:
     return load_library().ltlf_ctx_set_workspace(ctx, ctypes.c_void_p(dev_ptr), nbytes)
+
+
+def ltlf_ctx_cancel(ctx) -> int:
+    return load_library().ltlf_ctx_cancel(ctx)
 
 
 def ltlf_ctx_set_row_limit(ctx, max_rows: int) -> int:
@@ -311,6 +319,32 @@ def ltlf_formula_of(ctx, cost: int, index: int):
 
 
 # --------------------------------------------------------------- convenience --
+def _result_buffers(bound: int):
+    """An ltlf_result with caller buffers for levels 0..bound and the witness."""
+    counts = (ctypes.c_uint64 * (bound + 1))()
+    digests = (ctypes.c_uint64 * (bound + 1))()
+    fbuf = ctypes.create_string_buffer(8192)
+    res = ltlf_result()
+    res.level_counts = counts
+    res.level_digests = digests
+    res.level_counts_len = bound + 1
+    res.formula = ctypes.cast(fbuf, ctypes.c_char_p)
+    res.formula_cap = len(fbuf)
+    return res, (counts, digests, fbuf)
+
+
+def _result_of(st: int, res: "ltlf_result", bufs) -> "Result":
+    counts, digests, fbuf = bufs
+    return Result(status=st, min_cost=res.min_cost, levels_done=res.levels_done,
+                  overflow_level=res.overflow_level, level_counts=list(counts),
+                  formula=fbuf.value.decode(), candidates=res.candidates,
+                  unique_total=res.unique_total, enum_ms=res.enum_ms, deferred=res.deferred,
+                  row_bytes=res.row_bytes, gen_launches=res.gen_launches,
+                  verify_launches=res.verify_launches, gen_ms=res.gen_ms,
+                  verify_ms=res.verify_ms, dead_rows=res.dead_rows, checked_level=res.checked_level,
+                  level_digests=list(digests))
+
+
 @dataclass
 class Result:
     status: int
@@ -330,6 +364,7 @@ class Result:
     verify_ms: float = 0.0
     dead_rows: int = 0
     checked_level: int = 0  # no formula of this cost or less separates unless status is OK
+    level_digests: List[int] = field(default_factory=list)  # with FLAG_DIGEST: digest of U_c at index c
 
     @property
     def status_name(self) -> str:
@@ -405,24 +440,19 @@ class Synthesizer:
             raise LtlfError(st, "ltlf_load", ltlf_ctx_last_error(self._ctx))
 
     def run(self, cost_bound: int, op_cost=UNIT_ALL, atom_cost: int = 1, flags: int = 0) -> Result:
-        counts = (ctypes.c_uint64 * (cost_bound + 1))()
-        fbuf = ctypes.create_string_buffer(8192)
-        res = ltlf_result()
-        res.level_counts = counts
-        res.level_counts_len = cost_bound + 1
-        res.formula = ctypes.cast(fbuf, ctypes.c_char_p)
-        res.formula_cap = len(fbuf)
+        res, bufs = _result_buffers(cost_bound)
         st = ltlf_run(self._ctx, op_cost, atom_cost, cost_bound, flags, self._stream(), res)
         if st < 0:
             raise LtlfError(st, "ltlf_run", ltlf_ctx_last_error(self._ctx))
         self._bound = cost_bound
-        return Result(status=st, min_cost=res.min_cost, levels_done=res.levels_done,
-                      overflow_level=res.overflow_level, level_counts=list(counts),
-                      formula=fbuf.value.decode(), candidates=res.candidates,
-                      unique_total=res.unique_total, enum_ms=res.enum_ms, deferred=res.deferred,
-                      row_bytes=res.row_bytes, gen_launches=res.gen_launches,
-                      verify_launches=res.verify_launches, gen_ms=res.gen_ms,
-                      verify_ms=res.verify_ms, dead_rows=res.dead_rows, checked_level=res.checked_level)
+        return _result_of(st, res, bufs)
+
+    def cancel(self) -> None:
+        """Asks the running (or next) run of this context to stop between two
+        levels (ltlf_ctx_cancel; may be called from another thread)."""
+        st = ltlf_ctx_cancel(self._ctx)
+        if st != OK:
+            raise LtlfError(st, "ltlf_ctx_cancel")
 
     def solve(self, problem, cost_bound: Optional[int] = None, op_cost=UNIT_ALL, atom_cost: int = 1,
               flags: int = 0) -> Result:
@@ -478,28 +508,16 @@ class Synthesizer:
                                    [p.cost_bound for p in problems])]
         n = len(problems)
         results = (ltlf_result * n)()
-        counts = [(ctypes.c_uint64 * (b + 1))() for b in bounds]
-        fbufs = [ctypes.create_string_buffer(8192) for _ in range(n)]
+        bufs = []
         for i in range(n):
-            results[i].level_counts = counts[i]
-            results[i].level_counts_len = bounds[i] + 1
-            results[i].formula = ctypes.cast(fbufs[i], ctypes.c_char_p)
-            results[i].formula_cap = len(fbufs[i])
+            r, b = _result_buffers(bounds[i])
+            results[i] = r
+            bufs.append(b)
         st = ltlf_solve_batch(self._ctx, [(p.n_props,) + tuple(p.arrays()) for p in problems], op_cost,
                               atom_cost, bounds, flags, self._stream(), results)
         if st != OK:
             raise LtlfError(st, "ltlf_solve_batch", ltlf_ctx_last_error(self._ctx))
-        out = []
-        for i in range(n):
-            r = results[i]
-            out.append(Result(status=r.status, min_cost=r.min_cost, levels_done=r.levels_done,
-                              overflow_level=r.overflow_level, level_counts=list(counts[i]),
-                              formula=fbufs[i].value.decode(), candidates=r.candidates,
-                              unique_total=r.unique_total, enum_ms=r.enum_ms, deferred=r.deferred,
-                              row_bytes=r.row_bytes, gen_launches=r.gen_launches,
-                              verify_launches=r.verify_launches, gen_ms=r.gen_ms, verify_ms=r.verify_ms,
-                              dead_rows=r.dead_rows, checked_level=r.checked_level))
-        return out
+        return [_result_of(results[i].status, results[i], bufs[i]) for i in range(n)]
 
     def export_level(self, cost: int, first: int = 0, count: int = (1 << 64) - 1) -> np.ndarray:
         st, out = ltlf_export_level(self._ctx, cost, first, count)
@@ -546,25 +564,14 @@ class Server:
     def poll(self, ticket: int) -> Optional[Result]:
         """The result if the request finished (the ticket is then released), else None."""
         b = self._bounds.get(ticket, 0)
-        counts = (ctypes.c_uint64 * (b + 1))()
-        fbuf = ctypes.create_string_buffer(8192)
-        res = ltlf_result()
-        res.level_counts = counts
-        res.level_counts_len = b + 1
-        res.formula = ctypes.cast(fbuf, ctypes.c_char_p)
-        res.formula_cap = len(fbuf)
+        res, bufs = _result_buffers(b)
         st = ltlf_server_poll(self._srv, ticket, res)
         if st == PENDING:
             return None
         if st < 0:
             raise LtlfError(st, "ltlf_server_poll")
         del self._bounds[ticket]
-        return Result(status=st, min_cost=res.min_cost, levels_done=res.levels_done,
-                      overflow_level=res.overflow_level, level_counts=list(counts),
-                      formula=fbuf.value.decode(), candidates=res.candidates, unique_total=res.unique_total,
-                      enum_ms=res.enum_ms, deferred=res.deferred, row_bytes=res.row_bytes,
-                      gen_launches=res.gen_launches, verify_launches=res.verify_launches,
-                      checked_level=res.checked_level)
+        return _result_of(st, res, bufs)
 
     def cancel(self, ticket: int) -> None:
         st = ltlf_server_cancel(self._srv, ticket)

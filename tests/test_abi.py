@@ -22,9 +22,18 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(ltlf_[a-z_]+)\s*\(", src)))
 
 
+def test_status_values_match_header():
+    src = open(HEADER).read()
+    for name, val in (("LTLF_OK", 0), ("LTLF_NOT_FOUND", 1), ("LTLF_CAPACITY", 2), ("LTLF_PENDING", 3),
+                      ("LTLF_CANCELLED", 4)):
+        assert re.search(rf"\b{name} = {val},", src), name
+    assert L.CANCELLED == 4 and L.STATUS_NAMES[4] == "CANCELLED"
+    assert re.search(r"#define LTLF_FLAG_DIGEST 0x40u", src) and L.FLAG_DIGEST == 0x40
+
+
 def test_header_declares_the_entry_points():
     names = declared_functions()
-    for want in ["ltlf_ctx_create", "ltlf_ctx_set_workspace", "ltlf_ctx_set_row_limit",
+    for want in ["ltlf_ctx_create", "ltlf_ctx_set_workspace", "ltlf_ctx_set_row_limit", "ltlf_ctx_cancel",
                  "ltlf_ctx_destroy", "ltlf_load", "ltlf_run", "ltlf_solve",
                  "ltlf_export_level", "ltlf_formula_of", "ltlf_status_str"]:
         assert want in names
@@ -42,9 +51,10 @@ def test_binding_mirrors_every_entry_point():
 
 
 def test_status_strings():
-    for st in (0, 1, 2, -1, -2, -3, -4, -5):
+    for st in (0, 1, 2, 3, 4, -1, -2, -3, -4, -5):
         assert m.ltlf_status_str(st)
     assert m.ltlf_status_str(99) == "unknown status"
+    assert m.ltlf_status_str(4) == "cancelled"
 
 
 def test_null_arguments_rejected_without_device():
@@ -56,6 +66,7 @@ def test_null_arguments_rejected_without_device():
     assert lib.ltlf_run(None, ctypes.byref(c), 5, 0, None, ctypes.byref(res)) == L.EINVAL
     assert lib.ltlf_ctx_set_workspace(None, None, 0) == L.EINVAL
     assert lib.ltlf_ctx_set_row_limit(None, 5) == L.EINVAL
+    assert lib.ltlf_ctx_cancel(None) == L.EINVAL
     n, cw = ctypes.c_uint64(), ctypes.c_uint64()
     assert lib.ltlf_export_level(None, 1, 0, 1, None, 0, ctypes.byref(n), ctypes.byref(cw)) == L.EINVAL
     sres = L.ltlf_split_result()
@@ -69,7 +80,7 @@ def test_struct_layouts_match_header():
     # ltlf_costs: 8 uint32; ltlf_spec: 2 uint32 + 3 pointers
     assert ctypes.sizeof(L.ltlf_costs) == 32
     assert ctypes.sizeof(L.ltlf_spec) == 8 + 3 * ctypes.sizeof(ctypes.c_void_p)
-    assert ctypes.sizeof(L.ltlf_result) == 4 * 4 + 8 * 8 + 4 * 4 + 3 * 8 + 8
+    assert ctypes.sizeof(L.ltlf_result) == 4 * 4 + 8 * 8 + 4 * 4 + 3 * 8 + 8 + 8
 
 
 def test_struct_layouts_match_the_c_compiler(tmp_path):

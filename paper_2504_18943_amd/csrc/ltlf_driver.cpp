@@ -98,6 +98,10 @@ struct ltlf_ctx {
     // host mirrors
     unsigned long long* h_ctr = nullptr;  // pinned
     uint32_t* h_tokens = nullptr;         // pinned
+    // events around a whole run (created with the context, so a run creates
+    // no runtime objects)
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;    // ltlf_run
+    hipEvent_t evb0 = nullptr, evb1 = nullptr;  // ltlf_solve_batch (whose problems may run ltlf_run)
 
     // last run
     bool ran = false;
@@ -148,6 +152,35 @@ ltlf_status fail(ltlf_ctx* c, ltlf_status s, const char* what, hipError_t e = hi
     } while (0)
 
 
+// Sizes of the workspace carve-up (plan_memory_impl follows them):
+// the fixed regions, each 256-byte aligned, for a specification of n_pos
+// positions over T traces with m propositions and rows of Wp words ...
+uint64_t fixed_bytes(uint64_t n_pos, uint64_t T, uint64_t Wp, uint64_t m, uint64_t staging) {
+    uint64_t off = 0;
+    const uint64_t sizes[] = {4 * n_pos, 4 * T, 4 * (T + 1), 4 * (T + 1), T, 4 * n_pos, 4 * Wp, 4 * Wp, 4 * Wp,
+                              4 * Wp * m, (uint64_t)8 * C_NUM, (uint64_t)8 * (kMaxBound + 1),
+                              (uint64_t)4 * (1 + kMaxTokens + 3 * (kMaxTokens + 1)), staging};
+    for (const uint64_t b : sizes)
+        off = align_up(off, 256) + b;
+    return align_up(off, 256);
+}
+// ... the deferral lists (records) of what follows them ...
+void deferral_records(uint64_t rest, uint64_t& d0, uint64_t& d1) {
+    d0 = std::min<uint64_t>(std::max<uint64_t>(rest / 64 / 16, 1ull << 16), kDeferMax);
+    d1 = std::max<uint64_t>(d0 / 16, 4096);
+}
+// ... and the rows that fit a workspace of `bytes` (0: none).  Each row takes
+// 4 Wp bytes, a 16-byte derivation record and two 8-byte table slots.
+uint64_t row_capacity(uint64_t fixed, uint64_t Wp, uint64_t bytes) {
+    if (fixed >= bytes) return 0;
+    uint64_t d0, d1;
+    deferral_records(bytes - fixed, d0, d1);
+    if ((d0 + d1) * 16 + 4096 >= bytes - fixed) return 0;
+    const uint64_t off = align_up(align_up(fixed + 16 * d0, 256) + 16 * d1, 256);
+    if (off + 3 * 256 >= bytes) return 0;
+    return std::min<uint64_t>((bytes - off - 3 * 256) / (4 * Wp + 32), (1ull << 31) - 16);
+}
+
 // Carves the workspace.  Fixed regions first, then deferral lists, then the
 // row store and the table, which take what is left.
 ltlf_status plan_memory_impl(ltlf_ctx* c);
@@ -182,8 +215,8 @@ ltlf_status plan_memory_impl(ltlf_ctx* c) {
     if (off >= c->ws_bytes) return LTLF_ENOMEM;
     uint64_t rest = c->ws_bytes - off;
 
-    uint64_t d0 = std::min<uint64_t>(std::max<uint64_t>(rest / 64 / 16, 1ull << 16), kDeferMax);
-    uint64_t d1 = std::max<uint64_t>(d0 / 16, 4096);
+    uint64_t d0, d1;
+    deferral_records(rest, d0, d1);
     if ((d0 + d1) * 16 + 4096 >= rest) return LTLF_ENOMEM;
     c->st.def0 = reinterpret_cast<uint4*>(take(16 * d0));
     c->st.def1 = reinterpret_cast<uint4*>(take(16 * d1));
@@ -203,6 +236,8 @@ ltlf_status plan_memory_impl(ltlf_ctx* c) {
     c->st.rows = reinterpret_cast<uint32_t*>(take(4 * Wp * cap));
     c->st.meta = reinterpret_cast<uint4*>(take(16 * cap));
     if (off > c->ws_bytes) return LTLF_ENOMEM;
+    if (cap != row_capacity(fixed_bytes(c->n_pos, T, Wp, c->n_props, c->staging_bytes), Wp, c->ws_bytes))
+        return LTLF_EDEVICE;  // the size model disagrees with the carve-up
     c->table_max = slots;
     c->plan_cap = cap;
     c->st.cap = cap;
@@ -564,6 +599,32 @@ struct LevelRun {
         return begin_run(c, bound, flags, shape.kind, s);
     }
 
+    // Continues a run whose levels up to the last closed one are stored in
+    // ctx (moved there from another region, see Scheduler::migrate): the
+    // store, its counters and the level bookkeeping are as that level left
+    // them; rows_now rows are stored, cand_now candidates were generated.
+    void resume(ltlf_ctx* ctx, const ltlf_costs* costs, uint32_t cost_bound, uint32_t run_flags, ltlf_result* result,
+                uint64_t rows_now, uint64_t cand_now, ltlf_status status_now, uint32_t wo, uint32_t wa,
+                uint32_t wb) {
+        c = ctx;
+        k = costs;
+        bound = cost_bound;
+        flags = run_flags;
+        exhaust = (flags & LTLF_FLAG_EXHAUST) != 0;
+        profile = (flags & LTLF_FLAG_PROFILE) != 0;
+        res = result;
+        prof.c = c;
+        shape = tile_shape(c->Wp, c->lds_limit, tuned_kernel(c));
+        c->st.kernel = shape.kind;
+        rows = rows_now;
+        candidates = cand_now;
+        status = status_now;
+        wit_op = wo;
+        wit_a = wa;
+        wit_b = wb;
+        stop = false;
+    }
+
     // The level after `lev`, which overflowed with no separating candidate,
     // checked without storing anything.  Its candidates over stored levels
     // (binary operators, unary operators of cost >= 2: every operand level is
@@ -844,168 +905,50 @@ struct LevelRun {
 
 // ------------------------------------------------------------ scheduler --
 // Many problems on one device at once (batched solving and the request
-// server).  The workspace holds a small pool and one large region.  Each
-// problem in the small pool owns a reservation used as an ordinary
-// sub-context (row store, derivations, table, deferral lists, counters) and
-// sits at its own cost level; one step advances all of them by one level
-// with one generation launch (the wave kernel's tile body over pieces of
-// every problem's level plan), one verification launch per deferral budget,
-// and one transfer of all counters.  A problem stays in the pool only while
-// its next level is small and every candidate of it could be stored in its
-// reservation; otherwise it is restarted, from the start, in the large
-// region, which holds one problem at a time and runs one level of it per step
-// with the single-problem path (LevelRun: the level loop of ltlf_run).  The
-// large region is a request's capacity: results equal ltlf_solve's with a
-// workspace of that size, hence ltlf_solve's on the same context whenever
-// the run does not overflow it.
-struct Job {
-    uint64_t ticket = 0;
-    uint32_t n_props = 0;
-    std::vector<uint32_t> lengths, letters;
-    std::vector<uint8_t> positive;
-    ltlf_costs costs{};
-    uint32_t bound = 0, flags = 0, wp = 0;
-    ltlf_ctx* sub = nullptr;
-    uint64_t off = 0, bytes = 0, want = 0;
-    bool resident = false, done = false, solo = false;
-    uint32_t lev = 0;
-    uint64_t rows = 0, next_tile = 0, total = 0;
-    LevelPlan plan;
-    ltlf_status status = LTLF_NOT_FOUND;
-    uint32_t wit_op = 0, wit_a = 0, wit_b = 0;
-    ltlf_result res{};
-    std::vector<uint64_t> counts, digests;
-    std::string formula;
-    std::unique_ptr<LevelRun> run;  // set once its levels are large (single-problem kernels)
-    ltlf_spec spec() const {
-        return ltlf_spec{n_props, (uint32_t)lengths.size(), lengths.data(), letters.data(), positive.data()};
+// server).  The workspace holds a control region, a small pool and a large
+// area, each carved into regions by a first-fit allocator.  A job (one
+// problem) owns one region, used as an ordinary sub-context (row store,
+// derivations, table, deferral lists, counters, digests), and is either
+//   small: its levels are small (at most kBigLevel candidates); one step of
+//     the scheduler advances every small job by one level with one batched
+//     generation launch (the wave kernel's tile body over pieces of every
+//     job's level plan), one verification launch per deferral budget and one
+//     transfer of all counters; or
+//   large: it runs the single-problem level loop (LevelRun, the loop of
+//     ltlf_run) on a worker thread with a stream of its own while the main
+//     thread keeps stepping the small jobs; several large jobs run at once
+//     when their regions fit the large area.
+// Admission is sized by forecast: a job starts with a region for the first
+// few thousand rows, and before each level its region must hold the level's
+// worst case (every candidate a new row).  Otherwise the job moves to a
+// region sized for that worst case, at least four times its stored rows: its
+// stored levels (rows, derivation records, digests) are copied to the same
+// indices there and its table is rebuilt from the records, so no level is
+// enumerated twice (a small job whose next level is large moves into the
+// large area the same way).  A job whose worst case exceeds every region
+// short of the whole large area waits until the large area is empty and
+// runs there from the start: the large area is a request's capacity, and
+// every result equals ltlf_solve's with a workspace of the large area's size
+// (status, minimal cost, levels, overflow level, counts and sets), hence
+// ltlf_solve's on the same context whenever the run does not overflow it.
+
+// First-fit allocator over [lo, hi) of the workspace (offsets), 256-byte
+// granules.
+struct Arena {
+    uint64_t lo = 0, hi = 0;
+    std::vector<std::pair<uint64_t, uint64_t>> free_;  // (offset, bytes), sorted by offset
+    void init(uint64_t a, uint64_t b) {
+        lo = a;
+        hi = b;
+        free_.assign(1, {a, b - a});
     }
-};
-
-struct Scheduler {
-    ltlf_ctx* c = nullptr;
-    uint32_t max_resident = 0;
-    uint64_t base = 0, region = 0, small_end = 0;  // small pool [base, small_end), large region after it
-    std::vector<std::pair<uint64_t, uint64_t>> free_;  // small pool: (offset, bytes), sorted by offset
-    std::deque<Job*> queue;       // waiting for the small pool
-    std::deque<Job*> big_queue;   // waiting for the large region
-    std::deque<Job*> solo_queue;  // waiting for the whole workspace
-    std::vector<Job*> resident;   // in the small pool
-    Job* big = nullptr;           // in the large region
-    std::map<uint64_t, Job*> jobs;
-    uint64_t next_ticket = 1;
-    Store* d_stores = nullptr;
-    BSeg* d_segs = nullptr;
-    unsigned long long* d_gather = nullptr;
-    uint32_t launches = 0;
-    // The large region's levels run on a worker thread with a stream of its
-    // own, so the small pool keeps stepping while a large level runs; the
-    // worker owns `big` (its job, LevelRun and sub-context) until joined.
-    std::thread worker;
-    hipStream_t big_stream = nullptr;
-    std::mutex mu;
-    std::condition_variable cv;
-    bool big_running = false;          // guarded by mu
-    bool big_cancel = false;           // guarded by mu
-    ltlf_status big_status = LTLF_OK;  // the worker's, read after the join
-    std::atomic<bool> small_busy{false};  // small problems resident or waiting (main thread sets it)
-    static constexpr uint64_t kSegs = 1ull << 16;
-    static constexpr uint64_t kMinSlice = 16ull << 20;
-    static constexpr uint64_t kBigLevel = 1ull << 20;  // candidates of a level that runs on its own
-
-    ~Scheduler() {
-        stop_worker();
-        if (big_stream) {
-            (void)hipStreamSynchronize(big_stream);
-            (void)hipStreamDestroy(big_stream);
-        }
-        for (auto& kv : jobs) delete kv.second;
+    uint64_t total() const { return hi - lo; }
+    uint64_t free_bytes() const {
+        uint64_t f = 0;
+        for (const auto& r : free_) f += r.second;
+        return f;
     }
-
-    // asks the worker to stop after its current level and waits for it
-    void stop_worker() {
-        if (!worker.joinable()) return;
-        {
-            std::lock_guard<std::mutex> g(mu);
-            big_cancel = true;
-        }
-        worker.join();
-    }
-
-    // the large problem, level after level, on the worker thread
-    void big_loop(Job* j) {
-        ltlf_status st = hipSetDevice(c->device) == hipSuccess ? LTLF_OK : LTLF_EDEVICE;
-        LevelRun& r = *j->run;
-        while (st == LTLF_OK) {
-            {
-                std::lock_guard<std::mutex> g(mu);
-                if (big_cancel) break;
-            }
-            const uint32_t lev = j->lev + 1;
-            // persistent launches leave block slots to the small pool's
-            // launches while it has work
-            r.grid_eighths = small_busy.load(std::memory_order_relaxed) ? kBusyEighths : 8;
-            st = r.level(lev, big_stream);
-            if (st != LTLF_OK) break;
-            j->lev = lev;
-            j->res.candidates = r.candidates;
-            j->rows = r.rows;
-            j->status = r.status;
-            j->wit_op = r.wit_op;
-            j->wit_a = r.wit_a;
-            j->wit_b = r.wit_b;
-            if (r.stop || lev == j->bound) break;
-        }
-        // a level can end with work still queued (the compaction of its dead
-        // rows); the main thread reads the sub-context (witness formula) and
-        // hands the large region to the next job on its own stream, so the
-        // worker's stream must be drained first
-        if (hipStreamSynchronize(big_stream) != hipSuccess && st == LTLF_OK) st = LTLF_EDEVICE;
-        std::lock_guard<std::mutex> g(mu);
-        big_status = st;
-        big_running = false;
-        cv.notify_all();
-    }
-
-    ltlf_status init(ltlf_ctx* ctx, uint32_t max_res) {
-        c = ctx;
-        max_resident = max_res;
-        TRY(ensure_workspace(c));
-        c->loaded = false;  // the workspace is carved below
-        c->ran = false;
-        const uint64_t off_segs = align_up(sizeof(Store) * (uint64_t)max_res, 256);
-        const uint64_t off_gather = off_segs + align_up(sizeof(BSeg) * kSegs, 256);
-        base = off_gather + align_up(8ull * C_NUM * max_res, 256);
-        if (base + 4 * kMinSlice > c->ws_bytes) return fail(c, LTLF_ENOMEM, "workspace too small for the scheduler");
-        region = c->ws_bytes - base;
-        // the small pool is kept small: a request that overflows the large
-        // region is solved again with the whole workspace, so the large
-        // region should be nearly all of it
-        const uint64_t small = std::max<uint64_t>(region / 32, std::min<uint64_t>(region / 2, 256ull << 20));
-        small_end = base + small / 256 * 256;
-        d_stores = reinterpret_cast<Store*>(c->ws);
-        d_segs = reinterpret_cast<BSeg*>(c->ws + off_segs);
-        d_gather = reinterpret_cast<unsigned long long*>(c->ws + off_gather);
-        free_.assign(1, {base, small_end - base});
-        if (c->h_batch_cap < (uint64_t)C_NUM * max_res) {
-            if (c->h_batch) (void)hipHostFree(c->h_batch);
-            c->h_batch = nullptr;
-            c->h_batch_cap = 0;
-            TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_batch), 8ull * C_NUM * max_res,
-                                  hipHostMallocDefault));
-            c->h_batch_cap = (uint64_t)C_NUM * max_res;
-        }
-        while (c->subs.size() < (size_t)max_res + 1) {
-            ltlf_ctx* sub = nullptr;
-            TRY(ltlf_ctx_create(c->device, 0, &sub));
-            sub->staging_bytes = 4096;
-            c->subs.push_back(sub);
-        }
-        return LTLF_OK;
-    }
-    uint64_t small_pool() const { return small_end - base; }
-    uint64_t large_region() const { return base + region - small_end; }
-
+    bool empty() const { return free_bytes() == total(); }
     bool alloc(uint64_t bytes, uint64_t& off) {
         bytes = align_up(bytes, 256);
         for (size_t i = 0; i < free_.size(); ++i) {
@@ -1032,6 +975,121 @@ struct Scheduler {
             free_.erase(it);
         }
     }
+};
+
+struct Job {
+    enum Mode : uint32_t { QUEUED, SMALL, LARGE, FINISHED };
+    uint64_t ticket = 0;
+    uint32_t n_props = 0;
+    std::vector<uint32_t> lengths, letters;
+    std::vector<uint8_t> positive;
+    ltlf_costs costs{};
+    uint32_t bound = 0, flags = 0, wp = 0;
+    uint64_t n_pos = 0;
+    uint64_t want = 0;  // caller's first region in bytes (0: the forecast)
+    Mode mode = QUEUED;
+    bool done = false;
+    ltlf_ctx* sub = nullptr;  // sub-context on the region
+    Arena* arena = nullptr;   // owner of the region (nullptr: none)
+    uint64_t off = 0, bytes = 0;
+    bool full = false;  // the region is the whole large area
+    uint32_t lev = 0;   // last closed level
+    uint64_t rows = 0, next_tile = 0, total = 0;
+    uint64_t need_rows = 0;  // rows the next level may need (a request for a larger region)
+    LevelPlan plan;
+    ltlf_status status = LTLF_NOT_FOUND;
+    uint32_t wit_op = 0, wit_a = 0, wit_b = 0;
+    ltlf_result res{};
+    std::vector<uint64_t> counts, digests;
+    std::string formula;
+    std::unique_ptr<LevelRun> run;  // large jobs
+    // the large job's worker (running, stop and grow are guarded by Scheduler::mu)
+    std::thread worker;
+    hipStream_t stream = nullptr;
+    bool running = false, stop = false, grow = false;
+    ltlf_status wstatus = LTLF_OK;
+    ltlf_spec spec() const {
+        return ltlf_spec{n_props, (uint32_t)lengths.size(), lengths.data(), letters.data(), positive.data()};
+    }
+};
+
+struct Scheduler {
+    ltlf_ctx* c = nullptr;
+    uint32_t max_resident = 0;
+    uint64_t base = 0;
+    Arena small, large;
+    std::deque<Job*> queue;        // not started
+    std::deque<Job*> grow_queue;   // waiting for a larger region in the large area (region kept)
+    std::deque<Job*> full_queue;   // waiting for the whole large area (to start there)
+    std::deque<Job*> solo_queue;   // fixed regions beyond the large area: the whole workspace
+    std::vector<Job*> resident;    // small jobs
+    std::vector<Job*> bigs;        // large jobs with a worker (running, or finished and not yet reaped)
+    std::map<uint64_t, Job*> jobs;
+    std::vector<ltlf_ctx*> used;   // sub-contexts held by jobs
+    std::vector<hipStream_t> streams;  // one per large job slot, reused
+    uint64_t next_ticket = 1;
+    Store* d_stores = nullptr;
+    BSeg* d_segs = nullptr;
+    unsigned long long* d_gather = nullptr;
+    uint32_t launches = 0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::atomic<uint32_t> big_running{0};
+    std::atomic<bool> small_busy{false};
+    static constexpr uint64_t kSegs = 1ull << 16;
+    static constexpr uint64_t kMinSlice = 16ull << 20;
+    static constexpr uint64_t kBigLevel = 1ull << 20;  // candidates of a level that runs on its own
+    static constexpr uint64_t kFirstRows = 1ull << 12;  // rows of a first region
+    static constexpr uint64_t kSubStaging = 4096;
+
+    ~Scheduler() {
+        for (Job* j : bigs) stop_worker(j);
+        for (hipStream_t st : streams) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+        }
+        for (auto& kv : jobs) delete kv.second;
+    }
+
+    // -------------------------------------------------------------- set-up
+    ltlf_status init(ltlf_ctx* ctx, uint32_t max_res) {
+        c = ctx;
+        max_resident = max_res;
+        TRY(ensure_workspace(c));
+        c->loaded = false;  // the workspace is carved below
+        c->ran = false;
+        const uint64_t off_segs = align_up(sizeof(Store) * (uint64_t)max_res, 256);
+        const uint64_t off_gather = off_segs + align_up(sizeof(BSeg) * kSegs, 256);
+        base = off_gather + align_up(8ull * C_NUM * max_res, 256);
+        if (base + 4 * kMinSlice > c->ws_bytes) return fail(c, LTLF_ENOMEM, "workspace too small for the scheduler");
+        const uint64_t region = c->ws_bytes - base;
+        // the small pool is kept small: the large area is a request's
+        // capacity, so it should be nearly all of the workspace
+        const uint64_t pool = std::max<uint64_t>(region / 32, std::min<uint64_t>(region / 2, 256ull << 20));
+        const uint64_t small_end = base + pool / 256 * 256;
+        small.init(base, small_end);
+        large.init(small_end, small_end + (c->ws_bytes - small_end) / 256 * 256);
+        d_stores = reinterpret_cast<Store*>(c->ws);
+        d_segs = reinterpret_cast<BSeg*>(c->ws + off_segs);
+        d_gather = reinterpret_cast<unsigned long long*>(c->ws + off_gather);
+        if (c->h_batch_cap < (uint64_t)C_NUM * max_res) {
+            if (c->h_batch) (void)hipHostFree(c->h_batch);
+            c->h_batch = nullptr;
+            c->h_batch_cap = 0;
+            TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_batch), 8ull * C_NUM * max_res,
+                                  hipHostMallocDefault));
+            c->h_batch_cap = (uint64_t)C_NUM * max_res;
+        }
+        // one sub-context per resident job, plus the targets of moves
+        while (c->subs.size() < (size_t)max_res + 2) {
+            ltlf_ctx* sub = nullptr;
+            TRY(ltlf_ctx_create(c->device, 0, &sub));
+            sub->staging_bytes = kSubStaging;
+            c->subs.push_back(sub);
+        }
+        return LTLF_OK;
+    }
+    uint64_t small_pool() const { return small.total(); }
 
     ltlf_status submit(const ltlf_spec* sp, const ltlf_costs* k, uint32_t bound, uint32_t flags, uint64_t want,
                        uint64_t* ticket) {
@@ -1048,15 +1106,14 @@ struct Scheduler {
             total += sp->lengths[t];
             bits += sp->lengths[t] + 1;
         }
+        j->n_pos = total;
         j->letters.assign(sp->letters, sp->letters + total);
         j->positive.assign(sp->positive, sp->positive + sp->n_traces);
         j->costs = *k;
         j->bound = bound;
         j->flags = flags & (LTLF_FLAG_EXHAUST | LTLF_FLAG_NO_LOOKAHEAD | LTLF_FLAG_DEBUG_WEAK_HASH | LTLF_FLAG_DIGEST);
         j->wp = (uint32_t)align_up((bits + 31) / 32, 4);
-        // default reservation: room for ~2^18 rows, at most an eighth of the small pool
-        const uint64_t dflt = std::min<uint64_t>((4ull * j->wp + 48) << 18, small_pool() / 8);
-        j->want = std::min<uint64_t>(std::max<uint64_t>(want ? want : dflt, kMinSlice), small_pool());
+        j->want = want;
         reset_result(&j->res, 4 * j->wp);
         jobs[j->ticket] = j;
         queue.push_back(j);
@@ -1064,57 +1121,451 @@ struct Scheduler {
         return LTLF_OK;
     }
 
-    ltlf_ctx* take_sub() {
-        for (ltlf_ctx* sub : c->subs) {
-            bool used = big && big->sub == sub;
-            for (Job* r : resident) used |= r->sub == sub;
-            if (!used) return sub;
-        }
-        return nullptr;
+    // ------------------------------------------------------------ regions
+    // Bytes of a region that holds `rows` rows of job j (see row_capacity).
+    uint64_t region_for(const Job* j, uint64_t rows) const {
+        const uint64_t f = fixed_bytes(j->n_pos, j->lengths.size(), j->wp, j->n_props, kSubStaging);
+        const uint64_t per = 4ull * j->wp + 32;
+        uint64_t b = align_up(f + rows * per + rows * per / 32 + (2ull << 20), 1ull << 20);
+        while (row_capacity(f, j->wp, b) < rows) b = align_up(b + b / 16, 1ull << 20);
+        return b;
     }
 
+    ltlf_ctx* take_sub() {
+        for (ltlf_ctx* sub : c->subs)
+            if (std::find(used.begin(), used.end(), sub) == used.end()) {
+                used.push_back(sub);
+                return sub;
+            }
+        ltlf_ctx* sub = nullptr;  // pooled in the context for later schedulers
+        if (ltlf_ctx_create(c->device, 0, &sub) != LTLF_OK) return nullptr;
+        sub->staging_bytes = kSubStaging;
+        c->subs.push_back(sub);
+        used.push_back(sub);
+        return sub;
+    }
+    void give_sub(ltlf_ctx* sub) {
+        if (!sub) return;
+        sub->loaded = false;
+        auto it = std::find(used.begin(), used.end(), sub);
+        if (it != used.end()) used.erase(it);
+    }
+
+    // A sub-context on region [off, off + bytes) with j's specification
+    // loaded (synchronises s).
+    ltlf_status open_sub(Job* j, uint64_t off, uint64_t bytes, hipStream_t s, ltlf_ctx*& out) {
+        ltlf_ctx* sub = take_sub();
+        if (!sub) return fail(c, LTLF_EDEVICE, "no sub-context free");
+        sub->ws = c->ws + off;
+        sub->ws_bytes = bytes;
+        sub->own_ws = false;
+        sub->row_limit = c->row_limit;
+        sub->tune = c->tune;
+        const ltlf_spec sp = j->spec();
+        const ltlf_status ls = ltlf_load(sub, &sp, s);
+        if (ls != LTLF_OK) {
+            give_sub(sub);
+            return ls == LTLF_ENOMEM ? ls : fail(c, ls, sub->err.c_str());
+        }
+        out = sub;
+        return LTLF_OK;
+    }
+
+    // The job leaves its region (and sub-context).
+    void leave_region(Job* j) {
+        if (j->arena) j->arena->release(j->off, j->bytes);
+        give_sub(j->sub);
+        j->sub = nullptr;
+        j->arena = nullptr;
+        j->off = j->bytes = 0;
+        j->full = false;
+    }
+
+    // Moves j's stored levels into sub-context `to` (loaded, on a region
+    // disjoint from j's): atoms and masks encoded there, counters reset,
+    // then the rows and derivation records of every stored level copied to
+    // the same indices, the digests and level bookkeeping carried over, the
+    // counters set as the last closed level left them, and the table rebuilt
+    // from the records.  The caller drains s before the old region is reused.
+    ltlf_status migrate(Job* j, ltlf_ctx* to, uint32_t kernel, hipStream_t s) {
+        ltlf_ctx* from = j->sub;
+        TRY(begin_run(to, j->bound, j->flags & (LTLF_FLAG_DEBUG_WEAK_HASH | LTLF_FLAG_DIGEST), kernel, s));
+        const uint64_t n = j->rows;
+        if (n > to->plan_cap) return fail(c, LTLF_EDEVICE, "a moved job does not fit its new region");
+        if (n) {
+            TRY_HIP(hipMemcpyAsync(to->st.rows, from->st.rows, n * 4ull * j->wp, hipMemcpyDeviceToDevice, s));
+            TRY_HIP(hipMemcpyAsync(to->st.meta, from->st.meta, n * sizeof(uint4), hipMemcpyDeviceToDevice, s));
+        }
+        if (j->flags & LTLF_FLAG_DIGEST)
+            TRY_HIP(hipMemcpyAsync(to->d_digest, from->d_digest, 8ull * (kMaxBound + 1), hipMemcpyDeviceToDevice, s));
+        TRY_HIP(launch_set_counter(to->d_ctr, C_ROWS, n, s));
+        TRY_HIP(launch_set_counter(to->d_ctr, C_SNAP, n, s));
+        TRY_HIP(launch_set_counter(to->d_ctr, C_CAND, j->res.candidates, s));
+        TRY_HIP(launch_set_counter(to->d_ctr, C_DEFERRED, j->res.deferred, s));
+        to->lstart = from->lstart;
+        to->lcount = from->lcount;
+        if (n && ensure_table(to, n, n, s) != LTLF_OK) return fail(c, LTLF_EDEVICE, to->err.c_str());
+        return LTLF_OK;
+    }
+
+    // ------------------------------------------------------------- workers
+    hipStream_t take_stream() {
+        for (hipStream_t st : streams) {
+            bool busy = false;
+            for (Job* b : bigs) busy |= b->stream == st;
+            for (Job* b : grow_queue) busy |= b->stream == st;
+            if (!busy) return st;
+        }
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        streams.push_back(st);
+        return st;
+    }
+
+    // the large job, level after level, on its worker thread: before each
+    // level (unless its region is the whole large area) the region must hold
+    // the level's worst case, else the job stops and asks for a larger one
+    void big_loop(Job* j) {
+        ltlf_status st = hipSetDevice(c->device) == hipSuccess ? LTLF_OK : LTLF_EDEVICE;
+        LevelRun& r = *j->run;
+        bool grow = false;
+        while (st == LTLF_OK) {
+            {
+                std::lock_guard<std::mutex> g(mu);
+                if (j->stop) break;
+            }
+            const uint32_t lev = j->lev + 1;
+            if (!j->full) {
+                const LevelPlan p = plan_level(j->sub, &j->costs, lev, r.shape);
+                uint64_t need = r.rows + p.cand_ub;
+                if (c->row_limit) need = std::min<uint64_t>(need, std::max<uint64_t>(c->row_limit, r.rows) + 1);
+                if (need > j->sub->plan_cap) {
+                    j->need_rows = std::max<uint64_t>(need, 4 * r.rows);
+                    grow = true;
+                    break;
+                }
+            }
+            // persistent launches share the resident block slots with the
+            // other large jobs and leave room to the small jobs' launches
+            const uint32_t nb = std::max<uint32_t>(1, big_running.load(std::memory_order_relaxed));
+            const uint32_t share = small_busy.load(std::memory_order_relaxed) ? kBusyEighths : 8;
+            r.grid_eighths = std::max<uint32_t>(1, share / nb);
+            st = r.level(lev, j->stream);
+            if (st != LTLF_OK) break;
+            j->lev = lev;
+            j->res.candidates = r.candidates;
+            j->rows = r.rows;
+            j->status = r.status;
+            j->wit_op = r.wit_op;
+            j->wit_a = r.wit_a;
+            j->wit_b = r.wit_b;
+            if (r.stop || lev == j->bound) break;
+        }
+        // a level can end with work still queued (the compaction of its dead
+        // rows); the main thread reads the sub-context and may hand the
+        // region on, so the stream is drained first
+        if (hipStreamSynchronize(j->stream) != hipSuccess && st == LTLF_OK) st = LTLF_EDEVICE;
+        std::lock_guard<std::mutex> g(mu);
+        j->wstatus = st;
+        j->grow = grow;
+        j->running = false;
+        big_running.fetch_sub(1, std::memory_order_relaxed);
+        cv.notify_all();
+    }
+
+    ltlf_status start_worker(Job* j) {
+        j->stream = take_stream();
+        if (!j->stream) return fail(c, LTLF_EDEVICE, "cannot create a stream for a large job");
+        {
+            std::lock_guard<std::mutex> g(mu);
+            j->running = true;
+            j->stop = false;
+            j->grow = false;
+            j->wstatus = LTLF_OK;
+        }
+        big_running.fetch_add(1, std::memory_order_relaxed);
+        try {
+            j->worker = std::thread([this, j] { big_loop(j); });
+        } catch (...) {
+            std::lock_guard<std::mutex> g(mu);
+            j->running = false;
+            big_running.fetch_sub(1, std::memory_order_relaxed);
+            return fail(c, LTLF_EDEVICE, "cannot start a large job's worker thread");
+        }
+        bigs.push_back(j);
+        return LTLF_OK;
+    }
+
+    // asks j's worker to stop after its current level and waits for it
+    void stop_worker(Job* j) {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            j->stop = true;
+        }
+        if (j->worker.joinable()) j->worker.join();
+    }
+
+    // ------------------------------------------------------------ placement
+    enum Place { PLACED, WAIT, NEED_FULL };
+
+    // A region of the large area for j's next `rows` rows: j moves there
+    // (keeping its stored levels) or, with nothing stored yet, starts there;
+    // then its worker starts.  WAIT: no such region is free now; NEED_FULL:
+    // only the whole large area would do.
+    ltlf_status place_large(Job* j, uint64_t rows, hipStream_t s, Place& out) {
+        out = WAIT;
+        const uint64_t bytes = region_for(j, rows);
+        if (bytes > large.total()) {
+            out = NEED_FULL;
+            return LTLF_OK;
+        }
+        uint64_t off = 0;
+        if (!large.alloc(bytes, off)) return LTLF_OK;
+        ltlf_ctx* sub = nullptr;
+        const ltlf_status ls = open_sub(j, off, bytes, s, sub);
+        if (ls != LTLF_OK) {
+            large.release(off, bytes);
+            if (ls == LTLF_ENOMEM) out = NEED_FULL;
+            return ls == LTLF_ENOMEM ? LTLF_OK : ls;
+        }
+        TRY(start_large(j, sub, &large, off, bytes, false, s));
+        out = PLACED;
+        return LTLF_OK;
+    }
+
+    // j becomes a large job on sub-context `sub` (region [off, off+bytes) of
+    // `ar`): moved there with its stored levels, or started there.
+    ltlf_status start_large(Job* j, ltlf_ctx* sub, Arena* ar, uint64_t off, uint64_t bytes, bool full,
+                            hipStream_t s) {
+        const bool fresh = j->sub == nullptr || j->lev == 0;
+        if (!fresh) {
+            const uint32_t kind = tile_shape(sub->Wp, sub->lds_limit, tuned_kernel(sub)).kind;
+            TRY(migrate(j, sub, kind, s));
+            TRY_HIP(hipStreamSynchronize(s));  // the copies have read the old region
+        }
+        if (j->mode == Job::SMALL) resident.erase(std::find(resident.begin(), resident.end(), j));
+        leave_region(j);
+        j->sub = sub;
+        j->arena = ar;
+        j->off = off;
+        j->bytes = bytes;
+        j->full = full;
+        j->mode = Job::LARGE;
+        if (!j->run) j->run.reset(new (std::nothrow) LevelRun());
+        if (!j->run) return fail(c, LTLF_ENOMEM, "out of host memory");
+        if (fresh) {
+            j->lev = 0;
+            j->rows = 0;
+            j->status = LTLF_NOT_FOUND;
+            reset_result(&j->res, 4 * j->wp);
+            TRY(j->run->begin(sub, &j->costs, j->bound, j->flags, &j->res, s));
+            TRY_HIP(hipStreamSynchronize(s));  // the load and the run's set-up precede its levels
+        } else {
+            j->run->resume(sub, &j->costs, j->bound, j->flags, &j->res, j->rows, j->res.candidates, j->status,
+                           j->wit_op, j->wit_a, j->wit_b);
+        }
+        return start_worker(j);
+    }
+
+    // A small job moves to a region of the small pool for `rows` rows.
+    ltlf_status move_small(Job* j, uint64_t rows, hipStream_t s, bool& moved) {
+        moved = false;
+        const uint64_t bytes = region_for(j, rows);
+        uint64_t off = 0;
+        if (bytes > small.total() / 4 || !small.alloc(bytes, off)) return LTLF_OK;
+        ltlf_ctx* sub = nullptr;
+        const ltlf_status ls = open_sub(j, off, bytes, s, sub);
+        if (ls != LTLF_OK) {
+            small.release(off, bytes);
+            return ls == LTLF_ENOMEM ? LTLF_OK : ls;
+        }
+        TRY(migrate(j, sub, KERNEL_WAVE, s));
+        TRY_HIP(hipStreamSynchronize(s));
+        const uint32_t lev = j->lev;
+        leave_region(j);
+        j->sub = sub;
+        j->arena = &small;
+        j->off = off;
+        j->bytes = bytes;
+        j->lev = lev;
+        moved = true;
+        return LTLF_OK;
+    }
+
+    ltlf_status start_small(Job* j, hipStream_t s, bool& placed) {
+        placed = false;
+        const uint64_t bytes = std::max<uint64_t>(j->want ? j->want : region_for(j, kFirstRows), 1ull << 20);
+        if (bytes > small.total() / 4) {  // too wide for the small pool: a large job from the start
+            queue.erase(std::find(queue.begin(), queue.end(), j));
+            j->need_rows = kFirstRows;
+            grow_queue.push_back(j);
+            placed = true;
+            return LTLF_OK;
+        }
+        uint64_t off = 0;
+        if (!small.alloc(bytes, off)) return LTLF_OK;
+        ltlf_ctx* sub = nullptr;
+        const ltlf_status ls = open_sub(j, off, bytes, s, sub);
+        if (ls != LTLF_OK) {
+            small.release(off, bytes);
+            if (ls != LTLF_ENOMEM) return ls;
+            queue.erase(std::find(queue.begin(), queue.end(), j));
+            j->need_rows = kFirstRows;
+            grow_queue.push_back(j);
+            placed = true;
+            return LTLF_OK;
+        }
+        j->sub = sub;
+        j->arena = &small;
+        j->off = off;
+        j->bytes = bytes;
+        j->mode = Job::SMALL;
+        resident.push_back(j);
+        placed = true;
+        queue.erase(std::find(queue.begin(), queue.end(), j));
+        return begin_run(sub, j->bound, j->flags & (LTLF_FLAG_DEBUG_WEAK_HASH | LTLF_FLAG_DIGEST), KERNEL_WAVE, s);
+    }
+
+    // back to the queue, from the start (its device state is discarded)
+    void restart(Job* j, bool front) {
+        if (j->mode == Job::SMALL) resident.erase(std::find(resident.begin(), resident.end(), j));
+        leave_region(j);
+        j->mode = Job::QUEUED;
+        j->run.reset();
+        j->lev = 0;
+        j->rows = 0;
+        j->status = LTLF_NOT_FOUND;
+        reset_result(&j->res, 4 * j->wp);
+        if (front) queue.push_front(j);
+        else queue.push_back(j);
+    }
+
+    uint32_t holding() const {
+        uint32_t n = (uint32_t)(resident.size() + bigs.size());
+        for (Job* j : grow_queue) n += j->sub != nullptr;
+        return n;
+    }
+
+    // ------------------------------------------------------------- admission
+    ltlf_status admit(hipStream_t s) {
+        if (!solo_queue.empty()) return LTLF_OK;  // the whole workspace is wanted: drain first
+        // the whole large area, once nothing holds any of it
+        if (!full_queue.empty() && large.empty()) {
+            Job* j = full_queue.front();
+            full_queue.pop_front();
+            ltlf_ctx* sub = nullptr;
+            const ltlf_status ls = open_sub(j, large.lo, large.total(), s, sub);
+            if (ls == LTLF_ENOMEM) {  // not even the large area: the whole workspace
+                solo_queue.push_back(j);
+                return LTLF_OK;
+            }
+            if (ls != LTLF_OK) return ls;
+            uint64_t off = 0;
+            if (!large.alloc(large.total(), off)) return fail(c, LTLF_EDEVICE, "the large area is not free");
+            j->lev = 0;  // from the start
+            TRY(start_large(j, sub, &large, off, large.total(), true, s));
+        }
+        // larger regions, oldest first; none while the whole area is wanted
+        while (full_queue.empty() && !grow_queue.empty()) {
+            Job* j = grow_queue.front();
+            Place pl = WAIT;
+            TRY(place_large(j, j->need_rows, s, pl));
+            if (pl == WAIT) break;
+            grow_queue.pop_front();
+            if (pl == NEED_FULL) {
+                if (j->mode == Job::SMALL) resident.erase(std::find(resident.begin(), resident.end(), j));
+                leave_region(j);
+                j->mode = Job::QUEUED;
+                full_queue.push_back(j);
+            }
+        }
+        // nothing runs in the large area and its waiters cannot be served:
+        // the younger waiters that hold parts of it start over later
+        if (big_running.load() == 0 && bigs.empty() && (!grow_queue.empty() || !full_queue.empty())) {
+            const bool keep_head = full_queue.empty();
+            for (size_t i = keep_head ? 1 : 0; i < grow_queue.size();) {
+                Job* w = grow_queue[i];
+                if (w->arena == &large) {
+                    grow_queue.erase(grow_queue.begin() + (long)i);
+                    restart(w, true);
+                } else {
+                    ++i;
+                }
+            }
+            if (keep_head && !grow_queue.empty() && grow_queue.front()->arena == &large) {
+                // the head itself blocks what it needs: it starts over in a fresh region
+                Job* h = grow_queue.front();
+                grow_queue.pop_front();
+                const uint64_t need = h->need_rows;
+                restart(h, true);
+                queue.erase(std::find(queue.begin(), queue.end(), h));
+                h->need_rows = need;
+                grow_queue.push_front(h);
+            }
+        }
+        // new jobs into the small pool
+        for (size_t i = 0; i < queue.size() && holding() < max_resident;) {
+            Job* j = queue[i];
+            bool placed = false;
+            TRY(start_small(j, s, placed));
+            if (!placed) ++i;
+        }
+        return LTLF_OK;
+    }
+
+    // ---------------------------------------------------------------- finish
     // a job ends: its result is kept until polled; its memory is returned
     // (cancelled: the levels it completed stand, its status is CANCELLED)
     ltlf_status finish(Job* j, hipStream_t s, bool cancelled = false) {
         ltlf_ctx* sub = j->sub;
         ltlf_result& r = j->res;
         j->counts.assign(j->bound + 1, 0);
+        j->digests.assign(j->bound + 1, 0);
         uint64_t uniq = 0;
-        for (uint32_t lev = 1; lev <= r.levels_done; ++lev) {
-            j->counts[lev] = sub->lcount[lev];
-            uniq += sub->lcount[lev];
+        if (sub) {
+            for (uint32_t lev = 1; lev <= r.levels_done; ++lev) {
+                j->counts[lev] = sub->lcount[lev];
+                uniq += sub->lcount[lev];
+            }
+            if (copy_digests(sub, r.levels_done, (j->flags & LTLF_FLAG_DIGEST) != 0, j->digests.data(), j->bound + 1,
+                             s) != LTLF_OK)
+                return fail(c, LTLF_EDEVICE, sub->err.c_str());
+        } else {
+            r.levels_done = 0;
         }
         r.unique_total = uniq;
         r.checked_level = std::max({r.checked_level, r.levels_done, r.overflow_level});
         r.status = j->status;
-        j->digests.assign(j->bound + 1, 0);
-        if (copy_digests(sub, r.levels_done, (j->flags & LTLF_FLAG_DIGEST) != 0, j->digests.data(), j->bound + 1,
-                         s) != LTLF_OK)
-            return fail(c, LTLF_EDEVICE, sub->err.c_str());
         j->formula.clear();
-        if (j->status == LTLF_OK && render_formula(sub, j->wit_op, j->wit_a, j->wit_b, s, j->formula) != LTLF_OK)
+        if (sub && j->status == LTLF_OK && render_formula(sub, j->wit_op, j->wit_a, j->wit_b, s, j->formula) != LTLF_OK)
             return fail(c, LTLF_EDEVICE, sub->err.c_str());
         r.formula_len = j->formula.size() + 1;
         if (cancelled) r.status = LTLF_CANCELLED;
         j->done = true;
-        drop(j);
+        if (j->mode == Job::SMALL) resident.erase(std::find(resident.begin(), resident.end(), j));
+        auto b = std::find(bigs.begin(), bigs.end(), j);
+        if (b != bigs.end()) bigs.erase(b);
+        leave_region(j);
+        j->mode = Job::FINISHED;
+        j->run.reset();
         return LTLF_OK;
     }
 
     // Every unfinished job ends as CANCELLED with the levels it completed:
-    // the large job after its running level (the worker is stopped between
-    // levels), small-pool jobs at their last closed level, queued ones with
-    // none.
+    // large jobs after their running level (workers are stopped between
+    // levels), small jobs at their last closed level, queued ones with none.
     ltlf_status cancel_all(hipStream_t s) {
-        if (big) {
-            stop_worker();
-            if (big_status != LTLF_OK) return fail(c, big_status, big->sub->err.c_str());
-            big_running = false;
-            TRY(finish(big, s, true));
+        for (Job* j : std::vector<Job*>(bigs)) {
+            stop_worker(j);
+            if (j->wstatus != LTLF_OK) return fail(c, j->wstatus, j->sub->err.c_str());
+            TRY(finish(j, s, true));
         }
         for (Job* j : std::vector<Job*>(resident)) TRY(finish(j, s, true));
-        for (std::deque<Job*>* q : {&queue, &big_queue, &solo_queue}) {
+        for (Job* j : std::vector<Job*>(grow_queue.begin(), grow_queue.end()))
+            if (j->sub) TRY(finish(j, s, true));
+        for (std::deque<Job*>* q : {&queue, &grow_queue, &full_queue, &solo_queue}) {
             for (Job* j : *q) {
+                if (j->done) continue;
                 j->counts.assign(j->bound + 1, 0);
                 j->digests.assign(j->bound + 1, 0);
                 reset_result(&j->res, 4 * j->wp);
@@ -1122,140 +1573,9 @@ struct Scheduler {
                 j->formula.clear();
                 j->res.formula_len = 1;
                 j->done = true;
+                j->mode = Job::FINISHED;
             }
             q->clear();
-        }
-        return LTLF_OK;
-    }
-
-    // off the device (its reservation is returned); progress is discarded
-    void drop(Job* j) {
-        if (j == big) {
-            big->sub->loaded = false;
-            big->sub = nullptr;
-            big->resident = false;
-            big = nullptr;
-        } else if (j->resident) {
-            release(j->off, j->bytes);
-            j->sub->loaded = false;
-            resident.erase(std::find(resident.begin(), resident.end(), j));
-            j->resident = false;
-            j->sub = nullptr;
-        }
-        j->run.reset();
-    }
-    void restart(Job* j, std::deque<Job*>& to) {
-        drop(j);
-        j->lev = 0;
-        j->rows = 0;
-        j->status = LTLF_NOT_FOUND;
-        reset_result(&j->res, 4 * j->wp);
-        to.push_back(j);
-    }
-
-    ltlf_status start_small(Job* j, hipStream_t s, bool& placed) {
-        placed = false;
-        uint64_t off = 0;
-        if (!alloc(j->want, off)) return LTLF_OK;
-        ltlf_ctx* sub = take_sub();
-        if (!sub) {
-            release(off, j->want);
-            return fail(c, LTLF_EDEVICE, "no sub-context free for the small pool");
-        }
-        sub->ws = c->ws + off;
-        sub->ws_bytes = align_up(j->want, 256);
-        sub->own_ws = false;
-        sub->row_limit = c->row_limit;
-        const ltlf_spec sp = j->spec();
-        const ltlf_status ls = ltlf_load(sub, &sp, s);
-        if (ls != LTLF_OK) {
-            release(off, sub->ws_bytes);
-            if (ls != LTLF_ENOMEM) return fail(c, ls, sub->err.c_str());
-            placed = true;  // its fixed regions need more than a slice: the large region
-            queue.erase(std::find(queue.begin(), queue.end(), j));
-            big_queue.push_back(j);
-            return LTLF_OK;
-        }
-        j->sub = sub;
-        j->off = off;
-        j->bytes = sub->ws_bytes;
-        j->resident = true;
-        resident.push_back(j);
-        placed = true;
-        queue.erase(std::find(queue.begin(), queue.end(), j));
-        return begin_run(sub, j->bound, j->flags & (LTLF_FLAG_DEBUG_WEAK_HASH | LTLF_FLAG_DIGEST), KERNEL_WAVE, s);
-    }
-
-    // The job takes the large region: load, run set-up, worker thread.  On
-    // any failure the job goes back to the front of the large-region queue
-    // with nothing of it on the device, so a later step can try again.
-    ltlf_status start_big(Job* j, hipStream_t s) {
-        ltlf_ctx* sub = take_sub();
-        if (!sub) {
-            big_queue.push_front(j);
-            return fail(c, LTLF_EDEVICE, "no sub-context free for the large region");
-        }
-        sub->ws = c->ws + small_end;
-        sub->ws_bytes = large_region() / 256 * 256;
-        sub->own_ws = false;
-        sub->row_limit = c->row_limit;
-        sub->tune = c->tune;
-        const ltlf_spec sp = j->spec();
-        const ltlf_status ls = ltlf_load(sub, &sp, s);
-        if (ls == LTLF_ENOMEM) {  // not even the large region: the whole workspace
-            solo_queue.push_back(j);
-            return LTLF_OK;
-        }
-        auto undo = [&](ltlf_status st, const std::string& what) {
-            sub->loaded = false;
-            j->sub = nullptr;
-            j->resident = false;
-            j->run.reset();
-            big_queue.push_front(j);
-            return fail(c, st, what.c_str());
-        };
-        if (ls != LTLF_OK) return undo(ls, sub->err);
-        j->sub = sub;
-        j->resident = true;
-        j->run.reset(new (std::nothrow) LevelRun());
-        if (!j->run) return undo(LTLF_ENOMEM, "out of host memory");
-        j->lev = 0;
-        const ltlf_status st = j->run->begin(sub, &j->costs, j->bound, j->flags, &j->res, s);
-        if (st != LTLF_OK) return undo(st, sub->err);
-        if (!big_stream) {
-            const hipError_t e = hipStreamCreateWithFlags(&big_stream, hipStreamNonBlocking);
-            if (e != hipSuccess) return undo(LTLF_EDEVICE, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
-        }
-        {
-            const hipError_t e = hipStreamSynchronize(s);  // the load and the run's set-up precede its levels
-            if (e != hipSuccess) return undo(LTLF_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
-        }
-        big_running = true;
-        big_cancel = false;
-        big_status = LTLF_OK;
-        small_busy.store(!resident.empty() || !queue.empty(), std::memory_order_relaxed);
-        try {
-            worker = std::thread([this, j] { big_loop(j); });
-        } catch (...) {  // no thread: nothing runs it
-            big_running = false;
-            return undo(LTLF_EDEVICE, "cannot start the large region's worker thread");
-        }
-        big = j;  // only now: step() joins the worker of `big`
-        return LTLF_OK;
-    }
-
-    ltlf_status admit(hipStream_t s) {
-        if (!solo_queue.empty()) return LTLF_OK;  // the whole workspace is wanted: drain first
-        for (size_t i = 0; i < queue.size() && resident.size() < max_resident;) {
-            Job* j = queue[i];
-            bool placed = false;
-            TRY(start_small(j, s, placed));
-            if (!placed) ++i;
-        }
-        if (!big && !big_queue.empty()) {
-            Job* j = big_queue.front();
-            big_queue.pop_front();
-            TRY(start_big(j, s));
         }
         return LTLF_OK;
     }
@@ -1281,13 +1601,40 @@ struct Scheduler {
         j->res.level_counts = nullptr;
         j->res.level_digests = nullptr;
         j->done = true;
+        j->mode = Job::FINISHED;
+        return LTLF_OK;
+    }
+
+    // ------------------------------------------------------------------ step
+    ltlf_status reap(hipStream_t s, uint32_t& finished) {
+        for (Job* j : std::vector<Job*>(bigs)) {
+            bool running;
+            {
+                std::lock_guard<std::mutex> g(mu);
+                running = j->running;
+            }
+            if (running) continue;
+            if (j->worker.joinable()) j->worker.join();
+            if (j->wstatus != LTLF_OK) return fail(c, j->wstatus, j->sub ? j->sub->err.c_str() : "large job");
+            if (j->grow) {  // wants a larger region: waits for it, keeping its own
+                bigs.erase(std::find(bigs.begin(), bigs.end(), j));
+                grow_queue.push_back(j);
+                continue;
+            }
+            // an overflow is final only in the whole large area; elsewhere the
+            // worst-case check rules it out except through the row limit
+            if (j->status != LTLF_OK && j->res.overflow_level) j->status = LTLF_CAPACITY;
+            TRY(finish(j, s));
+            ++finished;
+        }
         return LTLF_OK;
     }
 
     ltlf_status step(hipStream_t s, uint32_t* n_done) {
         uint32_t finished = 0;
+        TRY(reap(s, finished));
         TRY(admit(s));
-        if (resident.empty() && !big) {
+        if (resident.empty() && bigs.empty() && grow_queue.empty() && full_queue.empty() && queue.empty()) {
             if (!solo_queue.empty()) {
                 Job* j = solo_queue.front();
                 solo_queue.pop_front();
@@ -1297,37 +1644,61 @@ struct Scheduler {
             if (n_done) *n_done = finished;
             return LTLF_OK;
         }
-        // small problems: plan the next level; a large one leaves for the large region
+        // small jobs: plan the next level; one that outgrows its region moves
         std::vector<Job*> live;
         for (Job* j : std::vector<Job*>(resident)) {
+            if (std::find(grow_queue.begin(), grow_queue.end(), j) != grow_queue.end()) continue;  // waiting
             ltlf_ctx* sub = j->sub;
             const uint32_t lev = j->lev + 1;
             sub->lstart[lev] = j->rows;
-            j->plan = plan_level(sub, &j->costs, lev, tile_shape(sub->Wp, sub->lds_limit, KERNEL_WAVE));
+            j->plan = plan_level(sub, &j->costs, lev, small_shape(sub));
             j->next_tile = 0;
             j->total = 0;
             for (const Seg& g : j->plan.segs) j->total += g.tiles;
             if (j->total) {
-                if (j->plan.cand_ub > kBigLevel || j->plan.cand_ub > sub->st.cap - j->rows ||
-                    2 * (j->rows + j->plan.cand_ub) > sub->table_max) {
-                    restart(j, big_queue);
+                const uint64_t need = j->rows + j->plan.cand_ub;
+                if (j->plan.cand_ub > kBigLevel) {
+                    j->need_rows = std::max<uint64_t>(need, 4 * j->rows);
+                    grow_queue.push_back(j);
                     continue;
+                }
+                if (need > sub->plan_cap) {
+                    bool moved = false;
+                    TRY(move_small(j, std::max<uint64_t>(need, 4 * j->rows), s, moved));
+                    if (!moved) {
+                        j->need_rows = std::max<uint64_t>(need, 4 * j->rows);
+                        grow_queue.push_back(j);
+                        continue;
+                    }
+                    sub = j->sub;
+                    sub->lstart[lev] = j->rows;
+                    j->plan = plan_level(sub, &j->costs, lev, small_shape(sub));
                 }
                 if (ensure_table(sub, j->rows, j->plan.cand_ub, s) != LTLF_OK)
                     return fail(c, LTLF_EDEVICE, sub->err.c_str());
             }
             live.push_back(j);
         }
+        small_busy.store(!live.empty() || !queue.empty(), std::memory_order_relaxed);
+        // large-area requests raised just now are served at once if they fit
+        if (!grow_queue.empty()) TRY(admit(s));
         if (!live.empty()) {
             std::vector<Store> h_stores(live.size());
             for (size_t i = 0; i < live.size(); ++i) h_stores[i] = live[i]->sub->st;
             TRY_HIP(hipMemcpyAsync(d_stores, h_stores.data(), sizeof(Store) * live.size(), hipMemcpyHostToDevice, s));
-            std::vector<BSeg> pieces;
+            // pieces of every job's plan, one list per kernel family, each
+            // job's share of a launch bounded by its deferral list
+            std::vector<BSeg> pieces[2];
+            uint32_t max_lane_wp = 0;
+            for (Job* j : live)
+                if (lane_class(j->sub)) max_lane_wp = std::max(max_lane_wp, j->sub->Wp);
             for (;;) {
-                pieces.clear();
-                uint64_t first = 0;
-                for (size_t i = 0; i < live.size() && pieces.size() + kMaxSegs < kSegs; ++i) {
+                pieces[0].clear();
+                pieces[1].clear();
+                uint64_t first[2] = {0, 0};
+                for (size_t i = 0; i < live.size() && pieces[0].size() + pieces[1].size() + kMaxSegs < kSegs; ++i) {
                     Job* j = live[i];
+                    const int fam = lane_class(j->sub) ? 0 : 1;
                     uint64_t budget = j->sub->st.def0_cap;
                     uint64_t seg_first = 0;
                     for (size_t g = 0; g < j->plan.segs.size() && j->next_tile < j->total; ++g) {
@@ -1340,20 +1711,24 @@ struct Scheduler {
                             if (take == 0) break;
                             BSeg b{};
                             b.problem = (uint32_t)i;
-                            b.first = first;
+                            b.first = first[fam];
                             b.lt0 = j->next_tile - seg_first;
                             b.seg = sg;
-                            pieces.push_back(b);
-                            first += take;
+                            pieces[fam].push_back(b);
+                            first[fam] += take;
                             j->next_tile += take;
                             budget -= take * per;
                         }
                         seg_first = seg_end;
                     }
                 }
-                if (pieces.empty()) break;
-                TRY_HIP(hipMemcpyAsync(d_segs, pieces.data(), sizeof(BSeg) * pieces.size(), hipMemcpyHostToDevice, s));
-                TRY_HIP(launch_generate_batch(d_stores, d_segs, (uint32_t)pieces.size(), 0, first, s));
+                const size_t nl = pieces[0].size(), nw = pieces[1].size();
+                if (nl + nw == 0) break;
+                pieces[0].insert(pieces[0].end(), pieces[1].begin(), pieces[1].end());
+                TRY_HIP(hipMemcpyAsync(d_segs, pieces[0].data(), sizeof(BSeg) * (nl + nw), hipMemcpyHostToDevice, s));
+                if (nl)
+                    TRY_HIP(launch_generate_lds_batch(d_stores, d_segs, (uint32_t)nl, 0, first[0], max_lane_wp, s));
+                if (nw) TRY_HIP(launch_generate_batch(d_stores, d_segs + nl, (uint32_t)nw, 0, first[1], s));
                 TRY_HIP(launch_verify_batch(d_stores, (uint32_t)live.size(), s));
                 TRY_HIP(launch_between_batch(d_stores, (uint32_t)live.size(), s));
                 ++launches;
@@ -1395,12 +1770,13 @@ struct Scheduler {
             const uint64_t now = std::min<uint64_t>(sub->h_ctr[C_ROWS], sub->st.cap);
             r->candidates = sub->h_ctr[C_CAND];
             r->deferred = sub->h_ctr[C_DEFERRED];
-            if (sub->h_ctr[C_DEF_OVF] || sub->h_ctr[C_OVERFLOW]) {
-                restart(j, big_queue);
-                continue;
-            }
-            if (sub->row_limit && now > sub->row_limit) {  // the large region applies it as ltlf_run does
-                restart(j, big_queue);
+            if (sub->h_ctr[C_DEF_OVF] || sub->h_ctr[C_OVERFLOW] || (sub->row_limit && now > sub->row_limit)) {
+                // not expected past the worst-case check except through the
+                // row limit: the large-area path applies it as ltlf_run does
+                restart(j, true);
+                queue.erase(std::find(queue.begin(), queue.end(), j));
+                j->need_rows = kFirstRows;
+                grow_queue.push_back(j);
                 continue;
             }
             sub->lcount[lev] = now - j->rows;
@@ -1423,26 +1799,17 @@ struct Scheduler {
             }
         }
         small_busy.store(!resident.empty() || !queue.empty(), std::memory_order_relaxed);
-        // the large problem runs on the worker (single-problem kernels); with
-        // nothing else to step, wait for it a little instead of returning at once
-        if (big) {
-            bool running;
-            {
-                std::unique_lock<std::mutex> lk(mu);
-                if (big_running && live.empty())
-                    cv.wait_for(lk, std::chrono::milliseconds(2), [this] { return !big_running; });
-                running = big_running;
-            }
-            if (!running) {
-                if (worker.joinable()) worker.join();
-                Job* j = big;
-                if (big_status != LTLF_OK) return fail(c, big_status, j->sub->err.c_str());
-                // an overflow here is final: the large region is the request's capacity
-                if (j->status != LTLF_OK && j->res.overflow_level) j->status = LTLF_CAPACITY;
-                TRY(finish(j, s));
-                ++finished;
-            }
+        // with nothing else to step, wait a little for a large job instead of
+        // returning at once
+        if (live.empty() && !bigs.empty()) {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait_for(lk, std::chrono::milliseconds(2), [this] {
+                for (Job* j : bigs)
+                    if (!j->running) return true;
+                return false;
+            });
         }
+        TRY(reap(s, finished));
         if (n_done) *n_done = finished;
         return LTLF_OK;
     }
@@ -1483,20 +1850,39 @@ struct Scheduler {
         auto it = jobs.find(ticket);
         if (it == jobs.end()) return LTLF_EINVAL;
         Job* j = it->second;
-        if (j == big) stop_worker();
-        drop(j);
-        for (std::deque<Job*>* q : {&queue, &big_queue, &solo_queue}) {
+        if (std::find(bigs.begin(), bigs.end(), j) != bigs.end()) {
+            stop_worker(j);
+            bigs.erase(std::find(bigs.begin(), bigs.end(), j));
+        }
+        if (j->mode == Job::SMALL) resident.erase(std::find(resident.begin(), resident.end(), j));
+        for (std::deque<Job*>* q : {&queue, &grow_queue, &full_queue, &solo_queue}) {
             auto f = std::find(q->begin(), q->end(), j);
             if (f != q->end()) q->erase(f);
         }
+        leave_region(j);
         jobs.erase(it);
         delete j;
         return LTLF_OK;
     }
 
-    uint32_t waiting() const { return (uint32_t)(queue.size() + big_queue.size() + solo_queue.size()); }
-    uint32_t on_device() const { return (uint32_t)resident.size() + (big ? 1u : 0u); }
-    bool idle() const { return waiting() == 0 && on_device() == 0; }
+    uint32_t waiting() const {
+        uint32_t n = (uint32_t)(queue.size() + full_queue.size() + solo_queue.size());
+        for (Job* j : grow_queue) n += j->sub == nullptr;
+        return n;
+    }
+    uint32_t on_device() const { return holding(); }
+    bool idle() const {
+        return queue.empty() && grow_queue.empty() && full_queue.empty() && solo_queue.empty() && resident.empty() &&
+               bigs.empty();
+    }
+    uint64_t free_bytes() const { return small.free_bytes() + large.free_bytes(); }
+
+    // Small jobs run the lane kernel's batched form where its 256-lane tile
+    // fits the LDS (rows of up to ~37 chunks), else the wave kernel's.
+    static bool lane_class(const ltlf_ctx* sub) { return lds_bytes(sub->Wp, kLanes) <= sub->lds_limit; }
+    static TileShape small_shape(const ltlf_ctx* sub) {
+        return tile_shape(sub->Wp, sub->lds_limit, lane_class(sub) ? KERNEL_LANE : KERNEL_WAVE);
+    }
 };
 
 }  // namespace
@@ -1538,8 +1924,13 @@ ltlf_status ltlf_ctx_create(int device, uint64_t hbm_budget_bytes, ltlf_ctx** ou
     c->budget = hbm_budget_bytes ? std::max<uint64_t>(hbm_budget_bytes, kMinWorkspace) : kDefaultBudget;
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_ctr), 8 * C_NUM, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->h_tokens), 4 * (1 + kMaxTokens), hipHostMallocDefault) !=
-            hipSuccess) {
+            hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipEventCreate(&c->evb0) != hipSuccess || hipEventCreate(&c->evb1) != hipSuccess) {
         if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+        if (c->h_tokens) (void)hipHostFree(c->h_tokens);
+        for (hipEvent_t e : {c->ev0, c->ev1, c->evb0, c->evb1})
+            if (e) (void)hipEventDestroy(e);
         delete c;
         return LTLF_EDEVICE;
     }
@@ -1585,6 +1976,8 @@ void ltlf_ctx_destroy(ltlf_ctx* c) {
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
     if (c->h_tokens) (void)hipHostFree(c->h_tokens);
+    for (hipEvent_t e : {c->ev0, c->ev1, c->evb0, c->evb1})
+        if (e) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -1635,16 +2028,7 @@ ltlf_status ltlf_run(ltlf_ctx* c, const ltlf_costs* k, uint32_t bound, uint32_t 
     hipStream_t s = static_cast<hipStream_t>(stream);
     reset_result(res, 4 * c->Wp);
 
-    hipEvent_t e0, e1;
-    TRY_HIP(hipEventCreate(&e0));
-    TRY_HIP(hipEventCreate(&e1));
-    struct EventGuard {
-        hipEvent_t a, b;
-        ~EventGuard() {
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
-        }
-    } guard{e0, e1};
+    hipEvent_t e0 = c->ev0, e1 = c->ev1;
     TRY_HIP(hipEventRecord(e0, s));
     LevelRun run;
     TRY(run.begin(c, k, bound, flags, res, s));
@@ -1786,31 +2170,11 @@ ltlf_status ltlf_solve_batch(ltlf_ctx* c, uint32_t n, const ltlf_spec* specs, co
     hipStream_t s = static_cast<hipStream_t>(stream);
     Scheduler sc;
     TRY(sc.init(c, n));
-    // reservations in proportion to the bytes a stored row costs
-    std::vector<double> w(n, 0.0);
-    double wsum = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        uint64_t bits = 0;
-        if (specs[i].lengths)
-            for (uint32_t t = 0; t < specs[i].n_traces; ++t) bits += specs[i].lengths[t] + 1;
-        w[i] = 4.0 * (double)align_up((bits + 31) / 32, 4) + 48.0;
-        wsum += w[i];
-    }
-    hipEvent_t e0, e1;
-    TRY_HIP(hipEventCreate(&e0));
-    TRY_HIP(hipEventCreate(&e1));
-    struct EventGuard {
-        hipEvent_t a, b;
-        ~EventGuard() {
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
-        }
-    } guard{e0, e1};
+    hipEvent_t e0 = c->evb0, e1 = c->evb1;
     TRY_HIP(hipEventRecord(e0, s));
     std::vector<uint64_t> ticket(n, 0);
     for (uint32_t i = 0; i < n; ++i) {
-        const uint64_t want = (uint64_t)((double)sc.small_pool() * w[i] / wsum);
-        const ltlf_status st = sc.submit(&specs[i], k, bounds[i], flags, want, &ticket[i]);
+        const ltlf_status st = sc.submit(&specs[i], k, bounds[i], flags, 0, &ticket[i]);
         if (st == LTLF_EINVAL) {
             reset_result(&results[i], 0);
             results[i].status = LTLF_EINVAL;
@@ -1889,7 +2253,7 @@ ltlf_status ltlf_server_load(const ltlf_server* sv, uint32_t* queued, uint32_t* 
     if (resident) *resident = sv->sched.on_device();
     if (free_bytes) {
         uint64_t f = 0;
-        for (const auto& r : sv->sched.free_) f += r.second;
+        f = sv->sched.free_bytes();
         *free_bytes = f;
     }
     return LTLF_OK;

@@ -93,14 +93,23 @@ __device__ __forceinline__ unsigned long long wave_alloc(unsigned long long* ctr
 // holds one chunk each combines its parts with shuffles, and every kernel
 // (one lane per candidate or one group per candidate) gets the same value.
 // Only speed depends on the quality: every match is verified against the
-// full row.
-__device__ __forceinline__ uint64_t chunk_hash(uint32_t k, uint4 r) {
-    const uint64_t a = ((uint64_t)r.y << 32) | r.x;
-    const uint64_t b = ((uint64_t)r.w << 32) | r.z;
-    uint64_t h = (a ^ ((uint64_t)(k + 1) * 0x9E3779B97F4A7C15ull)) * 0xbf58476d1ce4e5b9ull;
-    h ^= (b + (h >> 31)) * 0x94d049bb133111ebull;
-    return h ^ (h >> 29);
+// full row.  chunk_hash is a keyed multiply-add in the manner of NH: the four
+// words plus four keys of the chunk index, multiplied in pairs into 64 bits
+// (two 32 x 32 -> 64 multiply-adds per chunk).  The keys depend on the chunk
+// index only, so the candidates of a work item share them, and a lane that
+// walks a row keeps them in scalar registers.
+struct ChunkKey {
+    uint32_t k0, k1, k2, k3;
+};
+__device__ __forceinline__ ChunkKey chunk_key(uint32_t k) {
+    const uint32_t u = (k + 1u) * 0x9E3779B9u;
+    return ChunkKey{u ^ 0x85EBCA6Bu, u + 0xC2B2AE35u, ((u << 13) | (u >> 19)) ^ 0x27D4EB2Fu,
+                    ((u << 27) | (u >> 5)) + 0x165667B1u};
 }
+__device__ __forceinline__ uint64_t chunk_hash(const ChunkKey& K, uint4 r) {
+    return (uint64_t)(r.x + K.k0) * (uint64_t)(r.y + K.k1) + (uint64_t)(r.z + K.k2) * (uint64_t)(r.w + K.k3);
+}
+__device__ __forceinline__ uint64_t chunk_hash(uint32_t k, uint4 r) { return chunk_hash(chunk_key(k), r); }
 __device__ __forceinline__ uint64_t hash_fin(uint64_t k) {
     k ^= k >> 33;
     k *= 0xff51afd7ed558ccdull;
@@ -673,22 +682,15 @@ __host__ __device__ __forceinline__ uint32_t lds_stride(uint32_t nq) { return nq
 // rows whose 256-lane tile does not fit the LDS) is both the workgroup size
 // and the width of a pair tile.
 template <int BATCH, int LANES>
-__global__ __launch_bounds__(LANES) void k_generate_lds(Store s, SegTable t) {
-    extern __shared__ uint4 dyn[];
+__device__ __forceinline__ void lds_tile(const Store& s, const Seg& g, uint64_t lt, uint4* dyn) {
     const uint32_t NQ = s.Wp / 4, SB = lds_stride(NQ);
     uint4* sh_b = dyn;
     uint4* sh_a = sh_b + LANES * SB;
     uint4* sh_v = sh_a + kTileA * NQ;
     uint4* sh_s = sh_v + NQ;
     uint4* sh_p = sh_s + NQ;
-    const uint64_t tile = t.tile_begin + blockIdx.x;
-    if (tile >= t.tile_end) return;
     const uint64_t snap = s.ctr[C_SNAP];
     const bool full_store = store_full(s);
-    uint32_t si = 0;
-    while (si + 1 < t.n && t.first[si + 1] <= tile) ++si;
-    const Seg& g = t.seg[si];
-    const uint64_t lt = tile - t.first[si];
     const uint32_t tid = threadIdx.x;
     const uint4* rows4 = reinterpret_cast<const uint4*>(s.rows);
     for (uint32_t q = tid; q < NQ; q += LANES) {
@@ -802,6 +804,34 @@ __global__ __launch_bounds__(LANES) void k_generate_lds(Store s, SegTable t) {
     unsigned long long cc = count;
     for (int off = 32; off > 0; off >>= 1) cc += __shfl_down(cc, off);
     if (__lane_id() == 0 && cc) atomicAdd(&s.ctr[C_CAND], cc);
+}
+
+template <int BATCH, int LANES>
+__global__ __launch_bounds__(LANES) void k_generate_lds(Store s, SegTable t) {
+    extern __shared__ uint4 dyn[];
+    const uint64_t tile = t.tile_begin + blockIdx.x;
+    if (tile >= t.tile_end) return;
+    uint32_t si = 0;
+    while (si + 1 < t.n && t.first[si + 1] <= tile) ++si;
+    lds_tile<BATCH, LANES>(s, t.seg[si], tile - t.first[si], dyn);
+}
+
+// Batched form: tiles of many problems in one launch, one block per tile
+// (pieces as in k_generate_wave_batch); the dynamic LDS fits the widest row
+// of the launch.
+template <int BATCH, int LANES>
+__global__ __launch_bounds__(LANES) void k_generate_lds_batch(const Store* stores, const BSeg* segs, uint32_t nsegs,
+                                                              uint64_t tile0) {
+    extern __shared__ uint4 dyn[];
+    const uint64_t tile = tile0 + blockIdx.x;
+    uint32_t lo = 0, hi = nsegs;  // last piece with first <= tile
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (segs[mid].first <= tile) lo = mid;
+        else hi = mid;
+    }
+    const BSeg& b = segs[lo];
+    lds_tile<BATCH, LANES>(stores[b.problem], b.seg, b.lt0 + (tile - b.first), dyn);
 }
 
 // ------------------------------------------------ one lane group per candidate --
@@ -1189,6 +1219,7 @@ constexpr uint32_t kWB = 8;   // right operands per pair tile (square triangles)
 constexpr uint32_t kWU = 16;  // operands per unary tile
 constexpr uint32_t kWaveChunk = 8;  // rows / records a wave takes per atomic
 
+
 // X + Y over a whole row, one step of 64 chunks: `carry` (wave-uniform) is
 // the carry into lane 0 on entry and the carry out of lane 63 on return.
 __device__ __forceinline__ uint4 wave_add(uint4 x, uint4 y, uint32_t& carry) {
@@ -1284,55 +1315,191 @@ __device__ __forceinline__ uint64_t lane_pick4(uint32_t j, uint64_t v0, uint64_t
     return j == 0 ? v0 : j == 1 ? v1 : j == 2 ? v2 : v3;
 }
 
-// Hash, operand-equality tests, spec check and table work of one work item
-// (every lane of the wave calls it).  act[j]: candidate j is enabled; op[j],
-// L[j], R[j]: its derivation.  Lane j (< 4) owns candidate j.
-__device__ __forceinline__ void wave_item(const Store& s, WaveAlloc& wa, bool unary, const uint4* A,
-                                          const uint4* B, uint32_t nq, uint64_t snap, bool full_store,
-                                          const bool (&en)[4], const uint32_t (&op)[4], const uint32_t (&L)[4],
-                                          const uint32_t (&R)[4], uint32_t chunk) {
+// The same stream, specialised: UNARY fixed at compile time, and only the
+// results selected by `need` (bit j: result j; wave-uniform, constant over
+// the pass, so every carry chain runs on every step or on none) computed,
+// the others left zero.  Side loads travel with the operands, one step
+// ahead: with ROWS, the step's chunk of the stored row M[j] for every j in
+// `need` (verification); with MASKS, the step's chunks of P0 and S (spec
+// check).  body(q, in, a, b, r0, r1, r2, r3, m, P, S) runs once per step (b is
+// a for unary items; m[j], P, S zero where not loaded).
+// Side loads one step ahead (1) or in their own step (0).
+#ifndef LTLF_SIDE_PREFETCH
+#define LTLF_SIDE_PREFETCH 1
+#endif
+template <bool UNARY, bool ROWS, bool MASKS, class Body>
+__device__ __forceinline__ void wave_pass_t(const Store& s, const uint4* A, const uint4* B, uint32_t nq,
+                                            uint32_t need, const uint4* const (&M)[4], Body&& body) {
+    const uint4* V4 = reinterpret_cast<const uint4*>(s.V);
     const uint4* P4 = reinterpret_cast<const uint4*>(s.P0);
     const uint4* S4 = reinterpret_cast<const uint4*>(s.S);
-    uint4* rows4 = reinterpret_cast<uint4*>(s.rows);
+    const uint4 zero = make_uint4(0, 0, 0, 0);
+    uint32_t c0 = 0, c1 = 0, c2 = 0;
+    const uint32_t steps = (nq + 63) / 64;
     const uint32_t lane = __lane_id();
-    uint64_t h[4] = {0, 0, 0, 0};
-    uint32_t da[4] = {0, 0, 0, 0}, db[4] = {0, 0, 0, 0}, ck[4] = {0, 0, 0, 0};
-    // once the store has overflowed (uniform over the wave) candidates are
-    // only checked: no hash, no operand-equality test
-    wave_pass(s, unary, A, B, nq, [&](uint32_t q, bool in, uint4 a, uint4 b, uint4 r0, uint4 r1, uint4 r2, uint4 r3) {
-        if (!in) return;
-        const uint4 P = P4[q], S = S4[q];
-        const uint4 r[4] = {r0, r1, r2, r3};
+    uint4 a_nx, b_nx = zero, v_nx = zero, p_nx = zero, s_nx = zero;
+    uint4 m_nx[4] = {zero, zero, zero, zero};
+    auto side = [&](uint32_t qq, bool ok) {
+        if constexpr (ROWS) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) m_nx[j] = load_if(ok && ((need >> j) & 1u), &M[j][qq]);
+        }
+        if constexpr (MASKS) {
+            p_nx = load_if(ok, &P4[qq]);
+            s_nx = load_if(ok, &S4[qq]);
+        }
+    };
+    auto fetch = [&](uint32_t qq, bool ok) {
+        a_nx = load_if(ok, &A[qq]);
+        if constexpr (UNARY) v_nx = load_if(ok, &V4[qq]);
+        else b_nx = load_if(ok, &B[qq]);
+        if (LTLF_SIDE_PREFETCH) side(qq, ok);
+    };
+    fetch(lane, lane < nq);
+    for (uint32_t st = 0; st < steps; ++st) {
+        const uint32_t q = st * 64 + lane;
+        const bool in = q < nq;
+        if (!LTLF_SIDE_PREFETCH) side(q, in);
+        const uint4 a = a_nx, b = b_nx, V = v_nx, P = p_nx, S = s_nx;
+        const uint4 m[4] = {m_nx[0], m_nx[1], m_nx[2], m_nx[3]};
+        const uint32_t qn = q + 64;
+        fetch(qn, st + 1 < steps && qn < nq);
+        uint4 r0 = zero, r1 = zero, r2 = zero, r3 = zero;
+        if constexpr (UNARY) {
+            if (need & 1u) r0 = make_uint4(~a.x & V.x, ~a.y & V.y, ~a.z & V.z, ~a.w & V.w);
+            if (need & 2u) r1 = x_chunk(a, wave_shift_in(a, c0), V);
+            if (need & 4u) {
+                const uint4 sf = wave_add(a, V, c1);
+                r2 = make_uint4(a.x | (V.x & (sf.x ^ a.x ^ V.x)), a.y | (V.y & (sf.y ^ a.y ^ V.y)),
+                                a.z | (V.z & (sf.z ^ a.z ^ V.z)), a.w | (V.w & (sf.w ^ a.w ^ V.w)));
+            }
+            if (need & 8u) {
+                const uint4 x = make_uint4(V.x & ~a.x, V.y & ~a.y, V.z & ~a.z, V.w & ~a.w);
+                const uint4 sg = wave_add(x, V, c2);
+                r3 = make_uint4(V.x & ~(x.x | (V.x & (sg.x ^ x.x ^ V.x))), V.y & ~(x.y | (V.y & (sg.y ^ x.y ^ V.y))),
+                                V.z & ~(x.z | (V.z & (sg.z ^ x.z ^ V.z))), V.w & ~(x.w | (V.w & (sg.w ^ x.w ^ V.w))));
+            }
+            body(q, in, a, a, r0, r1, r2, r3, m, P, S);
+        } else {
+            const uint4 o = make_uint4(a.x | b.x, a.y | b.y, a.z | b.z, a.w | b.w);
+            if (need & 1u) r0 = make_uint4(a.x & b.x, a.y & b.y, a.z & b.z, a.w & b.w);
+            if (need & 2u) r1 = o;
+            if (need & 4u) {
+                const uint4 s1 = wave_add(b, o, c1);
+                r2 = make_uint4(b.x | (a.x & (s1.x ^ b.x ^ o.x)), b.y | (a.y & (s1.y ^ b.y ^ o.y)),
+                                b.z | (a.z & (s1.z ^ b.z ^ o.z)), b.w | (a.w & (s1.w ^ b.w ^ o.w)));
+            }
+            if (need & 8u) {
+                const uint4 s2 = wave_add(a, o, c2);
+                r3 = make_uint4(a.x | (b.x & (s2.x ^ a.x ^ o.x)), a.y | (b.y & (s2.y ^ a.y ^ o.y)),
+                                a.z | (b.z & (s2.z ^ a.z ^ o.z)), a.w | (b.w & (s2.w ^ a.w ^ o.w)));
+            }
+            body(q, in, a, b, r0, r1, r2, r3, m, P, S);
+        }
+    }
+}
+
+// OR over a chunk of x & ~y, accumulated (x within y iff the total is 0).
+__device__ __forceinline__ uint32_t andnot4(uint4 x, uint4 y) {
+    return (x.x & ~y.x) | (x.y & ~y.y) | (x.z & ~y.z) | (x.w & ~y.w);
+}
+
+// Hash, operand-equality tests, spec check and table work of one work item
+// (every lane of the wave calls it).  en[j]: candidate j is enabled; op[j],
+// L[j], R[j]: its derivation.  Lane j (< 4) owns candidate j.
+//
+// Passes over the row (each recomputes the candidates from the operands):
+//   1. hash of every candidate and its operand-equality tests (a result
+//      equal to an operand is a stored, cheaper CM: dropped);
+//   2. (only if some owner met its tag) verification against stored rows;
+//   3. (only if some candidate won a slot or found the table full) the spec
+//      check of those candidates and the row writes of the winners.
+// A duplicate cannot separate (its stored equal was checked when written, or
+// is a cheaper formula's, which would have ended the search), so only stored
+// and check-only candidates are checked.  Once the store has overflowed
+// (full_store, uniform) candidates are only checked: one pass, no hash.
+template <bool UNARY>
+__device__ __forceinline__ void wave_item_t(const Store& s, WaveAlloc& wa, const uint4* A, const uint4* B,
+                                            uint32_t nq, uint64_t snap, bool full_store, const bool (&en)[4],
+                                            const uint32_t (&op)[4], const uint32_t (&L)[4], const uint32_t (&R)[4],
+                                            uint32_t chunk) {
+    uint4* rows4 = reinterpret_cast<uint4*>(s.rows);
+    const uint4* const kNoRows[4] = {nullptr, nullptr, nullptr, nullptr};
+    const uint32_t lane = __lane_id();
+    const uint32_t enm = (en[0] ? 1u : 0u) | (en[1] ? 2u : 0u) | (en[2] ? 4u : 0u) | (en[3] ? 8u : 0u);
+    if (enm == 0) return;
+    if (full_store) {  // check only
+        uint32_t ck[4] = {0, 0, 0, 0};
+        wave_pass_t<UNARY, false, true>(s, A, B, nq, enm, kNoRows, [&](uint32_t, bool in, uint4, uint4, uint4 r0,
+                                                                     uint4 r1, uint4 r2, uint4 r3, const uint4(&)[4],
+                                                                     uint4 P, uint4 S) {
+            if (!in) return;
+            ck[0] |= check_chunk(r0, P, S);
+            ck[1] |= check_chunk(r1, P, S);
+            ck[2] |= check_chunk(r2, P, S);
+            ck[3] |= check_chunk(r3, P, S);
+        });
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            if (!full_store) {
-                h[j] ^= chunk_hash(q, r[j]);
-                da[j] |= diff4(r[j], a);
-                db[j] |= diff4(r[j], b);
-            }
-            ck[j] |= check_chunk(r[j], P, S);
+            const bool sep = ((enm >> j) & 1u) && __ballot(ck[j] != 0) == 0;
+            if (sep && lane == 0) report_found(s, op[j], L[j], R[j]);
+        }
+        return;
+    }
+    // pass 1: hashes and operand-equality tests
+    uint64_t h[4] = {0, 0, 0, 0};
+    uint32_t e[4] = {0, 0, 0, 0};  // pair: a-b, b-a, aUb vs a|b, bUa vs a|b; unary: X, F, G vs a
+    uint32_t f[2] = {0, 0};        // pair: aUb vs b, bUa vs a
+    wave_pass_t<UNARY, false, false>(s, A, B, nq, enm, kNoRows, [&](uint32_t q, bool in, uint4 a, uint4 b, uint4 r0,
+                                                                  uint4 r1, uint4 r2, uint4 r3, const uint4(&)[4],
+                                                                  uint4, uint4) {
+        if (!in) return;
+        const ChunkKey K = chunk_key(q);
+        h[0] ^= chunk_hash(K, r0);
+        h[1] ^= chunk_hash(K, r1);
+        h[2] ^= chunk_hash(K, r2);
+        h[3] ^= chunk_hash(K, r3);
+        if constexpr (UNARY) {  // not a never equals a
+            e[1] |= diff4(r1, a);
+            e[2] |= diff4(r2, a);
+            e[3] |= diff4(r3, a);
+        } else {
+            // a & b and a | b equal an operand iff one operand contains the other
+            e[0] |= andnot4(a, b);
+            e[1] |= andnot4(b, a);
+            // a U b equals b iff it lies within b; equals a iff a U b == a
+            f[0] |= andnot4(r2, b);
+            e[2] |= diff4(r2, a);
+            f[1] |= andnot4(r3, a);
+            e[3] |= diff4(r3, b);
         }
     });
-    bool act[4], sep[4];
-    uint64_t hj[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        bool eq = false;
-        if (!full_store) {
-            hj[j] = hash_fin(group_xor<64>(h[j])) & s.hmask;
-            // a result equal to an operand is a stored, cheaper CM
-            const bool ea = __ballot(da[j] != 0) == 0;
-            const bool eb = __ballot(db[j] != 0) == 0;
-            eq = ea || eb;
+    bool act[4];
+    uint64_t hj[4];
+    {
+        bool eq[4];
+        if constexpr (UNARY) {
+            eq[0] = false;
+            eq[1] = __ballot(e[1] != 0) == 0;
+            eq[2] = __ballot(e[2] != 0) == 0;
+            eq[3] = __ballot(e[3] != 0) == 0;
+        } else {
+            const bool nest = __ballot(e[0] != 0) == 0 || __ballot(e[1] != 0) == 0;
+            eq[0] = eq[1] = nest;
+            eq[2] = __ballot(f[0] != 0) == 0 || __ballot(e[2] != 0) == 0;
+            eq[3] = __ballot(f[1] != 0) == 0 || __ballot(e[3] != 0) == 0;
         }
-        act[j] = en[j] && !eq;
-        sep[j] = __ballot(ck[j] != 0) == 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            act[j] = ((enm >> j) & 1u) && !eq[j];
+            hj[j] = act[j] ? hash_fin(group_xor<64>(h[j])) & s.hmask : 0;
+        }
     }
     // owner lanes 0..3 run the probe; tag matches are verified by the wave
     const bool mine = lane < 4 && (lane == 0 ? act[0] : lane == 1 ? act[1] : lane == 2 ? act[2] : act[3]);
     const uint64_t hh = lane_pick4(lane & 3u, hj[0], hj[1], hj[2], hj[3]);
     const uint32_t tag = tag_of(hh);
-    uint32_t st = mine ? (full_store ? S_FULL : S_PROBE) : S_DONE;
+    uint32_t st = mine ? S_PROBE : S_DONE;
     uint64_t pos = 0, cur = 0, steps = 0;
     if (st == S_PROBE) {
         pos = slot_of(s, hh);
@@ -1362,21 +1529,21 @@ __device__ __forceinline__ void wave_item(const Store& s, WaveAlloc& wa, bool un
                 }
             }
         }
-        const uint64_t nvm = __ballot(need_v) & 0xFull;
+        const uint32_t nvm = (uint32_t)(__ballot(need_v) & 0xFull);
         if (nvm) {
-            uint32_t vr[4];
+            const uint4* M[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) vr[j] = __shfl(vrow, j, 64);
+            for (int j = 0; j < 4; ++j) M[j] = rows4 + (uint64_t)__shfl(vrow, j, 64) * nq;
             uint32_t d[4] = {0, 0, 0, 0};
-            wave_pass(s, unary, A, B, nq,
-                      [&](uint32_t q, bool in, uint4, uint4, uint4 r0, uint4 r1, uint4 r2, uint4 r3) {
-                          const uint4 r[4] = {r0, r1, r2, r3};
+            wave_pass_t<UNARY, true, false>(s, A, B, nq, nvm, M, [&](uint32_t, bool in, uint4, uint4, uint4 r0,
+                                                                   uint4 r1, uint4 r2, uint4 r3,
+                                                                   const uint4(&mr)[4], uint4, uint4) {
+                if (!in) return;
+                const uint4 r[4] = {r0, r1, r2, r3};
 #pragma unroll
-                          for (int j = 0; j < 4; ++j) {
-                              const bool v = ((nvm >> j) & 1u) && in;
-                              d[j] |= diff4(load_if(v, &rows4[(uint64_t)vr[j] * nq + q]), v ? r[j] : make_uint4(0, 0, 0, 0));
-                          }
-                      });
+                for (int j = 0; j < 4; ++j)
+                    if ((nvm >> j) & 1u) d[j] |= diff4(mr[j], r[j]);
+            });
             bool eq_mine = false;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -1396,25 +1563,38 @@ __device__ __forceinline__ void wave_item(const Store& s, WaveAlloc& wa, bool un
     // a wave stores at most four rows per work item: small chunks keep the
     // unused tails short
     wave_take(s, wa, st == S_WON ? 1u : 0u, st == S_DEFER ? 1u : 0u, rb, dbase, chunk);
-    const uint64_t wonm = __ballot(st == S_WON) & 0xFull;
+    const uint32_t wonm = (uint32_t)(__ballot(st == S_WON) & 0xFull);
+    const uint32_t chkm = (uint32_t)(__ballot(st == S_WON || st == S_FULL) & 0xFull);
     const uint32_t myrow = st == S_WON && rb < s.cap ? (uint32_t)rb : 0xFFFFFFFFu;
-    if (wonm) {
+    bool sep_mine = false;
+    if (chkm) {
         uint32_t wr[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) wr[j] = __shfl(myrow, j, 64);
-        wave_pass(s, unary, A, B, nq, [&](uint32_t q, bool in, uint4, uint4, uint4 r0, uint4 r1, uint4 r2, uint4 r3) {
+        uint32_t ck[4] = {0, 0, 0, 0};
+        wave_pass_t<UNARY, false, true>(s, A, B, nq, chkm, kNoRows, [&](uint32_t q, bool in, uint4, uint4, uint4 r0,
+                                                                      uint4 r1, uint4 r2, uint4 r3,
+                                                                      const uint4(&)[4], uint4 P, uint4 S) {
+            if (!in) return;
             const uint4 r[4] = {r0, r1, r2, r3};
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (((wonm >> j) & 1u) && in && wr[j] < s.cap) rows4[(uint64_t)wr[j] * nq + q] = r[j];
+            for (int j = 0; j < 4; ++j) {
+                if (!((chkm >> j) & 1u)) continue;
+                ck[j] |= check_chunk(r[j], P, S);
+                if (((wonm >> j) & 1u) && wr[j] < s.cap) rows4[(uint64_t)wr[j] * nq + q] = r[j];
+            }
         });
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool sep = __ballot(ck[j] != 0) == 0;
+            if (lane == (uint32_t)j) sep_mine = sep;
+        }
     }
     if (lane < 4) {
         const uint32_t j = lane;
         const uint32_t opj = op[0] * (j == 0) + op[1] * (j == 1) + op[2] * (j == 2) + op[3] * (j == 3);
         const uint32_t Lj = L[0] * (j == 0) + L[1] * (j == 1) + L[2] * (j == 2) + L[3] * (j == 3);
         const uint32_t Rj = R[0] * (j == 0) + R[1] * (j == 1) + R[2] * (j == 2) + R[3] * (j == 3);
-        const bool sepj = j == 0 ? sep[0] : j == 1 ? sep[1] : j == 2 ? sep[2] : sep[3];
         if (st == S_WON) {
             if (rb >= s.cap) {  // the slot stays reserved; the level will not be stored
                 atomicExch(&s.ctr[C_OVERFLOW], 1ull);
@@ -1422,12 +1602,12 @@ __device__ __forceinline__ void wave_item(const Store& s, WaveAlloc& wa, bool un
                 s.meta[rb] = make_uint4(opj | (tag << 3), Lj, Rj, (uint32_t)hh);
                 slot_store(&s.table[pos], ((uint64_t)tag << 32) | (uint32_t)rb);
             }
-            if (sepj) report_found(s, opj, Lj, Rj);
+            if (sep_mine) report_found(s, opj, Lj, Rj);
         } else if (st == S_DEFER) {
             write_defer(s, dbase, opj, Lj, Rj, pos);
         } else if (st == S_FULL) {
-            if (!full_store) atomicExch(&s.ctr[C_OVERFLOW], 1ull);
-            if (sepj) report_found(s, opj, Lj, Rj);
+            atomicExch(&s.ctr[C_OVERFLOW], 1ull);
+            if (sep_mine) report_found(s, opj, Lj, Rj);
         }
     }
 }
@@ -1502,11 +1682,22 @@ __device__ __forceinline__ uint32_t wave_tile(const Store& s, const Seg& g, uint
     return wave_items(s, g, lt,
                       [&](bool unary, const uint4* A, const uint4* B, const bool (&en)[4], const uint32_t (&op)[4],
                           const uint32_t (&L)[4], const uint32_t (&R)[4]) {
-                          wave_item(s, wa, unary, A, B, NQ, snap, full_store, en, op, L, R, chunk);
+                          if (unary) wave_item_t<true>(s, wa, A, B, NQ, snap, full_store, en, op, L, R, chunk);
+                          else wave_item_t<false>(s, wa, A, B, NQ, snap, full_store, en, op, L, R, chunk);
                       });
 }
 
+// Minimum waves per SIMD asked of the compiler for the wave kernel (0: its
+// own choice by register use, 195 VGPRs = 2 waves; 3 costs ~17 spilled
+// VGPRs and measured 18% faster on 328-chunk rows).
+#ifndef LTLF_WAVE_OCC
+#define LTLF_WAVE_OCC 3
+#endif
+#if LTLF_WAVE_OCC > 0
+__global__ __launch_bounds__(kLanes, LTLF_WAVE_OCC) void k_generate_wave(Store s, SegTable t) {
+#else
 __global__ __launch_bounds__(kLanes) void k_generate_wave(Store s, SegTable t) {
+#endif
     __shared__ unsigned long long sh_tile;
     __shared__ uint32_t sh_full;
     const uint64_t snap = s.ctr[C_SNAP];
@@ -2349,6 +2540,18 @@ hipError_t launch_generate_batch(const Store* d_stores, const BSeg* d_segs, uint
     if (tiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_generate_wave_batch, dim3((uint32_t)tiles), dim3(kLanes), 0, st, d_stores, d_segs, nsegs,
                        tile0);
+    return hipGetLastError();
+}
+
+hipError_t launch_generate_lds_batch(const Store* d_stores, const BSeg* d_segs, uint32_t nsegs, uint64_t tile0,
+                                     uint64_t tiles, uint32_t max_Wp, hipStream_t st) {
+    if (tiles == 0) return hipSuccess;
+    if (tiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    const uint64_t lds = lds_bytes(max_Wp, kLanes);
+    hipError_t e = raise_lds(k_generate_lds_batch<kBatch, kLanes>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_generate_lds_batch<kBatch, kLanes>), dim3((uint32_t)tiles), dim3(kLanes), (uint32_t)lds, st,
+                       d_stores, d_segs, nsegs, tile0);
     return hipGetLastError();
 }
 

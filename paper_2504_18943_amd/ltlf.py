@@ -418,6 +418,9 @@ class Synthesizer:
         if getattr(self, "_ctx", None):
             ltlf_ctx_destroy(self._ctx)
             self._ctx = None
+        # the workspace tensor goes with the context, even if this object
+        # stays referenced (e.g. by a traceback)
+        self.workspace = None
 
     def __del__(self):
         try:

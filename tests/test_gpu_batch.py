@@ -1,9 +1,11 @@
 """GPU parity of the batched solve (ltlf_solve_batch) against the CPU oracle
 and against solving each problem alone.
 
-Bar: per problem, status, minimal cost, levels_done and |U_c| of every
-stored level identical to the oracle's (and to the problem solved alone on
-the GPU); the witness separates and costs the minimal cost.
+Bar: per problem, status, minimal cost, levels_done, |U_c| and the digest
+of U_c (the set of CMs, LTLF_FLAG_DIGEST) of every stored level identical to
+the oracle's (digests computed by the tests from the oracle's exported
+levels) and to the problem solved alone on the GPU; the witness separates
+and costs the minimal cost.
 """
 from __future__ import annotations
 
@@ -13,11 +15,16 @@ import oracle
 import paper_2504_18943_amd as m
 import workload
 from oracle import evaluator as ev
+from tests import digest
 
 pytestmark = pytest.mark.gpu
 
 # batched-configuration problems whose oracle runs take seconds at bound <= 8
 SUBSET = [0, 1, 2, 3, 5, 6, 8, 9, 11, 13, 14, 15, 16, 19, 20, 22]
+# problems of the batched configuration whose oracle solve at the full bound
+# (planted cost + 3; the solve stops at the minimal cost) takes at most ~2 s
+SUBSET_FULL = [0, 1, 2, 3, 5, 6, 8, 9, 11, 13, 14, 15, 16, 19, 20, 22, 23, 24, 25, 26, 27, 28, 30, 32, 33, 34,
+               35, 36, 37, 39, 41, 42, 43, 44, 45, 46, 47, 49, 51, 53, 54, 55]
 
 
 @pytest.fixture(scope="module")
@@ -27,10 +34,16 @@ def big():
     s.close()
 
 
+def oracle_digests(o, p):
+    return [0] + [digest.level_digest(o.export_level(c), p.lengths) for c in range(1, o.levels_done + 1)]
+
+
 def check(r, o, p):
     assert (r.status, r.min_cost, r.levels_done, r.overflow_level, r.checked_level) == \
         (o.status, o.min_cost, o.levels_done, o.overflow_level, o.checked_level), (p.name, r, o)
     assert r.level_counts[: o.levels_done + 1] == o.level_counts[: o.levels_done + 1], p.name
+    if any(r.level_digests):  # run with LTLF_FLAG_DIGEST
+        assert r.level_digests[: o.levels_done + 1] == oracle_digests(o, p), p.name
     if r.status == m.ltlf.OK:
         assert ev.separates(r.formula, p.traces, p.positive), (p.name, r.formula)
         assert ev.cost(r.formula) == r.min_cost, (p.name, r.formula)
@@ -41,9 +54,20 @@ def test_batch_matches_oracle(big):
     ps = [ps[i] for i in SUBSET]
     bounds = [min(p.cost_bound, 8) for p in ps]
     print(f"[batch] {len(ps)} batched-config problems", flush=True)
-    rs = big.solve_batch(ps, bounds)
+    rs = big.solve_batch(ps, bounds, flags=m.FLAG_DIGEST)
     for p, b, r in zip(ps, bounds, rs):
         check(r, oracle.solve(p, cost_bound=b), p)
+
+
+def test_batch_matches_oracle_at_full_bounds(big):
+    """Batched-configuration problems at their own bounds (planted cost + 3),
+    counts and sets of every level against the oracle."""
+    ps = workload.batched(1, max(SUBSET_FULL) + 1)
+    ps = [ps[i] for i in SUBSET_FULL]
+    print(f"[batch] {len(ps)} batched-config problems at full bounds", flush=True)
+    rs = big.solve_batch(ps, flags=m.FLAG_DIGEST)
+    for p, r in zip(ps, rs):
+        check(r, oracle.solve(p), p)
 
 
 def test_batch_mixed_widths_exhaustive(big):
@@ -51,7 +75,7 @@ def test_batch_mixed_widths_exhaustive(big):
     ps = [workload.tiny(s) for s in (1, 2, 3, 4)] + [workload.medium(1), workload.large(1)]
     bounds = [8, 8, 8, 8, 7, 5]
     print("[batch] mixed widths exhaustive", flush=True)
-    rs = big.solve_batch(ps, bounds, flags=m.FLAG_EXHAUST)
+    rs = big.solve_batch(ps, bounds, flags=m.FLAG_EXHAUST | m.FLAG_DIGEST)
     for p, b, r in zip(ps, bounds, rs):
         check(r, oracle.solve(p, cost_bound=b, exhaust=True), p)
 
@@ -60,11 +84,12 @@ def test_alone_and_in_the_mix_identical(big):
     ps = [workload.medium(2), workload.tiny(5), workload.medium(3), workload.tiny(6)]
     bounds = [p.cost_bound for p in ps]
     print("[batch] alone vs mix", flush=True)
-    mix = big.solve_batch(ps, bounds)
+    mix = big.solve_batch(ps, bounds, flags=m.FLAG_DIGEST)
     for p, b, r in zip(ps, bounds, mix):
-        a = big.solve(p, cost_bound=b)
-        assert (a.status, a.min_cost, a.levels_done, a.level_counts) == \
-            (r.status, r.min_cost, r.levels_done, r.level_counts), p.name
+        a = big.solve(p, cost_bound=b, flags=m.FLAG_DIGEST)
+        assert (a.status, a.min_cost, a.levels_done, a.level_counts, a.level_digests) == \
+            (r.status, r.min_cost, r.levels_done, r.level_counts, r.level_digests), p.name
+        assert any(r.level_digests), p.name
         assert ev.separates(r.formula, p.traces, p.positive)
 
 
@@ -125,13 +150,43 @@ def test_large_region_jobs_in_sequence():
     s = m.Synthesizer(device=0, workspace_bytes=32 << 30)
     try:
         print("[batch] large-region jobs in sequence", flush=True)
-        mix = s.solve_batch(ps)
+        mix = s.solve_batch(ps, flags=m.FLAG_DIGEST)
         for p, r in zip(ps, mix):
-            a = s.solve(p)
-            assert (a.status, a.min_cost, a.levels_done, a.overflow_level, a.level_counts) == \
-                (r.status, r.min_cost, r.levels_done, r.overflow_level, r.level_counts), p.name
+            a = s.solve(p, flags=m.FLAG_DIGEST)
+            assert (a.status, a.min_cost, a.levels_done, a.overflow_level, a.level_counts, a.level_digests) == \
+                (r.status, r.min_cost, r.levels_done, r.overflow_level, r.level_counts, r.level_digests), p.name
             if r.status == m.ltlf.OK:
                 assert ev.separates(r.formula, p.traces, p.positive), (p.name, r.formula)
                 assert ev.cost(r.formula) == r.min_cost, (p.name, r.formula)
     finally:
         s.close()
+
+
+def test_batched_configuration_equals_one_by_one():
+    """The whole batched configuration (256 problems, bounds planted cost +
+    3) solved in one ltlf_solve_batch call and one by one: every result
+    identical, sets included (digests of every stored level).  A problem may
+    overflow the store (batched problem 113 stores levels 1..10 and finds its
+    minimum, 11, in the level that does not fit); both modes then report the
+    same overflow."""
+    import torch
+
+    import bench
+
+    free, _ = torch.cuda.mem_get_info(0)
+    ws = int(min(free * 0.8, 200 * (1 << 30)))
+    ps = workload.batched(1, 256)
+    s = m.Synthesizer(device=0, workspace_bytes=ws)
+    try:
+        print(f"[batch] batched configuration, 256 problems, {ws >> 30} GiB workspace", flush=True)
+        mix = s.solve_batch(ps, flags=m.FLAG_DIGEST)
+        print("[batch]   batch done; one by one", flush=True)
+        alone = [s.solve(p, flags=m.FLAG_DIGEST) for p in ps]
+        assert bench.compare_results(ps, alone, mix) == []
+        for p, r in zip(ps, mix):
+            if r.status == m.ltlf.OK:
+                assert ev.separates(r.formula, p.traces, p.positive), (p.name, r.formula)
+                assert ev.cost(r.formula) == r.min_cost, (p.name, r.formula)
+    finally:
+        s.close()
+        torch.cuda.empty_cache()

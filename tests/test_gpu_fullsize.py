@@ -1,28 +1,32 @@
 """GPU parity at the benchmark's full size and launch configuration.
 
 Workload: the medium problem of seed 1 with every cost level enumerated to 13
-(exactly what bench.py times).  Levels 1..9 are within the oracle's reach and
-are compared exactly (counts and sets).  Levels 10..13 (~3.3e8 CMs) are beyond
-it, so for them the test checks properties that hold at any size on sampled
-rows: each sampled CM equals the CM of its own derivation re-evaluated from
-the definitions, that derivation costs exactly the level, the CM occurs in no
-level <= 9, and no two sampled CMs are equal.  The level counts must also be
+(the benchmark's medium leg; levels 12 and 13 run as several launches of at
+most 2^27 candidates with table growth between them).  Levels 1..10 are
+within the oracle's reach and are compared exactly (counts, sorted sets and
+digests).  Levels 11..13 (~3.3e8 CMs) are beyond it, so for them the test
+checks properties that hold at any size on sampled rows: each sampled CM
+equals the CM of its own derivation re-evaluated from the definitions, that
+derivation costs exactly the level, the CM occurs in no level <= 10, and no
+two sampled CMs are equal.  Level counts and digests (the sets) must also be
 identical over repeated runs.
 """
 from __future__ import annotations
 
 import numpy as np
 import pytest
+import torch
 
 import oracle
 import paper_2504_18943_amd as m
 import workload
 from oracle import evaluator as ev
+from tests import digest
 
 pytestmark = pytest.mark.gpu
 
 BOUND = 13
-ORACLE_BOUND = 9
+ORACLE_BOUND = 10
 SAMPLES = 48
 
 
@@ -32,19 +36,20 @@ def sorted_rows(a):
 
 @pytest.fixture(scope="module")
 def big_run():
-    import torch
     free, _ = torch.cuda.mem_get_info(0)
     ws = int(min(free * 0.6, 120 << 30))  # 3.3e8 rows x (160 + 16 + 16) bytes + lists
     print(f"[fullsize] workspace {ws >> 30} GiB", flush=True)
     s = m.Synthesizer(device=0, workspace_bytes=ws)
     p = workload.medium(1)
     s.load(p)
-    flags = m.FLAG_EXHAUST | m.FLAG_PROFILE
+    flags = m.FLAG_EXHAUST | m.FLAG_PROFILE | m.FLAG_DIGEST
     r1 = s.run(BOUND, flags=flags)
     r2 = s.run(BOUND, flags=flags)
-    print(f"[fullsize] counts {r2.level_counts[1:]}", flush=True)
+    print(f"[fullsize] counts {r2.level_counts[1:]}, {r2.gen_launches} generation launches", flush=True)
     yield s, p, r1, r2
     s.close()
+    del s
+    torch.cuda.empty_cache()
 
 
 @pytest.fixture(scope="module")
@@ -56,7 +61,9 @@ def oracle_low():
 def test_counts_repeatable_and_complete(big_run):
     s, p, r1, r2 = big_run
     assert r1.level_counts == r2.level_counts
+    assert r1.level_digests == r2.level_digests and all(r2.level_digests[1:])
     assert r2.levels_done == BOUND and r2.overflow_level == 0
+    assert r2.gen_launches > BOUND  # the largest levels span several launches
     assert r2.unique_total == sum(r2.level_counts[1:BOUND + 1])
     assert r2.status == m.ltlf.OK
 
@@ -67,7 +74,9 @@ def test_low_levels_equal_oracle(big_run, oracle_low):
     assert r.min_cost == o.min_cost
     assert r.level_counts[: ORACLE_BOUND + 1] == o.level_counts[: ORACLE_BOUND + 1]
     for c in range(1, ORACLE_BOUND + 1):
-        assert np.array_equal(sorted_rows(s.export_level(c)), sorted_rows(o.export_level(c))), c
+        want = o.export_level(c)
+        assert np.array_equal(sorted_rows(s.export_level(c)), sorted_rows(want)), c
+        assert r.level_digests[c] == digest.level_digest(want, p.lengths), c
     assert ev.separates(r.formula, p.traces, p.positive)
     assert ev.cost(r.formula) == r.min_cost
 
@@ -77,18 +86,20 @@ def test_high_levels_sampled(big_run, oracle_low):
     o = oracle_low
     low = set()
     for c in range(1, ORACLE_BOUND + 1):
-        low.update(tuple(int(x) for x in row) for row in o.export_level(c))
+        lv = np.ascontiguousarray(o.export_level(c))
+        low.update(lv.view(np.dtype((np.void, lv.shape[1] * 8))).ravel().tolist())
     rng = np.random.Generator(np.random.PCG64(2024))
     seen = set()
     for c in range(ORACLE_BOUND + 1, BOUND + 1):
         n = r.level_counts[c]
         idx = sorted(set([0, n - 1] + [int(x) for x in rng.integers(0, n, size=SAMPLES)]))
         for i in idx:
-            row = tuple(int(x) for x in s.export_level(c, first=i, count=1)[0])
+            got = np.ascontiguousarray(s.export_level(c, first=i, count=1)[0])
+            row = tuple(int(x) for x in got)
             f = s.formula_of(c, i)
             assert ev.cost(f) == c, (c, i, f)
             want = tuple(ev.canonical_words(ev.characteristic_matrix(f, p.traces)))
             assert row == want, (c, i, f)
-            assert row not in low, (c, i, f)
+            assert got.tobytes() not in low, (c, i, f)
             assert row not in seen, (c, i, f)
             seen.add(row)

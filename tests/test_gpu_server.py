@@ -13,13 +13,15 @@ import oracle
 import paper_2504_18943_amd as m
 import workload
 from oracle import evaluator as ev
+from tests import digest
 
 pytestmark = pytest.mark.gpu
 
 
 def same(r, a, p):
-    assert (r.status, r.min_cost, r.levels_done, r.overflow_level, r.level_counts) == \
-        (a.status, a.min_cost, a.levels_done, a.overflow_level, a.level_counts), p.name
+    assert (r.status, r.min_cost, r.levels_done, r.overflow_level, r.level_counts, r.level_digests) == \
+        (a.status, a.min_cost, a.levels_done, a.overflow_level, a.level_counts, a.level_digests), p.name
+    assert any(r.level_digests), p.name
     if r.status == m.ltlf.OK:
         assert ev.separates(r.formula, p.traces, p.positive), (p.name, r.formula)
         assert ev.cost(r.formula) == r.min_cost, (p.name, r.formula)
@@ -46,15 +48,16 @@ def test_arrivals_while_running_match_alone_and_oracle():
           workload.large(1), workload.tiny(3), workload.medium(3), workload.tiny(4)]
     bounds = [p.cost_bound for p in ps]
     bounds[4] = 5  # the large problem: its oracle is cheap to this bound
-    alone = [s.solve(p, cost_bound=b) for p, b in zip(ps, bounds)]
+    D = m.FLAG_DIGEST
+    alone = [s.solve(p, cost_bound=b, flags=D) for p, b in zip(ps, bounds)]
     srv = m.Server(s, max_resident=8)
     print("[server] staggered arrivals", flush=True)
-    tickets = [srv.submit(ps[0], bounds[0]), srv.submit(ps[1], bounds[1])]
+    tickets = [srv.submit(ps[0], bounds[0], flags=D), srv.submit(ps[1], bounds[1], flags=D)]
     srv.step()
-    tickets += [srv.submit(ps[2], bounds[2]), srv.submit(ps[3], bounds[3])]
+    tickets += [srv.submit(ps[2], bounds[2], flags=D), srv.submit(ps[3], bounds[3], flags=D)]
     srv.step()
     srv.step()
-    tickets += [srv.submit(p, b) for p, b in zip(ps[4:], bounds[4:])]
+    tickets += [srv.submit(p, b, flags=D) for p, b in zip(ps[4:], bounds[4:])]
     got = drain(srv, tickets)
     srv.close()
     for p, b, t, a in zip(ps, bounds, tickets, alone):
@@ -62,6 +65,8 @@ def test_arrivals_while_running_match_alone_and_oracle():
         o = oracle.solve(p, cost_bound=b)
         assert (got[t].status, got[t].min_cost, got[t].level_counts[: o.levels_done + 1]) == \
             (o.status, o.min_cost, o.level_counts[: o.levels_done + 1]), p.name
+        want = [0] + [digest.level_digest(o.export_level(c), p.lengths) for c in range(1, o.levels_done + 1)]
+        assert got[t].level_digests[: o.levels_done + 1] == want, p.name
     s.close()
 
 
@@ -73,13 +78,14 @@ def test_large_levels_move_to_the_large_region():
     p = workload.medium(1)
     srv = m.Server(s, max_resident=4)
     print("[server] large region", flush=True)
-    t = srv.submit(p, 9, flags=m.FLAG_EXHAUST, reserve_bytes=16 << 20)
+    t = srv.submit(p, 9, flags=m.FLAG_EXHAUST | m.FLAG_DIGEST, reserve_bytes=16 << 20)
     t2 = srv.submit(workload.tiny(5), 8, flags=m.FLAG_EXHAUST)
     got = drain(srv, [t, t2])
     srv.close()
     o = oracle.solve(p, cost_bound=9, exhaust=True)
     assert (got[t].status, got[t].min_cost, got[t].levels_done) == (o.status, o.min_cost, o.levels_done)
     assert got[t].level_counts == o.level_counts
+    assert got[t].level_digests == [0] + [digest.level_digest(o.export_level(c), p.lengths) for c in range(1, 10)]
     o2 = oracle.solve(workload.tiny(5), cost_bound=8, exhaust=True)
     assert got[t2].level_counts == o2.level_counts
     s.close()
@@ -169,4 +175,25 @@ def test_cancel_pending_invalid():
     p = workload.tiny(7)
     r = s.solve(p, cost_bound=7, flags=m.FLAG_EXHAUST)
     assert r.level_counts[:8] == oracle.solve(p, cost_bound=7, exhaust=True).level_counts[:8]
+    s.close()
+
+
+def test_large_jobs_run_together_and_keep_their_levels():
+    """Several requests whose levels outgrow the small pool: each moves into
+    the large area with its stored levels (no level is enumerated twice), and
+    they run there at the same time, each on its own worker.  Every result
+    equals the request solved alone (status, cost, levels, counts, digests)."""
+    s = m.Synthesizer(device=0, workspace_bytes=24 << 30)
+    ps = [workload.medium(1), workload.medium(2), workload.medium(3), workload.medium(4)]
+    D = m.FLAG_EXHAUST | m.FLAG_DIGEST
+    alone = [s.solve(p, cost_bound=10, flags=D) for p in ps]
+    srv = m.Server(s, max_resident=8)
+    print("[server] concurrent large jobs", flush=True)
+    tickets = [srv.submit(p, 10, flags=D) for p in ps]
+    tickets.append(srv.submit(workload.tiny(3), 8, flags=D))
+    got = drain(srv, tickets)
+    srv.close()
+    for p, t, a in zip(ps, tickets, alone):
+        same(got[t], a, p)
+        assert got[t].levels_done == 10
     s.close()

@@ -250,6 +250,24 @@ ltlf_status ltlf_run(ltlf_ctx *ctx, const ltlf_costs *costs, uint32_t cost_bound
 ltlf_status ltlf_solve(ltlf_ctx *ctx, const ltlf_spec *spec, const ltlf_costs *costs,
                        uint32_t cost_bound, uint32_t flags, void *stream, ltlf_result *res);
 
+/* ltlf_solve without device memory allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the workspace is a static 64 MiB device array of the
+ * library (one per device, held until the process ends) instead of the
+ * context's, and the call makes no hipMalloc / hipFree / hipHostMalloc and
+ * creates no events.  Results are those of ltlf_solve on a context whose
+ * workspace is 64 MiB: levels that do not fit end the run as described at
+ * LTLF_CAPACITY.  The context's own workspace and row limit are kept; the
+ * context has no loaded problem afterwards (export / formula_of: ESTATE).
+ * All calls on one device share the one array and each call overwrites it,
+ * so calls that overlap in time on the same device (from several threads or
+ * contexts) race and must not be made.
+ * EINVAL: as ltlf_solve, or LTLF_FLAG_PROFILE (it creates events).  ENOMEM:
+ * the specification's fixed regions (raw traces, masks, atoms, staging) do
+ * not fit 64 MiB (ltlf_ctx_last_error says so).  EDEVICE: HIP failure. */
+ltlf_status ltlf_solve_static(ltlf_ctx *ctx, const ltlf_spec *spec, const ltlf_costs *costs,
+                              uint32_t cost_bound, uint32_t flags, void *stream, ltlf_result *res);
+
 /* Solve n independent problems together: the batched form of ltlf_solve
  * (paper, "Program synthesis": the same bottom-up enumeration, run for many
  * specifications at once), through the request server's scheduler (see

@@ -2161,6 +2161,39 @@ ltlf_status ltlf_solve(ltlf_ctx* c, const ltlf_spec* sp, const ltlf_costs* k, ui
     return ltlf_run(c, k, bound, flags, stream, res);
 }
 
+ltlf_status ltlf_solve_static(ltlf_ctx* c, const ltlf_spec* sp, const ltlf_costs* k, uint32_t bound,
+                              uint32_t flags, void* stream, ltlf_result* res) {
+    if (!c || !sp || !k || !res) return LTLF_EINVAL;
+    c->err.clear();
+    if (flags & LTLF_FLAG_PROFILE) return fail(c, LTLF_EINVAL, "LTLF_FLAG_PROFILE creates events: not available here");
+    TRY_HIP(hipSetDevice(c->device));
+    void* p = nullptr;
+    TRY_HIP(static_workspace(c->device, &p));
+    // the context's own workspace is put aside for the call; the problem
+    // lives in the static array, so nothing of it stays loaded afterwards
+    struct Swap {
+        ltlf_ctx* c;
+        char* ws;
+        uint64_t bytes;
+        bool own;
+        ~Swap() {
+            c->ws = ws;
+            c->ws_bytes = bytes;
+            c->own_ws = own;
+            c->loaded = false;
+            c->ran = false;
+        }
+    } swap{c, c->ws, c->ws_bytes, c->own_ws};
+    c->ws = static_cast<char*>(p);
+    c->ws_bytes = kStaticWorkspaceBytes;
+    c->own_ws = false;
+    c->loaded = false;
+    const ltlf_status st = ltlf_solve(c, sp, k, bound, flags, stream, res);
+    if (st == LTLF_ENOMEM)
+        return fail(c, LTLF_ENOMEM, "the specification's fixed regions need more than the 64 MiB static workspace");
+    return st;
+}
+
 ltlf_status ltlf_solve_batch(ltlf_ctx* c, uint32_t n, const ltlf_spec* specs, const ltlf_costs* k,
                              const uint32_t* bounds, uint32_t flags, void* stream, ltlf_result* results) {
     if (!c || !specs || !k || !bounds || !results || n == 0) return LTLF_EINVAL;

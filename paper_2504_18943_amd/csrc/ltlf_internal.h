@@ -175,6 +175,12 @@ hipError_t launch_compact(const Store& s, uint64_t lo, uint64_t new_end, uint64_
                           uint32_t* movers, uint64_t cap, hipStream_t st);
 hipError_t launch_export(const uint32_t* rows, uint32_t Wp, uint64_t first, uint64_t n,
                          const uint32_t* canon_bit, uint64_t n_bits, uint64_t* out, hipStream_t st);
+// Static scratch workspace of ltlf_solve_static: kStaticWorkspaceBytes of
+// device memory per device (a file-scope device array); *ptr receives this
+// device's address of it.  The device must be current.
+constexpr uint64_t kStaticWorkspaceBytes = 64ull << 20;
+constexpr uint32_t kMaxStaticDevices = 64;
+hipError_t static_workspace(int device, void** ptr);
 // Adds the digest of rows [first, first + n) to *out (see k_digest).
 hipError_t launch_digest(const uint32_t* rows, uint32_t Wp, uint64_t first, uint64_t n,
                          unsigned long long* out, hipStream_t st);

@@ -45,6 +45,8 @@
 // exact: a candidate is dropped only after a full-row comparison.
 #include "ltlf_internal.h"
 
+#include <mutex>
+
 namespace ltlf {
 
 static constexpr uint64_t kEmpty = ~0ull;
@@ -2387,6 +2389,34 @@ __global__ void k_formula(const uint4* meta, uint32_t root_op, uint32_t root_a, 
         ++sp;
     }
     tokens[0] = nt;
+}
+
+// ------------------------------------------------- static scratch workspace --
+// The device memory of ltlf_solve_static: a file-scope array that every
+// device the library runs on holds until the process ends.  In host code
+// the array's name is only a stand-in for it, so its device address is
+// looked up once per device (with that device current) and kept; kernels
+// receive that address like any other workspace.
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+hipError_t static_workspace(int device, void** ptr) {
+    static std::mutex mu;
+    static void* addr[kMaxStaticDevices] = {};
+    if (device < 0 || device >= (int)kMaxStaticDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 255u)) return hipErrorInvalidValue;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------- launchers --

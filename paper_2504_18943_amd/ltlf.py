@@ -119,6 +119,9 @@ def load_library() -> ctypes.CDLL:
     L.ltlf_solve.restype = i32
     L.ltlf_solve.argtypes = [vp, ctypes.POINTER(ltlf_spec), ctypes.POINTER(ltlf_costs), u32, u32, vp,
                              ctypes.POINTER(ltlf_result)]
+    L.ltlf_solve_static.restype = i32
+    L.ltlf_solve_static.argtypes = [vp, ctypes.POINTER(ltlf_spec), ctypes.POINTER(ltlf_costs), u32, u32, vp,
+                                    ctypes.POINTER(ltlf_result)]
     L.ltlf_solve_batch.restype = i32
     L.ltlf_solve_batch.argtypes = [vp, u32, ctypes.POINTER(ltlf_spec), ctypes.POINTER(ltlf_costs),
                                    ctypes.POINTER(u32), u32, vp, ctypes.POINTER(ltlf_result)]
@@ -220,6 +223,14 @@ def ltlf_solve(ctx, n_props, lengths, letters, positive, op_cost, atom_cost, cos
     c = _costs(op_cost, atom_cost)
     return load_library().ltlf_solve(ctx, ctypes.byref(sp), ctypes.byref(c), cost_bound, flags,
                                      ctypes.c_void_p(stream), ctypes.byref(res))
+
+
+def ltlf_solve_static(ctx, n_props, lengths, letters, positive, op_cost, atom_cost, cost_bound, flags,
+                      stream, res: ltlf_result) -> int:
+    sp, keep = _spec(n_props, lengths, letters, positive)
+    c = _costs(op_cost, atom_cost)
+    return load_library().ltlf_solve_static(ctx, ctypes.byref(sp), ctypes.byref(c), cost_bound, flags,
+                                            ctypes.c_void_p(stream), ctypes.byref(res))
 
 
 def ltlf_solve_batch(ctx, problems, op_cost, atom_cost, bounds, flags, stream, results) -> int:
@@ -462,6 +473,19 @@ class Synthesizer:
         self.load(problem)
         return self.run(int(cost_bound if cost_bound is not None else problem.cost_bound),
                         op_cost=op_cost, atom_cost=atom_cost, flags=flags)
+
+    def solve_static(self, problem, cost_bound: Optional[int] = None, op_cost=UNIT_ALL, atom_cost: int = 1,
+                     flags: int = 0) -> Result:
+        """ltlf_solve on the library's static 64 MiB workspace (no device
+        allocation; see include/ltlf.h)."""
+        bound = int(cost_bound if cost_bound is not None else problem.cost_bound)
+        res, bufs = _result_buffers(bound)
+        lengths, letters, positive = problem.arrays()
+        st = ltlf_solve_static(self._ctx, problem.n_props, lengths, letters, positive, op_cost, atom_cost, bound,
+                               flags, self._stream(), res)
+        if st < 0:
+            raise LtlfError(st, "ltlf_solve_static", ltlf_ctx_last_error(self._ctx))
+        return _result_of(st, res, bufs)
 
     def autotune(self) -> List[dict]:
         """Measures the generation kernels per row-width class and keeps the

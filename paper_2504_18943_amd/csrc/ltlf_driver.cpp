@@ -13,6 +13,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -1032,6 +1033,8 @@ struct Scheduler {
     BSeg* d_segs = nullptr;
     unsigned long long* d_gather = nullptr;
     uint32_t launches = 0;
+    bool trace = false;  // LTLF_TRACE set: one line per job event on stderr
+    std::chrono::steady_clock::time_point t0;
     std::mutex mu;
     std::condition_variable cv;
     std::atomic<uint32_t> big_running{0};
@@ -1055,6 +1058,9 @@ struct Scheduler {
     ltlf_status init(ltlf_ctx* ctx, uint32_t max_res) {
         c = ctx;
         max_resident = max_res;
+        const char* tr = std::getenv("LTLF_TRACE");
+        trace = tr && *tr && *tr != '0';
+        t0 = std::chrono::steady_clock::now();
         TRY(ensure_workspace(c));
         c->loaded = false;  // the workspace is carved below
         c->ran = false;
@@ -1122,12 +1128,29 @@ struct Scheduler {
     }
 
     // ------------------------------------------------------------ regions
-    // Bytes of a region that holds `rows` rows of job j (see row_capacity).
+    void note(const Job* j, const char* what) const {
+        if (!trace) return;
+        const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        std::fprintf(stderr,
+                     "[ltlf] %8.3f s job %llu %s: level %u rows %llu status %d | queued %zu small %zu large %zu "
+                     "grow %zu full %zu\n",
+                     t, (unsigned long long)j->ticket, what, j->lev, (unsigned long long)j->rows, (int)j->status,
+                     queue.size(), resident.size(), bigs.size(), grow_queue.size(), full_queue.size());
+        std::fflush(stderr);
+    }
+
+    // Bytes of a region that holds `rows` rows of job j (see row_capacity);
+    // UINT64_MAX if no region of the workspace can (a store holds at most
+    // 2^31 - 16 rows).
     uint64_t region_for(const Job* j, uint64_t rows) const {
+        if (rows > (1ull << 31) - 16) return UINT64_MAX;
         const uint64_t f = fixed_bytes(j->n_pos, j->lengths.size(), j->wp, j->n_props, kSubStaging);
         const uint64_t per = 4ull * j->wp + 32;
         uint64_t b = align_up(f + rows * per + rows * per / 32 + (2ull << 20), 1ull << 20);
-        while (row_capacity(f, j->wp, b) < rows) b = align_up(b + b / 16, 1ull << 20);
+        while (row_capacity(f, j->wp, b) < rows) {
+            if (b > c->ws_bytes) return UINT64_MAX;
+            b = align_up(b + b / 16, 1ull << 20);
+        }
         return b;
     }
 
@@ -1364,6 +1387,7 @@ struct Scheduler {
             j->run->resume(sub, &j->costs, j->bound, j->flags, &j->res, j->rows, j->res.candidates, j->status,
                            j->wit_op, j->wit_a, j->wit_b);
         }
+        note(j, full ? "large (whole area)" : fresh ? "large (fresh)" : "large (moved)");
         return start_worker(j);
     }
 
@@ -1428,6 +1452,7 @@ struct Scheduler {
 
     // back to the queue, from the start (its device state is discarded)
     void restart(Job* j, bool front) {
+        note(j, "restart");
         if (j->mode == Job::SMALL) resident.erase(std::find(resident.begin(), resident.end(), j));
         leave_region(j);
         j->mode = Job::QUEUED;
@@ -1542,6 +1567,7 @@ struct Scheduler {
         r.formula_len = j->formula.size() + 1;
         if (cancelled) r.status = LTLF_CANCELLED;
         j->done = true;
+        note(j, "done");
         if (j->mode == Job::SMALL) resident.erase(std::find(resident.begin(), resident.end(), j));
         auto b = std::find(bigs.begin(), bigs.end(), j);
         if (b != bigs.end()) bigs.erase(b);
@@ -1686,19 +1712,14 @@ struct Scheduler {
             std::vector<Store> h_stores(live.size());
             for (size_t i = 0; i < live.size(); ++i) h_stores[i] = live[i]->sub->st;
             TRY_HIP(hipMemcpyAsync(d_stores, h_stores.data(), sizeof(Store) * live.size(), hipMemcpyHostToDevice, s));
-            // pieces of every job's plan, one list per kernel family, each
-            // job's share of a launch bounded by its deferral list
-            std::vector<BSeg> pieces[2];
-            uint32_t max_lane_wp = 0;
-            for (Job* j : live)
-                if (lane_class(j->sub)) max_lane_wp = std::max(max_lane_wp, j->sub->Wp);
+            // pieces of every job's plan, each job's share of a launch
+            // bounded by its deferral list
+            std::vector<BSeg> pieces;
             for (;;) {
-                pieces[0].clear();
-                pieces[1].clear();
-                uint64_t first[2] = {0, 0};
-                for (size_t i = 0; i < live.size() && pieces[0].size() + pieces[1].size() + kMaxSegs < kSegs; ++i) {
+                pieces.clear();
+                uint64_t first = 0;
+                for (size_t i = 0; i < live.size() && pieces.size() + kMaxSegs < kSegs; ++i) {
                     Job* j = live[i];
-                    const int fam = lane_class(j->sub) ? 0 : 1;
                     uint64_t budget = j->sub->st.def0_cap;
                     uint64_t seg_first = 0;
                     for (size_t g = 0; g < j->plan.segs.size() && j->next_tile < j->total; ++g) {
@@ -1711,24 +1732,20 @@ struct Scheduler {
                             if (take == 0) break;
                             BSeg b{};
                             b.problem = (uint32_t)i;
-                            b.first = first[fam];
+                            b.first = first;
                             b.lt0 = j->next_tile - seg_first;
                             b.seg = sg;
-                            pieces[fam].push_back(b);
-                            first[fam] += take;
+                            pieces.push_back(b);
+                            first += take;
                             j->next_tile += take;
                             budget -= take * per;
                         }
                         seg_first = seg_end;
                     }
                 }
-                const size_t nl = pieces[0].size(), nw = pieces[1].size();
-                if (nl + nw == 0) break;
-                pieces[0].insert(pieces[0].end(), pieces[1].begin(), pieces[1].end());
-                TRY_HIP(hipMemcpyAsync(d_segs, pieces[0].data(), sizeof(BSeg) * (nl + nw), hipMemcpyHostToDevice, s));
-                if (nl)
-                    TRY_HIP(launch_generate_lds_batch(d_stores, d_segs, (uint32_t)nl, 0, first[0], max_lane_wp, s));
-                if (nw) TRY_HIP(launch_generate_batch(d_stores, d_segs + nl, (uint32_t)nw, 0, first[1], s));
+                if (pieces.empty()) break;
+                TRY_HIP(hipMemcpyAsync(d_segs, pieces.data(), sizeof(BSeg) * pieces.size(), hipMemcpyHostToDevice, s));
+                TRY_HIP(launch_generate_batch(d_stores, d_segs, (uint32_t)pieces.size(), 0, first, s));
                 TRY_HIP(launch_verify_batch(d_stores, (uint32_t)live.size(), s));
                 TRY_HIP(launch_between_batch(d_stores, (uint32_t)live.size(), s));
                 ++launches;
@@ -1877,12 +1894,8 @@ struct Scheduler {
     }
     uint64_t free_bytes() const { return small.free_bytes() + large.free_bytes(); }
 
-    // Small jobs run the lane kernel's batched form where its 256-lane tile
-    // fits the LDS (rows of up to ~37 chunks), else the wave kernel's.
-    static bool lane_class(const ltlf_ctx* sub) { return lds_bytes(sub->Wp, kLanes) <= sub->lds_limit; }
-    static TileShape small_shape(const ltlf_ctx* sub) {
-        return tile_shape(sub->Wp, sub->lds_limit, lane_class(sub) ? KERNEL_LANE : KERNEL_WAVE);
-    }
+    // Small jobs run the wave kernel's batched form (any row width).
+    static TileShape small_shape(const ltlf_ctx* sub) { return tile_shape(sub->Wp, sub->lds_limit, KERNEL_WAVE); }
 };
 
 }  // namespace

@@ -154,10 +154,6 @@ hipError_t launch_verify_deferred(const Store& s, hipStream_t st);
 hipError_t launch_lookahead(const Store& s, const SegTable& t, uint32_t omask, hipStream_t st);
 hipError_t launch_generate_batch(const Store* d_stores, const BSeg* d_segs, uint32_t nsegs, uint64_t tile0,
                                  uint64_t tiles, hipStream_t st);
-// The lane kernel's batched form (rows whose 256-lane tile fits the LDS;
-// max_Wp: the widest row among the launch's problems).
-hipError_t launch_generate_lds_batch(const Store* d_stores, const BSeg* d_segs, uint32_t nsegs, uint64_t tile0,
-                                     uint64_t tiles, uint32_t max_Wp, hipStream_t st);
 hipError_t launch_verify_batch(const Store* d_stores, uint32_t n, hipStream_t st);
 hipError_t launch_between_batch(const Store* d_stores, uint32_t n, hipStream_t st);
 hipError_t launch_gather_ctr(const Store* d_stores, uint32_t n, unsigned long long* out, hipStream_t st);

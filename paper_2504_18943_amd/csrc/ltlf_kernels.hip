@@ -818,24 +818,6 @@ __global__ __launch_bounds__(LANES) void k_generate_lds(Store s, SegTable t) {
     lds_tile<BATCH, LANES>(s, t.seg[si], tile - t.first[si], dyn);
 }
 
-// Batched form: tiles of many problems in one launch, one block per tile
-// (pieces as in k_generate_wave_batch); the dynamic LDS fits the widest row
-// of the launch.
-template <int BATCH, int LANES>
-__global__ __launch_bounds__(LANES) void k_generate_lds_batch(const Store* stores, const BSeg* segs, uint32_t nsegs,
-                                                              uint64_t tile0) {
-    extern __shared__ uint4 dyn[];
-    const uint64_t tile = tile0 + blockIdx.x;
-    uint32_t lo = 0, hi = nsegs;  // last piece with first <= tile
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) / 2;
-        if (segs[mid].first <= tile) lo = mid;
-        else hi = mid;
-    }
-    const BSeg& b = segs[lo];
-    lds_tile<BATCH, LANES>(stores[b.problem], b.seg, b.lt0 + (tile - b.first), dyn);
-}
-
 // ------------------------------------------------ one lane group per candidate --
 // Rows of 2..64 chunks are handled by groups of G lanes (G = the next power of
 // two >= chunks, at least 4): lane k of a group holds chunk k of the operands
@@ -1216,9 +1198,15 @@ __global__ __launch_bounds__(kLanes) void k_generate_grp(Store s, SegTable t) {
 // the multi-word adds cross lanes by ballot carry-lookahead and steps through
 // the top lane.
 
-constexpr uint32_t kWA = 8;   // left operands per pair tile
-constexpr uint32_t kWB = 8;   // right operands per pair tile (square triangles)
-constexpr uint32_t kWU = 16;  // operands per unary tile
+// Pair tile (left x right operands, square: triangular segments use square
+// tiles) and unary tile of the wave kernel; the block's four waves share a
+// tile and meet at a barrier between tiles.
+#ifndef LTLF_WAVE_TILE
+#define LTLF_WAVE_TILE 8
+#endif
+constexpr uint32_t kWA = LTLF_WAVE_TILE;       // left operands per pair tile
+constexpr uint32_t kWB = LTLF_WAVE_TILE;       // right operands per pair tile
+constexpr uint32_t kWU = 2 * LTLF_WAVE_TILE;   // operands per unary tile
 constexpr uint32_t kWaveChunk = 8;  // rows / records a wave takes per atomic
 
 
@@ -2570,18 +2558,6 @@ hipError_t launch_generate_batch(const Store* d_stores, const BSeg* d_segs, uint
     if (tiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_generate_wave_batch, dim3((uint32_t)tiles), dim3(kLanes), 0, st, d_stores, d_segs, nsegs,
                        tile0);
-    return hipGetLastError();
-}
-
-hipError_t launch_generate_lds_batch(const Store* d_stores, const BSeg* d_segs, uint32_t nsegs, uint64_t tile0,
-                                     uint64_t tiles, uint32_t max_Wp, hipStream_t st) {
-    if (tiles == 0) return hipSuccess;
-    if (tiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
-    const uint64_t lds = lds_bytes(max_Wp, kLanes);
-    hipError_t e = raise_lds(k_generate_lds_batch<kBatch, kLanes>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_generate_lds_batch<kBatch, kLanes>), dim3((uint32_t)tiles), dim3(kLanes), (uint32_t)lds, st,
-                       d_stores, d_segs, nsegs, tile0);
     return hipGetLastError();
 }
 

@@ -9,6 +9,8 @@ and costs the minimal cost.
 """
 from __future__ import annotations
 
+import time
+
 import pytest
 
 import oracle
@@ -173,15 +175,23 @@ def test_batched_configuration_equals_one_by_one():
 
     import bench
 
+    t0 = time.perf_counter()
     free, _ = torch.cuda.mem_get_info(0)
     ws = int(min(free * 0.8, 200 * (1 << 30)))
     ps = workload.batched(1, 256)
     s = m.Synthesizer(device=0, workspace_bytes=ws)
     try:
-        print(f"[batch] batched configuration, 256 problems, {ws >> 30} GiB workspace", flush=True)
+        print(f"[batch] batched configuration, 256 problems generated in {time.perf_counter() - t0:.1f} s, "
+              f"{ws >> 30} GiB workspace", flush=True)
+        t1 = time.perf_counter()
         mix = s.solve_batch(ps, flags=m.FLAG_DIGEST)
-        print("[batch]   batch done; one by one", flush=True)
-        alone = [s.solve(p, flags=m.FLAG_DIGEST) for p in ps]
+        print(f"[batch]   batch done in {time.perf_counter() - t1:.1f} s; one by one", flush=True)
+        t1 = time.perf_counter()
+        alone = []
+        for i, p in enumerate(ps):
+            alone.append(s.solve(p, flags=m.FLAG_DIGEST))
+            if i % 64 == 63:
+                print(f"[batch]   {i + 1} solved alone, {time.perf_counter() - t1:.1f} s", flush=True)
         assert bench.compare_results(ps, alone, mix) == []
         for p, r in zip(ps, mix):
             if r.status == m.ltlf.OK:

@@ -45,6 +45,12 @@ constexpr uint64_t kLookaheadTiles = 1ull << 30;  // tiles per look-ahead launch
 #define LTLF_LAUNCH_CANDIDATES (1ull << 27)
 #endif
 constexpr uint64_t kLaunchCandidates = LTLF_LAUNCH_CANDIDATES;
+// Candidates per launch of the persistent kernels (a level larger than this
+// runs as several launches, for the same reason)
+#ifndef LTLF_PERSISTENT_CANDIDATES
+#define LTLF_PERSISTENT_CANDIDATES (1ull << 25)
+#endif
+constexpr uint64_t kPersistentCandidates = LTLF_PERSISTENT_CANDIDATES;
 // Largest deferral list 0 (records of 16 bytes; the list gets 1/1024 of the
 // workspace up to this)
 #ifndef LTLF_DEFER_MAX
@@ -577,6 +583,11 @@ struct LevelRun {
     uint32_t wit_op = 0, wit_a = 0, wit_b = 0;
     bool stop = false;  // the run ended: a separating level without EXHAUST, or an overflow
     uint32_t grid_eighths = 8;  // share of the resident blocks a persistent launch takes
+    // Set by the scheduler when the store is a region sized by forecast: a
+    // level that overflows it is dropped (overflowed = true, nothing of it
+    // kept, the run's state as the previous level left it) to be run again
+    // in a larger region, instead of ending the run.
+    bool redo_overflow = false, overflowed = false;
 
     ltlf_status begin(ltlf_ctx* ctx, const ltlf_costs* costs, uint32_t cost_bound, uint32_t run_flags,
                       ltlf_result* result, hipStream_t s) {
@@ -657,6 +668,7 @@ struct LevelRun {
                 TRY_HIP(generate_blocks(c->st, total, blocks));
                 t.tile_begin = 0;
                 t.tile_end = total;
+                t.tile_stop = total;
                 t.def_margin = t.row_margin = 0;
                 t.row_budget = ~0ull;
                 TRY_HIP(launch_set_counter(c->d_ctr, C_TILE, 0, s));
@@ -703,6 +715,7 @@ struct LevelRun {
     // close.  Sets `stop` when the run ends at this level.
     ltlf_status level(uint32_t lev, hipStream_t s) {
         c->lstart[lev] = rows;
+        const uint64_t cand_before = candidates;
         LevelPlan p = plan_level(c, k, lev, shape);
         if (p.segs.empty()) {
             res->levels_done = lev;
@@ -755,6 +768,7 @@ struct LevelRun {
                 blocks = std::max<uint64_t>(1, blocks * grid_eighths / 8);
                 blocks = std::max<uint64_t>(1, std::min<uint64_t>(blocks, c->st.def0_cap / (2 * per_block)));
                 const uint64_t margin = blocks * per_block;
+                const uint64_t share = std::max<uint64_t>(1, kPersistentCandidates / std::max<uint64_t>(per_tile, 1));
                 t.tile_begin = 0;
                 t.tile_end = total;
                 t.def_margin = margin;
@@ -774,6 +788,7 @@ struct LevelRun {
                         TRY(ensure_table(c, stored, extra + (ctr_rows - stored), s));
                     }
                     t.row_budget = c->st.tsize < c->table_max ? c->st.tsize / 2 : ~0ull;
+                    t.tile_stop = std::min<uint64_t>(total, taken + share);
                     if (profile) TRY(prof.mark(s));
                     TRY_HIP(launch_generate(c->st, t, blocks, s));
                     if (profile) TRY(prof.mark(s));
@@ -864,6 +879,13 @@ struct LevelRun {
         // the caller's row limit counts live rows only (unused allocation
         // tails do not count against it)
         const bool overflow = c->h_ctr[C_OVERFLOW] != 0 || (c->row_limit && live_end > c->row_limit);
+        if (redo_overflow && c->h_ctr[C_OVERFLOW]) {
+            c->lcount[lev] = 0;
+            candidates = cand_before;
+            overflowed = true;
+            stop = true;
+            return LTLF_OK;
+        }
         if (!overflow && dead) {
             // move the live rows above live_end into the holes below it, in
             // rounds of at most `lcap` (the deferral list is free now)
@@ -997,6 +1019,7 @@ struct Job {
     uint32_t lev = 0;   // last closed level
     uint64_t rows = 0, next_tile = 0, total = 0;
     uint64_t need_rows = 0;  // rows the next level may need (a request for a larger region)
+    uint32_t redo_level = 0;  // a level that overflowed a region sized by forecast
     LevelPlan plan;
     ltlf_status status = LTLF_NOT_FOUND;
     uint32_t wit_op = 0, wit_a = 0, wit_b = 0;
@@ -1258,16 +1281,22 @@ struct Scheduler {
                 if (j->stop) break;
             }
             const uint32_t lev = j->lev + 1;
+            uint64_t worst = 0;
             if (!j->full) {
                 const LevelPlan p = plan_level(j->sub, &j->costs, lev, r.shape);
-                uint64_t need = r.rows + p.cand_ub;
-                if (c->row_limit) need = std::min<uint64_t>(need, std::max<uint64_t>(c->row_limit, r.rows) + 1);
+                worst = r.rows + p.cand_ub;
+                uint64_t need = r.rows + forecast(j->sub, lev, p.cand_ub, j->redo_level == lev);
+                if (c->row_limit) {
+                    worst = std::min<uint64_t>(worst, std::max<uint64_t>(c->row_limit, r.rows) + 1);
+                    need = std::min<uint64_t>(need, worst);
+                }
                 if (need > j->sub->plan_cap) {
                     j->need_rows = std::max<uint64_t>(need, 4 * r.rows);
                     grow = true;
                     break;
                 }
             }
+            r.redo_overflow = !j->full;
             // persistent launches share the resident block slots with the
             // other large jobs and leave room to the small jobs' launches
             const uint32_t nb = std::max<uint32_t>(1, big_running.load(std::memory_order_relaxed));
@@ -1275,6 +1304,14 @@ struct Scheduler {
             r.grid_eighths = std::max<uint32_t>(1, share / nb);
             st = r.level(lev, j->stream);
             if (st != LTLF_OK) break;
+            if (r.overflowed) {  // the forecast fell short: the level again, in a region for its worst case
+                r.overflowed = false;
+                r.stop = false;
+                j->redo_level = lev;
+                j->need_rows = std::max<uint64_t>(worst, 4 * r.rows);
+                grow = true;
+                break;
+            }
             j->lev = lev;
             j->res.candidates = r.candidates;
             j->rows = r.rows;
@@ -1334,11 +1371,14 @@ struct Scheduler {
     // A region of the large area for j's next `rows` rows: j moves there
     // (keeping its stored levels) or, with nothing stored yet, starts there;
     // then its worker starts.  WAIT: no such region is free now; NEED_FULL:
-    // only the whole large area would do.
+    // only the whole large area would do, or more than half of it (such a
+    // region could only be had with the area nearly empty, and while waiting
+    // for it the job would hold what it has and be restarted by every job
+    // that wants the whole area: it takes the whole area, once).
     ltlf_status place_large(Job* j, uint64_t rows, hipStream_t s, Place& out) {
         out = WAIT;
         const uint64_t bytes = region_for(j, rows);
-        if (bytes > large.total()) {
+        if (bytes > large.total() / 2) {
             out = NEED_FULL;
             return LTLF_OK;
         }
@@ -1459,6 +1499,7 @@ struct Scheduler {
         j->run.reset();
         j->lev = 0;
         j->rows = 0;
+        j->redo_level = 0;
         j->status = LTLF_NOT_FOUND;
         reset_result(&j->res, 4 * j->wp);
         if (front) queue.push_front(j);
@@ -1490,42 +1531,77 @@ struct Scheduler {
             j->lev = 0;  // from the start
             TRY(start_large(j, sub, &large, off, large.total(), true, s));
         }
-        // larger regions, oldest first; none while the whole area is wanted
-        while (full_queue.empty() && !grow_queue.empty()) {
-            Job* j = grow_queue.front();
+        // a waiter that wants more than half the area (see place_large) waits
+        // for the whole area holding nothing, wherever it stands in the queue
+        for (size_t i = 0; i < grow_queue.size();) {
+            Job* w = grow_queue[i];
+            if (region_for(w, w->need_rows) > large.total() / 2) {
+                grow_queue.erase(grow_queue.begin() + (long)i);
+                if (w->mode == Job::SMALL) resident.erase(std::find(resident.begin(), resident.end(), w));
+                leave_region(w);
+                w->mode = Job::QUEUED;
+                full_queue.push_back(w);
+                note(w, "waits for the whole area");
+            } else {
+                ++i;
+            }
+        }
+        // larger regions, oldest first.  While a job waits for the whole area
+        // the area drains: only jobs that already hold large-area regions are
+        // served (they finish, or come to want the whole area themselves);
+        // others wait.
+        auto eligible = [&](const Job* w) { return full_queue.empty() || w->arena == &large; };
+        auto to_full = [&](Job* w) {
+            if (w->mode == Job::SMALL) resident.erase(std::find(resident.begin(), resident.end(), w));
+            leave_region(w);
+            w->mode = Job::QUEUED;
+            full_queue.push_back(w);
+        };
+        for (size_t i = 0; i < grow_queue.size();) {
+            Job* j = grow_queue[i];
+            if (!eligible(j)) {
+                ++i;
+                continue;
+            }
             Place pl = WAIT;
             TRY(place_large(j, j->need_rows, s, pl));
             if (pl == WAIT) break;
-            grow_queue.pop_front();
-            if (pl == NEED_FULL) {
-                if (j->mode == Job::SMALL) resident.erase(std::find(resident.begin(), resident.end(), j));
-                leave_region(j);
-                j->mode = Job::QUEUED;
-                full_queue.push_back(j);
-            }
+            grow_queue.erase(grow_queue.begin() + (long)i);
+            if (pl == NEED_FULL) to_full(j);
         }
-        // nothing runs in the large area and its waiters cannot be served:
-        // the younger waiters that hold parts of it start over later
-        if (big_running.load() == 0 && bigs.empty() && (!grow_queue.empty() || !full_queue.empty())) {
-            const bool keep_head = full_queue.empty();
-            for (size_t i = keep_head ? 1 : 0; i < grow_queue.size();) {
-                Job* w = grow_queue[i];
-                if (w->arena == &large) {
+        // nothing runs in the large area and the oldest eligible waiter cannot
+        // be served (the others hold part of what it needs): the youngest
+        // waiters that hold large-area regions start over later, one at a time
+        // until it fits; if none helps, it starts over itself in a fresh
+        // region.  (With no eligible waiter left the area is empty, and the
+        // job that waits for it starts above on the next call.)
+        if (big_running.load() == 0 && bigs.empty()) {
+            size_t hi = 0;
+            while (hi < grow_queue.size() && !eligible(grow_queue[hi])) ++hi;
+            if (hi < grow_queue.size()) {
+                Job* h = grow_queue[hi];
+                bool served = false;
+                for (size_t i = grow_queue.size(); i-- > 0 && !served;) {
+                    Job* w = grow_queue[i];
+                    if (w == h || w->arena != &large) continue;
+                    if (i < hi) break;  // only younger waiters
                     grow_queue.erase(grow_queue.begin() + (long)i);
                     restart(w, true);
-                } else {
-                    ++i;
+                    Place pl = WAIT;
+                    TRY(place_large(h, h->need_rows, s, pl));
+                    if (pl == WAIT) continue;
+                    served = true;
+                    grow_queue.erase(std::find(grow_queue.begin(), grow_queue.end(), h));
+                    if (pl == NEED_FULL) to_full(h);
                 }
-            }
-            if (keep_head && !grow_queue.empty() && grow_queue.front()->arena == &large) {
-                // the head itself blocks what it needs: it starts over in a fresh region
-                Job* h = grow_queue.front();
-                grow_queue.pop_front();
-                const uint64_t need = h->need_rows;
-                restart(h, true);
-                queue.erase(std::find(queue.begin(), queue.end(), h));
-                h->need_rows = need;
-                grow_queue.push_front(h);
+                if (!served && h->arena == &large) {
+                    grow_queue.erase(std::find(grow_queue.begin(), grow_queue.end(), h));
+                    const uint64_t need = h->need_rows;
+                    restart(h, true);
+                    queue.erase(std::find(queue.begin(), queue.end(), h));
+                    h->need_rows = need;
+                    grow_queue.push_front(h);
+                }
             }
         }
         // new jobs into the small pool
@@ -1683,8 +1759,9 @@ struct Scheduler {
             for (const Seg& g : j->plan.segs) j->total += g.tiles;
             if (j->total) {
                 const uint64_t need = j->rows + j->plan.cand_ub;
-                if (j->plan.cand_ub > kBigLevel) {
-                    j->need_rows = std::max<uint64_t>(need, 4 * j->rows);
+                if (j->plan.cand_ub > kBigLevel) {  // a large job from this level: a region by forecast
+                    j->need_rows = std::max<uint64_t>(j->rows + forecast(sub, lev, j->plan.cand_ub, false),
+                                                      4 * j->rows);
                     grow_queue.push_back(j);
                     continue;
                 }
@@ -1893,6 +1970,18 @@ struct Scheduler {
                bigs.empty();
     }
     uint64_t free_bytes() const { return small.free_bytes() + large.free_bytes(); }
+
+    // Rows level `lev` of a large job is expected to add: the growth ratio of
+    // the two levels before it, with a 1.5x margin (the table sizing's
+    // estimate), never above the candidate bound; the bound itself where that
+    // growth is unknown, or after the level overflowed a region sized this way.
+    static uint64_t forecast(const ltlf_ctx* sub, uint32_t lev, uint64_t cand_ub, bool worst) {
+        if (worst || lev < 3 || lev >= sub->lcount.size()) return cand_ub;
+        const uint64_t a = sub->lcount[lev - 1], b = sub->lcount[lev - 2];
+        if (!a || !b) return cand_ub;
+        const double est = 1.5 * (double)a / (double)b * (double)a + 4096.0;
+        return est >= (double)cand_ub ? cand_ub : (uint64_t)est;
+    }
 
     // Small jobs run the wave kernel's batched form (any row width).
     static TileShape small_shape(const ltlf_ctx* sub) { return tile_shape(sub->Wp, sub->lds_limit, KERNEL_WAVE); }

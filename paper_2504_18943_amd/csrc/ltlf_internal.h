@@ -81,8 +81,10 @@ struct SegTable {
     uint64_t tile_end;    // last tile (exclusive)
     // persistent group kernel only (tiles [0, tile_end) from the C_TILE
     // cursor): a block takes a tile only while C_DEF0 + def_margin <= the
-    // deferral capacity and C_ROWS + row_margin <= row_budget
-    uint64_t def_margin, row_margin, row_budget;
+    // deferral capacity and C_ROWS + row_margin <= row_budget, and while the
+    // cursor is below tile_stop (a launch's share of the level; blocks that
+    // pass the test together may take a few tiles beyond it)
+    uint64_t def_margin, row_margin, row_budget, tile_stop;
     uint64_t first[kMaxSegs + 1];  // prefix sums of tiles
     Seg seg[kMaxSegs];
 };

@@ -1018,7 +1018,8 @@ __global__ __launch_bounds__(kLanes) void k_generate_grp(Store s, SegTable t) {
         const unsigned long long d = __hip_atomic_load(&s.ctr[C_DEF0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned long long r = __hip_atomic_load(&s.ctr[C_ROWS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const bool full = store_full(s);
-        if (d + t.def_margin <= s.def0_cap && (full || r + t.row_margin <= t.row_budget))
+        const unsigned long long cur = __hip_atomic_load(&s.ctr[C_TILE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur < t.tile_stop && d + t.def_margin <= s.def0_cap && (full || r + t.row_margin <= t.row_budget))
             tl = atomicAdd(&s.ctr[C_TILE], 1ull);
         sh_tile = tl;
         sh_full = full;
@@ -1202,7 +1203,7 @@ __global__ __launch_bounds__(kLanes) void k_generate_grp(Store s, SegTable t) {
 // tiles) and unary tile of the wave kernel; the block's four waves share a
 // tile and meet at a barrier between tiles.
 #ifndef LTLF_WAVE_TILE
-#define LTLF_WAVE_TILE 8
+#define LTLF_WAVE_TILE 16
 #endif
 constexpr uint32_t kWA = LTLF_WAVE_TILE;       // left operands per pair tile
 constexpr uint32_t kWB = LTLF_WAVE_TILE;       // right operands per pair tile
@@ -1702,7 +1703,8 @@ __global__ __launch_bounds__(kLanes) void k_generate_wave(Store s, SegTable t) {
             const unsigned long long d = __hip_atomic_load(&s.ctr[C_DEF0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned long long r = __hip_atomic_load(&s.ctr[C_ROWS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const bool full = store_full(s);
-            if (d + t.def_margin <= s.def0_cap && (full || r + t.row_margin <= t.row_budget))
+            const unsigned long long cur = __hip_atomic_load(&s.ctr[C_TILE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (cur < t.tile_stop && d + t.def_margin <= s.def0_cap && (full || r + t.row_margin <= t.row_budget))
                 tl = atomicAdd(&s.ctr[C_TILE], 1ull);
             sh_tile = tl;
             sh_full = full;

@@ -3,10 +3,11 @@ over {a, b}; the paper's tool finds a size-16 formula) solved to its minimum
 under the paper's grammar {p, not, and, X, F, U} with unit costs and bound 16.
 
 Bar: the solve ends OK with a witness that separates and costs the minimal
-cost; the minimal cost is at most 16 (the printed formula separates, pinned
-on the CPU); every level the oracle reaches in seconds (to cost 13) has the
-oracle's count and set (digest), and the oracle finds nothing below 14.  The
-measured minimum is recorded in the test output.
+cost; the minimal cost is 16, the size of the printed formula (which
+separates, pinned on the CPU): every level the oracle reaches in seconds (to
+cost 13) has the oracle's count and set (digest), the oracle finds nothing
+below 14, and levels 14 and 15, beyond the oracle's reach, hold no separating
+formula on the GPU.
 """
 from __future__ import annotations
 
@@ -37,7 +38,7 @@ def test_seven_seven_minimum_under_the_paper_grammar():
         print(f"[7+7] status {r.status_name} min cost {r.min_cost} formula {r.formula!r} "
               f"counts {r.level_counts[1:]} candidates {r.candidates} {ms:.1f} ms", flush=True)
         assert r.status == m.ltlf.OK and r.overflow_level == 0
-        assert r.min_cost <= 16
+        assert r.min_cost == 16
         assert ev.separates(r.formula, p.traces, p.positive)
         assert ev.cost(r.formula) == r.min_cost
         o = oracle.solve(p, op_cost=UNIT_PAPER, cost_bound=ORACLE_BOUND, exhaust=True)

@@ -1057,6 +1057,7 @@ struct Scheduler {
     unsigned long long* d_gather = nullptr;
     uint32_t launches = 0;
     bool trace = false;  // LTLF_TRACE set: one line per job event on stderr
+    double forecast_margin = 1.5;  // LTLF_FORECAST_SCALE: margin of the large jobs' forecasts
     std::chrono::steady_clock::time_point t0;
     std::mutex mu;
     std::condition_variable cv;
@@ -1083,6 +1084,13 @@ struct Scheduler {
         max_resident = max_res;
         const char* tr = std::getenv("LTLF_TRACE");
         trace = tr && *tr && *tr != '0';
+        // a test hook: a small margin makes forecasts fall short, so that
+        // levels are dropped and run again in larger regions
+        const char* fm = std::getenv("LTLF_FORECAST_SCALE");
+        if (fm && *fm) {
+            const double v = std::atof(fm);
+            if (v > 0.0 && v <= 1e6) forecast_margin = v;
+        }
         t0 = std::chrono::steady_clock::now();
         TRY(ensure_workspace(c));
         c->loaded = false;  // the workspace is carved below
@@ -1719,6 +1727,8 @@ struct Scheduler {
             if (j->worker.joinable()) j->worker.join();
             if (j->wstatus != LTLF_OK) return fail(c, j->wstatus, j->sub ? j->sub->err.c_str() : "large job");
             if (j->grow) {  // wants a larger region: waits for it, keeping its own
+                note(j, j->redo_level == j->lev + 1 ? "level dropped (region too small), waits for a larger one"
+                                                    : "waits for a larger region");
                 bigs.erase(std::find(bigs.begin(), bigs.end(), j));
                 grow_queue.push_back(j);
                 continue;
@@ -1973,13 +1983,14 @@ struct Scheduler {
 
     // Rows level `lev` of a large job is expected to add: the growth ratio of
     // the two levels before it, with a 1.5x margin (the table sizing's
-    // estimate), never above the candidate bound; the bound itself where that
-    // growth is unknown, or after the level overflowed a region sized this way.
-    static uint64_t forecast(const ltlf_ctx* sub, uint32_t lev, uint64_t cand_ub, bool worst) {
+    // estimate; forecast_margin), never above the candidate bound; the bound
+    // itself where that growth is unknown, or after the level overflowed a
+    // region sized this way.
+    uint64_t forecast(const ltlf_ctx* sub, uint32_t lev, uint64_t cand_ub, bool worst) const {
         if (worst || lev < 3 || lev >= sub->lcount.size()) return cand_ub;
         const uint64_t a = sub->lcount[lev - 1], b = sub->lcount[lev - 2];
         if (!a || !b) return cand_ub;
-        const double est = 1.5 * (double)a / (double)b * (double)a + 4096.0;
+        const double est = forecast_margin * (double)a / (double)b * (double)a + 4096.0;
         return est >= (double)cand_ub ? cand_ub : (uint64_t)est;
     }
 

@@ -140,15 +140,23 @@ def test_context_usable_after_batch(big):
     assert len(big.export_level(3)) == r.level_counts[3]
 
 
-def test_large_region_jobs_in_sequence():
+@pytest.fixture(scope="module")
+def large_area_problems():
+    """Batched-configuration problems whose levels run in the large area
+    (47..56-chunk rows: group kernel; 102-chunk rows: wave kernel), and three
+    tiny ones."""
+    ps = workload.batched(1, 222)
+    return [ps[i] for i in (128, 164, 221, 81)] + [workload.tiny(s) for s in (1, 2, 3)]
+
+
+def test_large_region_jobs_in_sequence(large_area_problems):
     """Several problems whose levels run in the large region one after the
     other, with the group kernel (47..56-chunk rows) and the wave kernel
     (102-chunk rows); their persistent launches leave dead rows, so every
     level ends with a compaction before the region passes to the next job.
     Results equal the problems solved alone (status, cost, levels, counts),
     and every witness separates."""
-    ps = workload.batched(1, 222)
-    ps = [ps[i] for i in (128, 164, 221, 81)] + [workload.tiny(s) for s in (1, 2, 3)]
+    ps = large_area_problems
     s = m.Synthesizer(device=0, workspace_bytes=32 << 30)
     try:
         print("[batch] large-region jobs in sequence", flush=True)
@@ -160,6 +168,32 @@ def test_large_region_jobs_in_sequence():
             if r.status == m.ltlf.OK:
                 assert ev.separates(r.formula, p.traces, p.positive), (p.name, r.formula)
                 assert ev.cost(r.formula) == r.min_cost, (p.name, r.formula)
+    finally:
+        s.close()
+
+
+def test_forecast_short_levels_redone_exactly(large_area_problems, capfd, monkeypatch):
+    """Large jobs' regions are sized by a forecast of the next level; a level
+    that overflows such a region is dropped and run again in a region for its
+    worst case.  With the forecasts scaled far down (a test hook of the
+    library) levels are dropped; every result still equals the problem solved
+    alone (status, cost, levels, overflow level, counts and sets)."""
+    ps = large_area_problems
+    monkeypatch.setenv("LTLF_FORECAST_SCALE", "0.02")
+    monkeypatch.setenv("LTLF_TRACE", "1")
+    s = m.Synthesizer(device=0, workspace_bytes=32 << 30)
+    try:
+        mix = s.solve_batch(ps, flags=m.FLAG_DIGEST)
+        trace = capfd.readouterr().err
+        dropped = trace.count("level dropped")
+        print(f"[batch] forecasts x0.02: {dropped} levels dropped and run again", flush=True)
+        assert dropped > 0
+        for p, r in zip(ps, mix):
+            a = s.solve(p, flags=m.FLAG_DIGEST)
+            assert (a.status, a.min_cost, a.levels_done, a.overflow_level, a.level_counts, a.level_digests) == \
+                (r.status, r.min_cost, r.levels_done, r.overflow_level, r.level_counts, r.level_digests), p.name
+            if r.status == m.ltlf.OK:
+                assert ev.separates(r.formula, p.traces, p.positive), (p.name, r.formula)
     finally:
         s.close()
 

@@ -188,6 +188,15 @@ uint64_t row_capacity(uint64_t fixed, uint64_t Wp, uint64_t bytes) {
     return std::min<uint64_t>((bytes - off - 3 * 256) / (4 * Wp + 32), (1ull << 31) - 16);
 }
 
+// ... and the offset of the row store in a workspace of `bytes` (after the
+// deferral lists and the table).
+uint64_t rows_offset(uint64_t fixed, uint64_t Wp, uint64_t bytes) {
+    uint64_t d0, d1;
+    deferral_records(bytes - fixed, d0, d1);
+    const uint64_t table = align_up(align_up(fixed + 16 * d0, 256) + 16 * d1, 256);
+    return align_up(table + 16 * row_capacity(fixed, Wp, bytes), 256);
+}
+
 // Carves the workspace.  Fixed regions first, then deferral lists, then the
 // row store and the table, which take what is left.
 ltlf_status plan_memory_impl(ltlf_ctx* c);
@@ -985,6 +994,39 @@ struct Arena {
         }
         return false;
     }
+    // the top of the highest free range that fits (regions that are not
+    // aligned stay clear of the bottom of the large area, where aligned ones go)
+    bool alloc_high(uint64_t bytes, uint64_t& off) {
+        bytes = align_up(bytes, 256);
+        for (size_t i = free_.size(); i-- > 0;) {
+            if (free_[i].second >= bytes) {
+                free_[i].second -= bytes;
+                off = free_[i].first + free_[i].second;
+                if (free_[i].second == 0) free_.erase(free_.begin() + (long)i);
+                return true;
+            }
+        }
+        return false;
+    }
+    // [off, off + bytes) if it is free
+    bool alloc_at(uint64_t off, uint64_t bytes) {
+        bytes = align_up(bytes, 256);
+        for (size_t i = 0; i < free_.size(); ++i) {
+            const uint64_t o = free_[i].first, b = free_[i].second;
+            if (o > off || off + bytes > o + b) continue;
+            const uint64_t tail = o + b - (off + bytes);
+            if (off > o) {
+                free_[i].second = off - o;
+                if (tail) free_.insert(free_.begin() + (long)i + 1, {off + bytes, tail});
+            } else if (tail) {
+                free_[i] = {off + bytes, tail};
+            } else {
+                free_.erase(free_.begin() + (long)i);
+            }
+            return true;
+        }
+        return false;
+    }
     void release(uint64_t off, uint64_t bytes) {
         bytes = align_up(bytes, 256);
         auto it = std::lower_bound(free_.begin(), free_.end(), std::make_pair(off, (uint64_t)0));
@@ -1016,6 +1058,7 @@ struct Job {
     Arena* arena = nullptr;   // owner of the region (nullptr: none)
     uint64_t off = 0, bytes = 0;
     bool full = false;  // the region is the whole large area
+    bool aligned = false;  // the region's rows sit where the whole area's layout puts them
     uint32_t lev = 0;   // last closed level
     uint64_t rows = 0, next_tile = 0, total = 0;
     uint64_t need_rows = 0;  // rows the next level may need (a request for a larger region)
@@ -1233,6 +1276,7 @@ struct Scheduler {
         j->arena = nullptr;
         j->off = j->bytes = 0;
         j->full = false;
+        j->aligned = false;
     }
 
     // Moves j's stored levels into sub-context `to` (loaded, on a region
@@ -1241,16 +1285,19 @@ struct Scheduler {
     // the same indices, the digests and level bookkeeping carried over, the
     // counters set as the last closed level left them, and the table rebuilt
     // from the records.  The caller drains s before the old region is reused.
-    ltlf_status migrate(Job* j, ltlf_ctx* to, uint32_t kernel, hipStream_t s) {
+    // in_place: the rows already sit at to's row addresses and the caller
+    // restores the digests (promote).
+    ltlf_status migrate(Job* j, ltlf_ctx* to, uint32_t kernel, hipStream_t s, bool in_place = false) {
         ltlf_ctx* from = j->sub;
         TRY(begin_run(to, j->bound, j->flags & (LTLF_FLAG_DEBUG_WEAK_HASH | LTLF_FLAG_DIGEST), kernel, s));
         const uint64_t n = j->rows;
         if (n > to->plan_cap) return fail(c, LTLF_EDEVICE, "a moved job does not fit its new region");
         if (n) {
-            TRY_HIP(hipMemcpyAsync(to->st.rows, from->st.rows, n * 4ull * j->wp, hipMemcpyDeviceToDevice, s));
+            if (!in_place)
+                TRY_HIP(hipMemcpyAsync(to->st.rows, from->st.rows, n * 4ull * j->wp, hipMemcpyDeviceToDevice, s));
             TRY_HIP(hipMemcpyAsync(to->st.meta, from->st.meta, n * sizeof(uint4), hipMemcpyDeviceToDevice, s));
         }
-        if (j->flags & LTLF_FLAG_DIGEST)
+        if ((j->flags & LTLF_FLAG_DIGEST) && !in_place)
             TRY_HIP(hipMemcpyAsync(to->d_digest, from->d_digest, 8ull * (kMaxBound + 1), hipMemcpyDeviceToDevice, s));
         TRY_HIP(launch_set_counter(to->d_ctr, C_ROWS, n, s));
         TRY_HIP(launch_set_counter(to->d_ctr, C_SNAP, n, s));
@@ -1391,7 +1438,19 @@ struct Scheduler {
             return LTLF_OK;
         }
         uint64_t off = 0;
-        if (!large.alloc(bytes, off)) return LTLF_OK;
+        bool aligned = false;
+        if (bytes >= large.total() / 16) {
+            // a large region goes, if that part of the area is free, where its
+            // rows sit at the addresses the whole area's layout gives them, so
+            // that the job can later take the whole area without moving them
+            const uint64_t f = fixed_bytes(j->n_pos, j->lengths.size(), j->wp, j->n_props, kSubStaging);
+            const uint64_t rf = rows_offset(f, j->wp, large.total()), rr = rows_offset(f, j->wp, bytes);
+            if (rf >= rr && large.lo + (rf - rr) + bytes <= large.hi && large.alloc_at(large.lo + (rf - rr), bytes)) {
+                off = large.lo + (rf - rr);
+                aligned = true;
+            }
+        }
+        if (!aligned && !large.alloc_high(bytes, off)) return LTLF_OK;
         ltlf_ctx* sub = nullptr;
         const ltlf_status ls = open_sub(j, off, bytes, s, sub);
         if (ls != LTLF_OK) {
@@ -1400,8 +1459,71 @@ struct Scheduler {
             return ls == LTLF_ENOMEM ? LTLF_OK : ls;
         }
         TRY(start_large(j, sub, &large, off, bytes, false, s));
+        j->aligned = aligned;
         out = PLACED;
         return LTLF_OK;
+    }
+
+    // A job waiting for the whole area whose region is aligned (place_large)
+    // takes the area with its stored levels: its rows stay where they are,
+    // its derivation records move to the whole area's layout, its digests go
+    // through the host (the whole area's fixed regions overlap the region's),
+    // and its table is rebuilt there.  Starts it over in the whole area if
+    // the layouts do not line up after all.  Only j holds part of the area.
+    ltlf_status promote(Job* j, hipStream_t s) {
+        ltlf_ctx* from = j->sub;
+        const uint64_t f = fixed_bytes(j->n_pos, j->lengths.size(), j->wp, j->n_props, kSubStaging);
+        const uint64_t total = large.total();
+        const uint64_t rf = rows_offset(f, j->wp, total), cap = row_capacity(f, j->wp, total);
+        const uint64_t meta_lo = large.lo + align_up(rf + 4ull * j->wp * cap, 256);
+        const uint64_t from_meta = (uint64_t)(reinterpret_cast<char*>(from->st.meta) - c->ws);
+        const bool lined_up = reinterpret_cast<char*>(from->st.rows) == c->ws + large.lo + rf &&
+                              j->rows <= cap && from_meta + 16 * j->rows <= meta_lo;
+        std::vector<uint64_t> dig(kMaxBound + 1, 0);
+        if (lined_up && (j->flags & LTLF_FLAG_DIGEST)) {
+            TRY_HIP(hipMemcpyAsync(dig.data(), from->d_digest, 8ull * (kMaxBound + 1), hipMemcpyDeviceToHost, s));
+            TRY_HIP(hipStreamSynchronize(s));
+        }
+        large.release(j->off, j->bytes);
+        j->arena = nullptr;  // the region is gone; `from` is still j's sub-context
+        uint64_t off = 0;
+        if (!large.alloc(total, off)) return fail(c, LTLF_EDEVICE, "the large area is not free");
+        ltlf_ctx* to = nullptr;
+        const ltlf_status ls = open_sub(j, large.lo, total, s, to);
+        if (ls != LTLF_OK) {
+            large.release(off, total);
+            if (ls != LTLF_ENOMEM) return ls;
+            leave_region(j);
+            j->lev = 0;
+            solo_queue.push_back(j);
+            return LTLF_OK;
+        }
+        if (!lined_up) {
+            note(j, "takes the whole area from the start (layouts do not line up)");
+            give_sub(from);
+            j->sub = nullptr;
+            j->arena = nullptr;
+            j->aligned = false;
+            j->lev = 0;
+            return start_large(j, to, &large, off, total, true, s);
+        }
+        const uint32_t kind = tile_shape(to->Wp, to->lds_limit, tuned_kernel(to)).kind;
+        TRY(migrate(j, to, kind, s, true));
+        if (j->flags & LTLF_FLAG_DIGEST)
+            TRY_HIP(hipMemcpyAsync(to->d_digest, dig.data(), 8ull * (kMaxBound + 1), hipMemcpyHostToDevice, s));
+        TRY_HIP(hipStreamSynchronize(s));
+        give_sub(from);
+        j->sub = to;
+        j->arena = &large;
+        j->off = off;
+        j->bytes = total;
+        j->full = true;
+        j->aligned = false;
+        j->mode = Job::LARGE;
+        j->run->resume(to, &j->costs, j->bound, j->flags, &j->res, j->rows, j->res.candidates, j->status, j->wit_op,
+                       j->wit_a, j->wit_b);
+        note(j, "takes the whole area with its stored levels");
+        return start_worker(j);
     }
 
     // j becomes a large job on sub-context `sub` (region [off, off+bytes) of
@@ -1517,13 +1639,41 @@ struct Scheduler {
     uint32_t holding() const {
         uint32_t n = (uint32_t)(resident.size() + bigs.size());
         for (Job* j : grow_queue) n += j->sub != nullptr;
+        for (Job* j : full_queue) n += j->sub != nullptr;
         return n;
     }
 
     // ------------------------------------------------------------- admission
     ltlf_status admit(hipStream_t s) {
         if (!solo_queue.empty()) return LTLF_OK;  // the whole workspace is wanted: drain first
-        // the whole large area, once nothing holds any of it
+        // the whole large area, once nothing but the jobs waiting for it holds
+        // any of it: one that holds an aligned region takes it with its
+        // stored levels (others that hold regions give them up first)
+        if (!full_queue.empty() && bigs.empty() && !large.empty()) {
+            uint64_t held = 0;
+            std::vector<Job*> holders;
+            for (Job* w : full_queue)
+                if (w->arena == &large) {
+                    holders.push_back(w);
+                    held += align_up(w->bytes, 256);
+                }
+            if (!holders.empty() && large.free_bytes() + held == large.total()) {
+                for (size_t i = 1; i < holders.size(); ++i) {
+                    Job* w = holders[i];
+                    leave_region(w);
+                    w->run.reset();
+                    w->lev = 0;
+                    w->rows = 0;
+                    w->redo_level = 0;
+                    w->status = LTLF_NOT_FOUND;
+                    reset_result(&w->res, 4 * w->wp);
+                    w->mode = Job::QUEUED;
+                }
+                Job* h = holders[0];
+                full_queue.erase(std::find(full_queue.begin(), full_queue.end(), h));
+                TRY(promote(h, s));
+            }
+        }
         if (!full_queue.empty() && large.empty()) {
             Job* j = full_queue.front();
             full_queue.pop_front();
@@ -1545,10 +1695,14 @@ struct Scheduler {
             Job* w = grow_queue[i];
             if (region_for(w, w->need_rows) > large.total() / 2) {
                 grow_queue.erase(grow_queue.begin() + (long)i);
+                full_queue.push_back(w);
+                if (w->aligned && w->arena == &large && w->lev > 0) {  // keeps its region and levels
+                    note(w, "waits for the whole area, keeping its aligned region");
+                    continue;
+                }
                 if (w->mode == Job::SMALL) resident.erase(std::find(resident.begin(), resident.end(), w));
                 leave_region(w);
                 w->mode = Job::QUEUED;
-                full_queue.push_back(w);
                 note(w, "waits for the whole area");
             } else {
                 ++i;
@@ -1672,6 +1826,8 @@ struct Scheduler {
         }
         for (Job* j : std::vector<Job*>(resident)) TRY(finish(j, s, true));
         for (Job* j : std::vector<Job*>(grow_queue.begin(), grow_queue.end()))
+            if (j->sub) TRY(finish(j, s, true));
+        for (Job* j : std::vector<Job*>(full_queue.begin(), full_queue.end()))
             if (j->sub) TRY(finish(j, s, true));
         for (std::deque<Job*>* q : {&queue, &grow_queue, &full_queue, &solo_queue}) {
             for (Job* j : *q) {

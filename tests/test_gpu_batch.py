@@ -141,11 +141,16 @@ def test_context_usable_after_batch(big):
 
 
 @pytest.fixture(scope="module")
-def large_area_problems():
+def batched_222():
+    return workload.batched(1, 222)
+
+
+@pytest.fixture(scope="module")
+def large_area_problems(batched_222):
     """Batched-configuration problems whose levels run in the large area
     (47..56-chunk rows: group kernel; 102-chunk rows: wave kernel), and three
     tiny ones."""
-    ps = workload.batched(1, 222)
+    ps = batched_222
     return [ps[i] for i in (128, 164, 221, 81)] + [workload.tiny(s) for s in (1, 2, 3)]
 
 
@@ -188,6 +193,35 @@ def test_forecast_short_levels_redone_exactly(large_area_problems, capfd, monkey
         dropped = trace.count("level dropped")
         print(f"[batch] forecasts x0.02: {dropped} levels dropped and run again", flush=True)
         assert dropped > 0
+        for p, r in zip(ps, mix):
+            a = s.solve(p, flags=m.FLAG_DIGEST)
+            assert (a.status, a.min_cost, a.levels_done, a.overflow_level, a.level_counts, a.level_digests) == \
+                (r.status, r.min_cost, r.levels_done, r.overflow_level, r.level_counts, r.level_digests), p.name
+            if r.status == m.ltlf.OK:
+                assert ev.separates(r.formula, p.traces, p.positive), (p.name, r.formula)
+    finally:
+        s.close()
+
+
+def test_whole_area_taken_with_stored_levels(batched_222, capfd, monkeypatch):
+    """Batched problem 113 (372-chunk rows) in a 100 GiB workspace: its level
+    9 runs in a region of the large area placed so that its rows sit where the
+    whole area's layout puts them; its level 10 needs more than half the area,
+    so it takes the whole area keeping its stored levels (rows in place,
+    records moved, table rebuilt) instead of starting over, then overflows at
+    level 11 and finds its minimum there by the check.  Results equal the
+    problem solved alone, sets included."""
+    ps = [batched_222[113], workload.tiny(1), workload.tiny(2)]
+    monkeypatch.setenv("LTLF_TRACE", "1")
+    s = m.Synthesizer(device=0, workspace_bytes=100 << 30)
+    try:
+        print("[batch] whole area with stored levels", flush=True)
+        mix = s.solve_batch(ps, flags=m.FLAG_DIGEST)
+        trace = capfd.readouterr().err
+        promoted = trace.count("takes the whole area with its stored levels")
+        print(f"[batch]   promotions: {promoted}; {mix[0].status_name} min {mix[0].min_cost} "
+              f"levels {mix[0].levels_done} overflow {mix[0].overflow_level}", flush=True)
+        assert promoted == 1
         for p, r in zip(ps, mix):
             a = s.solve(p, flags=m.FLAG_DIGEST)
             assert (a.status, a.min_cost, a.levels_done, a.overflow_level, a.level_counts, a.level_digests) == \

@@ -26,6 +26,7 @@
 
 #include "../../include/ltlf.h"
 #include "ltlf_internal.h"
+#include "ltlf_host.h"
 
 using namespace ltlf;
 
@@ -51,12 +52,6 @@ constexpr uint64_t kLaunchCandidates = LTLF_LAUNCH_CANDIDATES;
 #define LTLF_PERSISTENT_CANDIDATES (1ull << 25)
 #endif
 constexpr uint64_t kPersistentCandidates = LTLF_PERSISTENT_CANDIDATES;
-// Largest deferral list 0 (records of 16 bytes; the list gets 1/1024 of the
-// workspace up to this)
-#ifndef LTLF_DEFER_MAX
-#define LTLF_DEFER_MAX (1ull << 27)
-#endif
-constexpr uint64_t kDeferMax = LTLF_DEFER_MAX;
 // Share of the resident block slots (eighths) the large region's persistent
 // launches take while small problems are on the device
 #ifndef LTLF_BUSY_EIGHTHS
@@ -64,7 +59,6 @@ constexpr uint64_t kDeferMax = LTLF_DEFER_MAX;
 #endif
 constexpr uint32_t kBusyEighths = LTLF_BUSY_EIGHTHS;
 
-inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 inline uint64_t pow2_ceil(uint64_t x) {
     uint64_t p = 1;
     while (p < x) p <<= 1;
@@ -159,9 +153,10 @@ ltlf_status fail(ltlf_ctx* c, ltlf_status s, const char* what, hipError_t e = hi
     } while (0)
 
 
-// Sizes of the workspace carve-up (plan_memory_impl follows them):
-// the fixed regions, each 256-byte aligned, for a specification of n_pos
-// positions over T traces with m propositions and rows of Wp words ...
+// Bytes of the fixed regions of the workspace carve-up (plan_memory_impl
+// follows them), each 256-byte aligned, for a specification of n_pos
+// positions over T traces with m propositions and rows of Wp words; the rest
+// of the size model (deferral lists, table, row store) is in ltlf_host.h.
 uint64_t fixed_bytes(uint64_t n_pos, uint64_t T, uint64_t Wp, uint64_t m, uint64_t staging) {
     uint64_t off = 0;
     const uint64_t sizes[] = {4 * n_pos, 4 * T, 4 * (T + 1), 4 * (T + 1), T, 4 * n_pos, 4 * Wp, 4 * Wp, 4 * Wp,
@@ -171,32 +166,6 @@ uint64_t fixed_bytes(uint64_t n_pos, uint64_t T, uint64_t Wp, uint64_t m, uint64
         off = align_up(off, 256) + b;
     return align_up(off, 256);
 }
-// ... the deferral lists (records) of what follows them ...
-void deferral_records(uint64_t rest, uint64_t& d0, uint64_t& d1) {
-    d0 = std::min<uint64_t>(std::max<uint64_t>(rest / 64 / 16, 1ull << 16), kDeferMax);
-    d1 = std::max<uint64_t>(d0 / 16, 4096);
-}
-// ... and the rows that fit a workspace of `bytes` (0: none).  Each row takes
-// 4 Wp bytes, a 16-byte derivation record and two 8-byte table slots.
-uint64_t row_capacity(uint64_t fixed, uint64_t Wp, uint64_t bytes) {
-    if (fixed >= bytes) return 0;
-    uint64_t d0, d1;
-    deferral_records(bytes - fixed, d0, d1);
-    if ((d0 + d1) * 16 + 4096 >= bytes - fixed) return 0;
-    const uint64_t off = align_up(align_up(fixed + 16 * d0, 256) + 16 * d1, 256);
-    if (off + 3 * 256 >= bytes) return 0;
-    return std::min<uint64_t>((bytes - off - 3 * 256) / (4 * Wp + 32), (1ull << 31) - 16);
-}
-
-// ... and the offset of the row store in a workspace of `bytes` (after the
-// deferral lists and the table).
-uint64_t rows_offset(uint64_t fixed, uint64_t Wp, uint64_t bytes) {
-    uint64_t d0, d1;
-    deferral_records(bytes - fixed, d0, d1);
-    const uint64_t table = align_up(align_up(fixed + 16 * d0, 256) + 16 * d1, 256);
-    return align_up(table + 16 * row_capacity(fixed, Wp, bytes), 256);
-}
-
 // Carves the workspace.  Fixed regions first, then deferral lists, then the
 // row store and the table, which take what is left.
 ltlf_status plan_memory_impl(ltlf_ctx* c);
@@ -963,84 +932,6 @@ struct LevelRun {
 // every result equals ltlf_solve's with a workspace of the large area's size
 // (status, minimal cost, levels, overflow level, counts and sets), hence
 // ltlf_solve's on the same context whenever the run does not overflow it.
-
-// First-fit allocator over [lo, hi) of the workspace (offsets), 256-byte
-// granules.
-struct Arena {
-    uint64_t lo = 0, hi = 0;
-    std::vector<std::pair<uint64_t, uint64_t>> free_;  // (offset, bytes), sorted by offset
-    void init(uint64_t a, uint64_t b) {
-        lo = a;
-        hi = b;
-        free_.assign(1, {a, b - a});
-    }
-    uint64_t total() const { return hi - lo; }
-    uint64_t free_bytes() const {
-        uint64_t f = 0;
-        for (const auto& r : free_) f += r.second;
-        return f;
-    }
-    bool empty() const { return free_bytes() == total(); }
-    bool alloc(uint64_t bytes, uint64_t& off) {
-        bytes = align_up(bytes, 256);
-        for (size_t i = 0; i < free_.size(); ++i) {
-            if (free_[i].second >= bytes) {
-                off = free_[i].first;
-                free_[i].first += bytes;
-                free_[i].second -= bytes;
-                if (free_[i].second == 0) free_.erase(free_.begin() + (long)i);
-                return true;
-            }
-        }
-        return false;
-    }
-    // the top of the highest free range that fits (regions that are not
-    // aligned stay clear of the bottom of the large area, where aligned ones go)
-    bool alloc_high(uint64_t bytes, uint64_t& off) {
-        bytes = align_up(bytes, 256);
-        for (size_t i = free_.size(); i-- > 0;) {
-            if (free_[i].second >= bytes) {
-                free_[i].second -= bytes;
-                off = free_[i].first + free_[i].second;
-                if (free_[i].second == 0) free_.erase(free_.begin() + (long)i);
-                return true;
-            }
-        }
-        return false;
-    }
-    // [off, off + bytes) if it is free
-    bool alloc_at(uint64_t off, uint64_t bytes) {
-        bytes = align_up(bytes, 256);
-        for (size_t i = 0; i < free_.size(); ++i) {
-            const uint64_t o = free_[i].first, b = free_[i].second;
-            if (o > off || off + bytes > o + b) continue;
-            const uint64_t tail = o + b - (off + bytes);
-            if (off > o) {
-                free_[i].second = off - o;
-                if (tail) free_.insert(free_.begin() + (long)i + 1, {off + bytes, tail});
-            } else if (tail) {
-                free_[i] = {off + bytes, tail};
-            } else {
-                free_.erase(free_.begin() + (long)i);
-            }
-            return true;
-        }
-        return false;
-    }
-    void release(uint64_t off, uint64_t bytes) {
-        bytes = align_up(bytes, 256);
-        auto it = std::lower_bound(free_.begin(), free_.end(), std::make_pair(off, (uint64_t)0));
-        it = free_.insert(it, {off, bytes});
-        if (it + 1 != free_.end() && it->first + it->second == (it + 1)->first) {
-            it->second += (it + 1)->second;
-            free_.erase(it + 1);
-        }
-        if (it != free_.begin() && (it - 1)->first + (it - 1)->second == it->first) {
-            (it - 1)->second += it->second;
-            free_.erase(it);
-        }
-    }
-};
 
 struct Job {
     enum Mode : uint32_t { QUEUED, SMALL, LARGE, FINISHED };

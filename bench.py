@@ -423,6 +423,9 @@ def main() -> int:
     ap.add_argument("--workspace-gb", type=float, default=0.0)
     ap.add_argument("--only-headline", action="store_true",
                     help="time the headline steps only (profiling runs)")
+    ap.add_argument("--only-medium", action="store_true",
+                    help="time the medium problem's steps only (profiling runs of the lane kernel); "
+                         "prints that leg's figures, not the headline line")
     ap.add_argument("--cpu-bound", type=int, default=6,
                     help="oracle baseline on the headline problem to this cost (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -474,6 +477,12 @@ def main() -> int:
 
     dev = 0
     free, total = torch.cuda.mem_get_info(dev)
+    if args.only_medium:
+        ws = int(args.workspace_gb * (1 << 30)) if args.workspace_gb > 0 else int(min(free * 0.6, 120 << 30))
+        synth = m.Synthesizer(device=dev, workspace_bytes=ws)
+        print(json.dumps({"medium": medium_leg(synth, args.medium_bound, args.steps)}), flush=True)
+        synth.close()
+        return 0
     ws = int(args.workspace_gb * (1 << 30)) if args.workspace_gb > 0 else large_workspace_bytes(free)
     log(f"[bench] workspace {ws / (1 << 30):.1f} GiB of {free / (1 << 30):.1f} GiB free")
     synth = m.Synthesizer(device=dev, workspace_bytes=ws)

@@ -197,3 +197,35 @@ def test_large_jobs_run_together_and_keep_their_levels():
         same(got[t], a, p)
         assert got[t].levels_done == 10
     s.close()
+
+
+def test_whole_area_taken_with_stored_levels_while_serving(capfd, monkeypatch):
+    """A served request that comes to need the whole large area (batched
+    problem 113 in a 100 GiB workspace, at its level 10) takes it with its
+    stored levels while tiny requests keep arriving and finishing; every
+    result equals the problem solved alone, sets included."""
+    big = workload.batched(1, 114)[113]
+    monkeypatch.setenv("LTLF_TRACE", "1")
+    s = m.Synthesizer(device=0, workspace_bytes=100 << 30)
+    try:
+        D = m.FLAG_DIGEST
+        smalls = [workload.tiny(i) for i in range(1, 7)]
+        srv = m.Server(s, max_resident=8)
+        print("[server] whole area with stored levels", flush=True)
+        tickets = [srv.submit(big, flags=D)]
+        ps = [big]
+        for i, p in enumerate(smalls):  # arrivals while the large request runs
+            for _ in range(3 + i):
+                srv.step()
+            tickets.append(srv.submit(p, flags=D))
+            ps.append(p)
+        out = drain(srv, tickets)
+        trace = capfd.readouterr().err
+        promoted = trace.count("takes the whole area with its stored levels")
+        print(f"[server]   promotions: {promoted}", flush=True)
+        assert promoted == 1
+        srv.close()
+        for t, p in zip(tickets, ps):
+            same(out[t], s.solve(p, flags=D), p)
+    finally:
+        s.close()

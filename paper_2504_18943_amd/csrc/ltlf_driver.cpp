@@ -991,6 +991,11 @@ struct Scheduler {
     unsigned long long* d_gather = nullptr;
     uint32_t launches = 0;
     bool trace = false;  // LTLF_TRACE set: one line per job event on stderr
+    // small-pool statistics (reported with the trace): steps with small jobs,
+    // their batched launches, wall time in those steps and, within it, time
+    // waiting for the device
+    uint64_t small_steps = 0;
+    double small_step_s = 0.0, small_wait_s = 0.0, admit_s = 0.0, plan_s = 0.0, close_s = 0.0;
     double forecast_margin = 1.5;  // LTLF_FORECAST_SCALE: margin of the large jobs' forecasts
     std::chrono::steady_clock::time_point t0;
     std::mutex mu;
@@ -1791,8 +1796,10 @@ struct Scheduler {
 
     ltlf_status step(hipStream_t s, uint32_t* n_done) {
         uint32_t finished = 0;
+        const auto t_admit = std::chrono::steady_clock::now();
         TRY(reap(s, finished));
         TRY(admit(s));
+        admit_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t_admit).count();
         if (resident.empty() && bigs.empty() && grow_queue.empty() && full_queue.empty() && queue.empty()) {
             if (!solo_queue.empty()) {
                 Job* j = solo_queue.front();
@@ -1804,6 +1811,7 @@ struct Scheduler {
             return LTLF_OK;
         }
         // small jobs: plan the next level; one that outgrows its region moves
+        const auto t_small = std::chrono::steady_clock::now();
         std::vector<Job*> live;
         for (Job* j : std::vector<Job*>(resident)) {
             if (std::find(grow_queue.begin(), grow_queue.end(), j) != grow_queue.end()) continue;  // waiting
@@ -1840,6 +1848,7 @@ struct Scheduler {
             live.push_back(j);
         }
         small_busy.store(!live.empty() || !queue.empty(), std::memory_order_relaxed);
+        plan_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t_small).count();
         // large-area requests raised just now are served at once if they fit
         if (!grow_queue.empty()) TRY(admit(s));
         if (!live.empty()) {
@@ -1883,12 +1892,19 @@ struct Scheduler {
                 TRY_HIP(launch_verify_batch(d_stores, (uint32_t)live.size(), s));
                 TRY_HIP(launch_between_batch(d_stores, (uint32_t)live.size(), s));
                 ++launches;
-                TRY_HIP(hipStreamSynchronize(s));  // `pieces` is reused
+                {
+                    const auto w0 = std::chrono::steady_clock::now();
+                    TRY_HIP(hipStreamSynchronize(s));  // `pieces` is reused
+                    small_wait_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
+                }
             }
             TRY_HIP(launch_gather_ctr(d_stores, (uint32_t)live.size(), d_gather, s));
             TRY_HIP(hipMemcpyAsync(c->h_batch, d_gather, 8ull * C_NUM * live.size(), hipMemcpyDeviceToHost, s));
+            const auto w0 = std::chrono::steady_clock::now();
             TRY_HIP(hipStreamSynchronize(s));
+            small_wait_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
         }
+        const auto t_close = std::chrono::steady_clock::now();
         for (size_t i = 0; i < live.size(); ++i) {
             Job* j = live[i];
             ltlf_ctx* sub = j->sub;
@@ -1948,6 +1964,11 @@ struct Scheduler {
                 TRY(finish(j, s));
                 ++finished;
             }
+        }
+        close_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t_close).count();
+        if (!live.empty()) {
+            ++small_steps;
+            small_step_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t_small).count();
         }
         small_busy.store(!resident.empty() || !queue.empty(), std::memory_order_relaxed);
         // with nothing else to step, wait a little for a large job instead of
@@ -2383,6 +2404,12 @@ ltlf_status ltlf_solve_batch(ltlf_ctx* c, uint32_t n, const ltlf_spec* specs, co
         }
         TRY(sc.step(s, nullptr));
     }
+    if (sc.trace)
+        std::fprintf(stderr,
+                     "[ltlf] small pool: %llu steps, %u batched launches, %.1f ms in those steps (planning and moves "
+                     "%.1f, level close and finish %.1f), %.1f ms of it waiting for the device; admission %.1f ms\n",
+                     (unsigned long long)sc.small_steps, sc.launches, 1e3 * sc.small_step_s, 1e3 * sc.plan_s,
+                     1e3 * sc.close_s, 1e3 * sc.small_wait_s, 1e3 * sc.admit_s);
     TRY_HIP(hipEventRecord(e1, s));
     TRY_HIP(hipEventSynchronize(e1));
     float ms = 0.f;

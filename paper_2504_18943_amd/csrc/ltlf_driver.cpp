@@ -99,6 +99,13 @@ struct ltlf_ctx {
     // host mirrors
     unsigned long long* h_ctr = nullptr;  // pinned
     uint32_t* h_tokens = nullptr;         // pinned
+    unsigned long long* h_dig = nullptr;  // pinned, level digests (kMaxBound + 1)
+    // the scheduler's loads: pinned image of the input regions, the event
+    // after its last copy, and whether that copy may still be in flight
+    uint8_t* h_load = nullptr;
+    uint64_t h_load_cap = 0;
+    hipEvent_t ev_load = nullptr;
+    bool h_load_busy = false;
     // events around a whole run (created with the context, so a run creates
     // no runtime objects)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;    // ltlf_run
@@ -264,15 +271,19 @@ const char* op_token(uint32_t op) {
     }
 }
 
-// Runs the formula kernel from a root derivation and renders prefix tokens.
-// Bits 8.. of op name a unary operator applied on top (a look-ahead witness).
-ltlf_status render_formula(ltlf_ctx* c, uint32_t op, uint32_t a, uint32_t b, hipStream_t s,
-                           std::string& out) {
-    const uint32_t outer = op >> 8;
-    op &= 0xFFu;
-    TRY_HIP(launch_formula(c->st.meta, op, a, b, kMaxTokens, c->d_tokens, s));
+// Runs the formula kernel from a root derivation (operator in bits 0..7 of
+// op) and copies its prefix tokens to c->h_tokens on s; read them with
+// decode_formula once s has been synchronised.
+ltlf_status enqueue_formula(ltlf_ctx* c, uint32_t op, uint32_t a, uint32_t b, hipStream_t s) {
+    TRY_HIP(launch_formula(c->st.meta, op & 0xFFu, a, b, kMaxTokens, c->d_tokens, s));
     TRY_HIP(hipMemcpyAsync(c->h_tokens, c->d_tokens, 4 * (1 + kMaxTokens), hipMemcpyDeviceToHost, s));
-    TRY_HIP(hipStreamSynchronize(s));
+    return LTLF_OK;
+}
+
+// Renders the tokens in c->h_tokens.  Bits 8.. of op name a unary operator
+// applied on top (a look-ahead witness).
+ltlf_status decode_formula(ltlf_ctx* c, uint32_t op, std::string& out) {
+    const uint32_t outer = op >> 8;
     const uint32_t n = c->h_tokens[0];
     if (n > kMaxTokens) return fail(c, LTLF_EDEVICE, "witness formula longer than the token buffer");
     out.clear();
@@ -288,6 +299,14 @@ ltlf_status render_formula(ltlf_ctx* c, uint32_t op, uint32_t a, uint32_t b, hip
         }
     }
     return LTLF_OK;
+}
+
+// Witness formula of a root derivation, rendered (synchronises s).
+ltlf_status render_formula(ltlf_ctx* c, uint32_t op, uint32_t a, uint32_t b, hipStream_t s,
+                           std::string& out) {
+    TRY(enqueue_formula(c, op, a, b, s));
+    TRY_HIP(hipStreamSynchronize(s));
+    return decode_formula(c, op, out);
 }
 
 struct LevelPlan {
@@ -464,21 +483,25 @@ void reset_result(ltlf_result* res, uint32_t row_bytes) {
     res->dead_rows = 0;
 }
 
-// Copies the witness formula (or an empty string) and the level counts of a
-// finished run into the caller's buffers.
 // Level digests of levels 1..levels_done into out[0..len) (0 elsewhere);
-// zeros when they were not computed.
+// zeros when they were not computed.  take_digests reads them from c->h_dig
+// (copied there on s, and s synchronised); copy_digests copies and waits.
+void take_digests(const ltlf_ctx* c, uint32_t levels_done, bool computed, uint64_t* out, uint32_t len) {
+    for (uint32_t i = 0; i < len; ++i)
+        out[i] = (computed && i >= 1 && i <= levels_done && i <= kMaxBound) ? c->h_dig[i] : 0;
+}
 ltlf_status copy_digests(ltlf_ctx* c, uint32_t levels_done, bool computed, uint64_t* out, uint32_t len,
                          hipStream_t s) {
-    std::vector<uint64_t> d(kMaxBound + 1, 0);
     if (computed) {
-        TRY_HIP(hipMemcpyAsync(d.data(), c->d_digest, 8 * (kMaxBound + 1), hipMemcpyDeviceToHost, s));
+        TRY_HIP(hipMemcpyAsync(c->h_dig, c->d_digest, 8 * (kMaxBound + 1), hipMemcpyDeviceToHost, s));
         TRY_HIP(hipStreamSynchronize(s));
     }
-    for (uint32_t i = 0; i < len; ++i) out[i] = (i >= 1 && i <= levels_done && i <= kMaxBound) ? d[i] : 0;
+    take_digests(c, levels_done, computed, out, len);
     return LTLF_OK;
 }
 
+// Copies the witness formula (or an empty string), the level counts and
+// digests of a finished run into the caller's buffers.
 ltlf_status finish_result(ltlf_ctx* c, ltlf_result* res, ltlf_status status, uint32_t wit_op, uint32_t wit_a,
                           uint32_t wit_b, bool digests, hipStream_t s) {
     uint64_t uniq = 0;
@@ -518,6 +541,87 @@ ltlf_status validate_spec(const ltlf_spec* sp) {
     const uint32_t bad = sp->n_props == 32 ? 0u : ~((1u << sp->n_props) - 1u);
     for (uint64_t i = 0; i < total; ++i)
         if (sp->letters[i] & bad) return LTLF_EINVAL;
+    return LTLF_OK;
+}
+
+// Sizes of specification sp recorded in c and the workspace carved for it
+// (nothing is copied yet; c is not loaded afterwards).
+ltlf_status load_layout(ltlf_ctx* c, const ltlf_spec* sp) {
+    TRY(validate_spec(sp));
+    TRY_HIP(hipSetDevice(c->device));
+    TRY(ensure_workspace(c));
+    const uint32_t T = sp->n_traces;
+    uint64_t n_pos = 0;
+    for (uint32_t t = 0; t < T; ++t) n_pos += sp->lengths[t];
+    c->loaded = false;
+    c->ran = false;
+    c->n_props = sp->n_props;
+    c->n_traces = T;
+    c->n_pos = n_pos;
+    c->n_bits = n_pos + T;
+    c->Wp = (uint32_t)align_up((c->n_bits + 31) / 32, 4);
+    return plan_memory(c);
+}
+
+// Bytes of the input regions (raw letters, lengths, position and segment
+// offsets, labels, canonical bit map), which the carve-up lays out one after
+// another from d_letters.
+uint64_t input_bytes(const ltlf_ctx* c) {
+    return (uint64_t)(reinterpret_cast<const char*>(c->d_canon) - reinterpret_cast<const char*>(c->d_letters)) +
+           4 * c->n_pos;
+}
+
+// The device image of the input regions of sp (after load_layout) written to
+// img[0, input_bytes(c)): the raw traces, per-trace position offsets, segment
+// offsets (length + 1 bits per trace, guard bit included), labels, and the
+// map from canonical bit (trace t, position k) to the packed bit of that
+// position.
+void fill_inputs(const ltlf_ctx* c, const ltlf_spec* sp, uint8_t* img) {
+    const char* base = reinterpret_cast<const char*>(c->d_letters);
+    auto at = [&](const void* d) { return img + (reinterpret_cast<const char*>(d) - base); };
+    const uint32_t T = c->n_traces;
+    std::memset(img, 0, input_bytes(c));
+    std::memcpy(img, sp->letters, 4 * c->n_pos);
+    std::memcpy(at(c->d_lengths), sp->lengths, 4ull * T);
+    std::memcpy(at(c->d_positive), sp->positive, T);
+    uint32_t* pos_off = reinterpret_cast<uint32_t*>(at(c->d_pos_off));
+    uint32_t* seg_off = reinterpret_cast<uint32_t*>(at(c->d_seg_off));
+    uint32_t* canon = reinterpret_cast<uint32_t*>(at(c->d_canon));
+    pos_off[0] = seg_off[0] = 0;
+    for (uint32_t t = 0; t < T; ++t) {
+        const uint32_t n = sp->lengths[t];
+        pos_off[t + 1] = pos_off[t] + n;
+        seg_off[t + 1] = seg_off[t] + n + 1;
+        for (uint32_t k = 0; k < n; ++k) canon[pos_off[t] + k] = seg_off[t] + (n - 1 - k);
+    }
+}
+
+// Load for the scheduler's sub-contexts: the image goes through the
+// context's pinned buffer in one copy on s, without waiting for it (work on
+// the region is ordered after it on s; callers that hand the region to
+// another stream synchronise s first).  The buffer is rewritten only after
+// the previous copy from it has completed.
+ltlf_status load_staged(ltlf_ctx* c, const ltlf_spec* sp, hipStream_t s) {
+    TRY(load_layout(c, sp));
+    const uint64_t bytes = input_bytes(c);
+    if (c->h_load_busy) {
+        TRY_HIP(hipEventSynchronize(c->ev_load));
+        c->h_load_busy = false;
+    }
+    if (!c->ev_load) TRY_HIP(hipEventCreateWithFlags(&c->ev_load, hipEventDisableTiming));
+    if (bytes > c->h_load_cap) {
+        if (c->h_load) (void)hipHostFree(c->h_load);
+        c->h_load = nullptr;
+        c->h_load_cap = 0;
+        const uint64_t cap = align_up(bytes, 1ull << 16);
+        TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_load), cap, hipHostMallocDefault));
+        c->h_load_cap = cap;
+    }
+    fill_inputs(c, sp, c->h_load);
+    TRY_HIP(hipMemcpyAsync(c->d_letters, c->h_load, bytes, hipMemcpyHostToDevice, s));
+    TRY_HIP(hipEventRecord(c->ev_load, s));
+    c->h_load_busy = true;
+    c->loaded = true;
     return LTLF_OK;
 }
 
@@ -954,6 +1058,7 @@ struct Job {
     uint64_t rows = 0, next_tile = 0, total = 0;
     uint64_t need_rows = 0;  // rows the next level may need (a request for a larger region)
     uint32_t redo_level = 0;  // a level that overflowed a region sized by forecast
+    bool early_full = false;  // asked for the whole area a level ahead (big_loop)
     LevelPlan plan;
     ltlf_status status = LTLF_NOT_FOUND;
     uint32_t wit_op = 0, wit_a = 0, wit_b = 0;
@@ -997,6 +1102,7 @@ struct Scheduler {
     uint64_t small_steps = 0;
     double small_step_s = 0.0, small_wait_s = 0.0, admit_s = 0.0, plan_s = 0.0, close_s = 0.0;
     double forecast_margin = 1.5;  // LTLF_FORECAST_SCALE: margin of the large jobs' forecasts
+    bool always_stage = false;     // LTLF_PROMOTE_STAGED: promote() stages even aligned regions
     std::chrono::steady_clock::time_point t0;
     std::mutex mu;
     std::condition_variable cv;
@@ -1030,6 +1136,10 @@ struct Scheduler {
             const double v = std::atof(fm);
             if (v > 0.0 && v <= 1e6) forecast_margin = v;
         }
+        // a test hook: a job that takes the whole area with its stored levels
+        // stages them even where they already sit in place
+        const char* ps = std::getenv("LTLF_PROMOTE_STAGED");
+        always_stage = ps && *ps && *ps != '0';
         t0 = std::chrono::steady_clock::now();
         TRY(ensure_workspace(c));
         c->loaded = false;  // the workspace is carved below
@@ -1145,7 +1255,8 @@ struct Scheduler {
     }
 
     // A sub-context on region [off, off + bytes) with j's specification
-    // loaded (synchronises s).
+    // loaded on s (the copy is ordered before later work on s; it is not
+    // waited for).
     ltlf_status open_sub(Job* j, uint64_t off, uint64_t bytes, hipStream_t s, ltlf_ctx*& out) {
         ltlf_ctx* sub = take_sub();
         if (!sub) return fail(c, LTLF_EDEVICE, "no sub-context free");
@@ -1155,7 +1266,8 @@ struct Scheduler {
         sub->row_limit = c->row_limit;
         sub->tune = c->tune;
         const ltlf_spec sp = j->spec();
-        const ltlf_status ls = ltlf_load(sub, &sp, s);
+        sub->err.clear();
+        const ltlf_status ls = load_staged(sub, &sp, s);
         if (ls != LTLF_OK) {
             give_sub(sub);
             return ls == LTLF_ENOMEM ? ls : fail(c, ls, sub->err.c_str());
@@ -1180,7 +1292,8 @@ struct Scheduler {
     // then the rows and derivation records of every stored level copied to
     // the same indices, the digests and level bookkeeping carried over, the
     // counters set as the last closed level left them, and the table rebuilt
-    // from the records.  The caller drains s before the old region is reused.
+    // from the records.  The old region may be reused by later work on s;
+    // the caller drains s before another stream may write it.
     // in_place: the rows already sit at to's row addresses and the caller
     // restores the digests (promote).
     ltlf_status migrate(Job* j, ltlf_ctx* to, uint32_t kernel, hipStream_t s, bool in_place = false) {
@@ -1240,6 +1353,16 @@ struct Scheduler {
                 if (c->row_limit) {
                     worst = std::min<uint64_t>(worst, std::max<uint64_t>(c->row_limit, r.rows) + 1);
                     need = std::min<uint64_t>(need, worst);
+                }
+                // the level after this one expected to need more than half
+                // the area: the job asks for the whole area now, where it will
+                // be anyway, instead of enumerating this level here first
+                const uint64_t next = c->row_limit || lev >= j->bound ? 0 : grown(j->sub, lev, need - r.rows);
+                if (next && region_for(j, need + next) > large.total() / 2) {
+                    j->need_rows = need + next;
+                    j->early_full = true;
+                    grow = true;
+                    break;
                 }
                 if (need > j->sub->plan_cap) {
                     j->need_rows = std::max<uint64_t>(need, 4 * r.rows);
@@ -1360,25 +1483,61 @@ struct Scheduler {
         return LTLF_OK;
     }
 
-    // A job waiting for the whole area whose region is aligned (place_large)
-    // takes the area with its stored levels: its rows stay where they are,
-    // its derivation records move to the whole area's layout, its digests go
-    // through the host (the whole area's fixed regions overlap the region's),
-    // and its table is rebuilt there.  Starts it over in the whole area if
-    // the layouts do not line up after all.  Only j holds part of the area.
+    // A job waiting for the whole area that holds a region of it takes the
+    // area with its stored levels, and its table is rebuilt there.  If the
+    // region is aligned (place_large) its rows stay where they are, its
+    // derivation records move to the whole area's layout and its digests go
+    // through the host (the whole area's fixed regions overlap the
+    // region's).  Otherwise rows, records and digests are first copied to a
+    // staging block of the area that overlaps neither the region, nor what
+    // the whole area's set-up writes before they are moved in (its fixed
+    // regions, deferral lists and the start of its table), nor their
+    // destinations; then moved to the whole area's layout as any move does.
+    // Starts it over in the whole area when neither works.  Only j holds part
+    // of the area.
     ltlf_status promote(Job* j, hipStream_t s) {
         ltlf_ctx* from = j->sub;
+        const uint64_t n = j->rows;
+        const bool digests = (j->flags & LTLF_FLAG_DIGEST) != 0;
         const uint64_t f = fixed_bytes(j->n_pos, j->lengths.size(), j->wp, j->n_props, kSubStaging);
         const uint64_t total = large.total();
         const uint64_t rf = rows_offset(f, j->wp, total), cap = row_capacity(f, j->wp, total);
+        const uint64_t rows_lo = large.lo + rf;
         const uint64_t meta_lo = large.lo + align_up(rf + 4ull * j->wp * cap, 256);
         const uint64_t from_meta = (uint64_t)(reinterpret_cast<char*>(from->st.meta) - c->ws);
-        const bool lined_up = reinterpret_cast<char*>(from->st.rows) == c->ws + large.lo + rf &&
-                              j->rows <= cap && from_meta + 16 * j->rows <= meta_lo;
+        const bool lined_up = !always_stage && reinterpret_cast<char*>(from->st.rows) == c->ws + rows_lo &&
+                              n <= cap && from_meta + 16 * n <= meta_lo;
+        uint64_t stage = UINT64_MAX;
+        const uint64_t rows_b = align_up(n * 4ull * j->wp, 256), meta_b = align_up(16 * n, 256);
+        if (!lined_up && n <= cap) {
+            // the table (two slots per row) ends where the rows start; the
+            // set-up fills its first slots0 slots
+            const uint64_t slots0 = pow2_ceil(std::max<uint64_t>(4ull * j->n_props, kMinTableSlots));
+            const uint64_t table_lo = rows_lo - 16 * cap;
+            stage = free_spot(large.lo, large.hi, rows_b + meta_b + align_up(8ull * (kMaxBound + 1), 256),
+                              {{j->off, j->off + j->bytes},
+                               {large.lo, table_lo + 8 * slots0 + 256},
+                               {rows_lo, rows_lo + 4ull * j->wp * n},
+                               {meta_lo, meta_lo + 16 * n}});
+        }
         std::vector<uint64_t> dig(kMaxBound + 1, 0);
-        if (lined_up && (j->flags & LTLF_FLAG_DIGEST)) {
+        if (lined_up && digests) {
             TRY_HIP(hipMemcpyAsync(dig.data(), from->d_digest, 8ull * (kMaxBound + 1), hipMemcpyDeviceToHost, s));
             TRY_HIP(hipStreamSynchronize(s));
+        }
+        if (stage != UINT64_MAX) {  // queued before anything is written to the area
+            char* base = c->ws + stage;
+            if (n) {
+                TRY_HIP(hipMemcpyAsync(base, from->st.rows, n * 4ull * j->wp, hipMemcpyDeviceToDevice, s));
+                TRY_HIP(hipMemcpyAsync(base + rows_b, from->st.meta, 16 * n, hipMemcpyDeviceToDevice, s));
+            }
+            if (digests)
+                TRY_HIP(hipMemcpyAsync(base + rows_b + meta_b, from->d_digest, 8ull * (kMaxBound + 1),
+                                       hipMemcpyDeviceToDevice, s));
+            // `from` is given back below: its pointers now name the copies
+            from->st.rows = reinterpret_cast<uint32_t*>(base);
+            from->st.meta = reinterpret_cast<uint4*>(base + rows_b);
+            from->d_digest = reinterpret_cast<unsigned long long*>(base + rows_b + meta_b);
         }
         large.release(j->off, j->bytes);
         j->arena = nullptr;  // the region is gone; `from` is still j's sub-context
@@ -1394,8 +1553,8 @@ struct Scheduler {
             solo_queue.push_back(j);
             return LTLF_OK;
         }
-        if (!lined_up) {
-            note(j, "takes the whole area from the start (layouts do not line up)");
+        if (!lined_up && stage == UINT64_MAX) {
+            note(j, "takes the whole area from the start (no room to stage its levels)");
             give_sub(from);
             j->sub = nullptr;
             j->arena = nullptr;
@@ -1404,8 +1563,8 @@ struct Scheduler {
             return start_large(j, to, &large, off, total, true, s);
         }
         const uint32_t kind = tile_shape(to->Wp, to->lds_limit, tuned_kernel(to)).kind;
-        TRY(migrate(j, to, kind, s, true));
-        if (j->flags & LTLF_FLAG_DIGEST)
+        TRY(migrate(j, to, kind, s, lined_up));
+        if (lined_up && digests)
             TRY_HIP(hipMemcpyAsync(to->d_digest, dig.data(), 8ull * (kMaxBound + 1), hipMemcpyHostToDevice, s));
         TRY_HIP(hipStreamSynchronize(s));
         give_sub(from);
@@ -1418,7 +1577,8 @@ struct Scheduler {
         j->mode = Job::LARGE;
         j->run->resume(to, &j->costs, j->bound, j->flags, &j->res, j->rows, j->res.candidates, j->status, j->wit_op,
                        j->wit_a, j->wit_b);
-        note(j, "takes the whole area with its stored levels");
+        note(j, lined_up ? "takes the whole area with its stored levels"
+                         : "takes the whole area with its stored levels (staged)");
         return start_worker(j);
     }
 
@@ -1469,8 +1629,9 @@ struct Scheduler {
             small.release(off, bytes);
             return ls == LTLF_ENOMEM ? LTLF_OK : ls;
         }
+        // the old region may be handed out again at once: all work on the
+        // small pool is on s, so its next use is ordered after these copies
         TRY(migrate(j, sub, KERNEL_WAVE, s));
-        TRY_HIP(hipStreamSynchronize(s));
         const uint32_t lev = j->lev;
         leave_region(j);
         j->sub = sub;
@@ -1543,7 +1704,7 @@ struct Scheduler {
     ltlf_status admit(hipStream_t s) {
         if (!solo_queue.empty()) return LTLF_OK;  // the whole workspace is wanted: drain first
         // the whole large area, once nothing but the jobs waiting for it holds
-        // any of it: one that holds an aligned region takes it with its
+        // any of it: the first of them that holds a region takes it with its
         // stored levels (others that hold regions give them up first)
         if (!full_queue.empty() && bigs.empty() && !large.empty()) {
             uint64_t held = 0;
@@ -1591,9 +1752,15 @@ struct Scheduler {
             Job* w = grow_queue[i];
             if (region_for(w, w->need_rows) > large.total() / 2) {
                 grow_queue.erase(grow_queue.begin() + (long)i);
+                // it keeps its region and levels if aligned, or if no other
+                // job waiting for the whole area holds a region (it will take
+                // the area first and keep them)
+                bool alone = true;
+                for (const Job* o : full_queue) alone = alone && (o->arena != &large);
                 full_queue.push_back(w);
-                if (w->aligned && w->arena == &large && w->lev > 0) {  // keeps its region and levels
-                    note(w, "waits for the whole area, keeping its aligned region");
+                if (w->arena == &large && w->lev > 0 && (w->aligned || alone)) {
+                    note(w, w->aligned ? "waits for the whole area, keeping its aligned region"
+                                       : "waits for the whole area, keeping its region");
                     continue;
                 }
                 if (w->mode == Job::SMALL) resident.erase(std::find(resident.begin(), resident.end(), w));
@@ -1676,6 +1843,23 @@ struct Scheduler {
     // a job ends: its result is kept until polled; its memory is returned
     // (cancelled: the levels it completed stand, its status is CANCELLED)
     ltlf_status finish(Job* j, hipStream_t s, bool cancelled = false) {
+        TRY(finish_enqueue(j, s));
+        if (j->sub) TRY_HIP(hipStreamSynchronize(s));
+        return finish_complete(j, cancelled);
+    }
+    // finish in two halves, so that the jobs that end together wait for the
+    // device once: the digests and the witness tokens are copied to the
+    // sub-context's pinned buffers on s, then read once s is synchronised
+    ltlf_status finish_enqueue(Job* j, hipStream_t s) {
+        ltlf_ctx* sub = j->sub;
+        if (!sub) return LTLF_OK;
+        if (j->flags & LTLF_FLAG_DIGEST)
+            TRY_HIP(hipMemcpyAsync(sub->h_dig, sub->d_digest, 8 * (kMaxBound + 1), hipMemcpyDeviceToHost, s));
+        if (j->status == LTLF_OK && enqueue_formula(sub, j->wit_op, j->wit_a, j->wit_b, s) != LTLF_OK)
+            return fail(c, LTLF_EDEVICE, sub->err.c_str());
+        return LTLF_OK;
+    }
+    ltlf_status finish_complete(Job* j, bool cancelled) {
         ltlf_ctx* sub = j->sub;
         ltlf_result& r = j->res;
         j->counts.assign(j->bound + 1, 0);
@@ -1686,9 +1870,7 @@ struct Scheduler {
                 j->counts[lev] = sub->lcount[lev];
                 uniq += sub->lcount[lev];
             }
-            if (copy_digests(sub, r.levels_done, (j->flags & LTLF_FLAG_DIGEST) != 0, j->digests.data(), j->bound + 1,
-                             s) != LTLF_OK)
-                return fail(c, LTLF_EDEVICE, sub->err.c_str());
+            take_digests(sub, r.levels_done, (j->flags & LTLF_FLAG_DIGEST) != 0, j->digests.data(), j->bound + 1);
         } else {
             r.levels_done = 0;
         }
@@ -1696,7 +1878,7 @@ struct Scheduler {
         r.checked_level = std::max({r.checked_level, r.levels_done, r.overflow_level});
         r.status = j->status;
         j->formula.clear();
-        if (sub && j->status == LTLF_OK && render_formula(sub, j->wit_op, j->wit_a, j->wit_b, s, j->formula) != LTLF_OK)
+        if (sub && j->status == LTLF_OK && decode_formula(sub, j->wit_op, j->formula) != LTLF_OK)
             return fail(c, LTLF_EDEVICE, sub->err.c_str());
         r.formula_len = j->formula.size() + 1;
         if (cancelled) r.status = LTLF_CANCELLED;
@@ -1780,7 +1962,9 @@ struct Scheduler {
             if (j->wstatus != LTLF_OK) return fail(c, j->wstatus, j->sub ? j->sub->err.c_str() : "large job");
             if (j->grow) {  // wants a larger region: waits for it, keeping its own
                 note(j, j->redo_level == j->lev + 1 ? "level dropped (region too small), waits for a larger one"
-                                                    : "waits for a larger region");
+                        : j->early_full                   ? "expects to need the whole area after the next level"
+                                                          : "waits for a larger region");
+                j->early_full = false;
                 bigs.erase(std::find(bigs.begin(), bigs.end(), j));
                 grow_queue.push_back(j);
                 continue;
@@ -1905,6 +2089,7 @@ struct Scheduler {
             small_wait_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
         }
         const auto t_close = std::chrono::steady_clock::now();
+        std::vector<Job*> ending;  // finished at this level: completed together below
         for (size_t i = 0; i < live.size(); ++i) {
             Job* j = live[i];
             ltlf_ctx* sub = j->sub;
@@ -1913,10 +2098,7 @@ struct Scheduler {
             j->lev = lev;
             if (j->total == 0) {
                 r->levels_done = lev;
-                if (lev == j->bound) {
-                    TRY(finish(j, s));
-                    ++finished;
-                }
+                if (lev == j->bound) ending.push_back(j);
                 continue;
             }
             std::memcpy(sub->h_ctr, c->h_batch + (uint64_t)i * C_NUM, 8ull * C_NUM);
@@ -1961,9 +2143,14 @@ struct Scheduler {
             if ((j->status == LTLF_OK && !(j->flags & LTLF_FLAG_EXHAUST)) || lev == j->bound) {
                 r->gen_launches = launches;
                 r->verify_launches = launches;
-                TRY(finish(j, s));
-                ++finished;
+                ending.push_back(j);
             }
+        }
+        if (!ending.empty()) {
+            for (Job* j : ending) TRY(finish_enqueue(j, s));
+            TRY_HIP(hipStreamSynchronize(s));
+            for (Job* j : ending) TRY(finish_complete(j, false));
+            finished += (uint32_t)ending.size();
         }
         close_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t_close).count();
         if (!live.empty()) {
@@ -2062,6 +2249,17 @@ struct Scheduler {
         return est >= (double)cand_ub ? cand_ub : (uint64_t)est;
     }
 
+    // Rows the level after `lev` is expected to add when level lev adds
+    // `est`: the same growth ratio as forecast's, without a second margin; 0
+    // where that growth is unknown.
+    static uint64_t grown(const ltlf_ctx* sub, uint32_t lev, uint64_t est) {
+        if (lev < 3 || lev >= sub->lcount.size()) return 0;
+        const uint64_t a = sub->lcount[lev - 1], b = sub->lcount[lev - 2];
+        if (!a || !b) return 0;
+        const double g = (double)a / (double)b * (double)est;
+        return g >= 1e18 ? (uint64_t)1e18 : (uint64_t)g;
+    }
+
     // Small jobs run the wave kernel's batched form (any row width).
     static TileShape small_shape(const ltlf_ctx* sub) { return tile_shape(sub->Wp, sub->lds_limit, KERNEL_WAVE); }
 };
@@ -2106,10 +2304,12 @@ ltlf_status ltlf_ctx_create(int device, uint64_t hbm_budget_bytes, ltlf_ctx** ou
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_ctr), 8 * C_NUM, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->h_tokens), 4 * (1 + kMaxTokens), hipHostMallocDefault) !=
             hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->h_dig), 8 * (kMaxBound + 1), hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
         hipEventCreate(&c->evb0) != hipSuccess || hipEventCreate(&c->evb1) != hipSuccess) {
         if (c->h_ctr) (void)hipHostFree(c->h_ctr);
         if (c->h_tokens) (void)hipHostFree(c->h_tokens);
+        if (c->h_dig) (void)hipHostFree(c->h_dig);
         for (hipEvent_t e : {c->ev0, c->ev1, c->evb0, c->evb1})
             if (e) (void)hipEventDestroy(e);
         delete c;
@@ -2157,7 +2357,10 @@ void ltlf_ctx_destroy(ltlf_ctx* c) {
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
     if (c->h_tokens) (void)hipHostFree(c->h_tokens);
-    for (hipEvent_t e : {c->ev0, c->ev1, c->evb0, c->evb1})
+    if (c->h_dig) (void)hipHostFree(c->h_dig);
+    if (c->h_load_busy) (void)hipEventSynchronize(c->ev_load);
+    if (c->h_load) (void)hipHostFree(c->h_load);
+    for (hipEvent_t e : {c->ev0, c->ev1, c->evb0, c->evb1, c->ev_load})
         if (e) (void)hipEventDestroy(e);
     delete c;
 }
@@ -2165,35 +2368,11 @@ void ltlf_ctx_destroy(ltlf_ctx* c) {
 ltlf_status ltlf_load(ltlf_ctx* c, const ltlf_spec* sp, void* stream) {
     if (!c) return LTLF_EINVAL;
     c->err.clear();
-    TRY(validate_spec(sp));
-    TRY_HIP(hipSetDevice(c->device));
-    TRY(ensure_workspace(c));
+    TRY(load_layout(c, sp));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const uint32_t T = sp->n_traces;
-    std::vector<uint32_t> pos_off(T + 1), seg_off(T + 1);
-    for (uint32_t t = 0; t < T; ++t) {
-        pos_off[t + 1] = pos_off[t] + sp->lengths[t];
-        seg_off[t + 1] = seg_off[t] + sp->lengths[t] + 1;
-    }
-    c->loaded = false;
-    c->ran = false;
-    c->n_props = sp->n_props;
-    c->n_traces = T;
-    c->n_pos = pos_off[T];
-    c->n_bits = seg_off[T];
-    c->Wp = (uint32_t)align_up((c->n_bits + 31) / 32, 4);
-    TRY(plan_memory(c));
-    // canonical bit g (trace t, position k) -> packed bit of that position
-    std::vector<uint32_t> canon(c->n_pos);
-    for (uint32_t t = 0; t < T; ++t)
-        for (uint32_t k = 0; k < sp->lengths[t]; ++k)
-            canon[pos_off[t] + k] = seg_off[t] + (sp->lengths[t] - 1 - k);
-    TRY_HIP(hipMemcpyAsync(c->d_letters, sp->letters, 4 * c->n_pos, hipMemcpyHostToDevice, s));
-    TRY_HIP(hipMemcpyAsync(c->d_lengths, sp->lengths, 4ull * T, hipMemcpyHostToDevice, s));
-    TRY_HIP(hipMemcpyAsync(c->d_pos_off, pos_off.data(), 4ull * (T + 1), hipMemcpyHostToDevice, s));
-    TRY_HIP(hipMemcpyAsync(c->d_seg_off, seg_off.data(), 4ull * (T + 1), hipMemcpyHostToDevice, s));
-    TRY_HIP(hipMemcpyAsync(c->d_positive, sp->positive, T, hipMemcpyHostToDevice, s));
-    TRY_HIP(hipMemcpyAsync(c->d_canon, canon.data(), 4 * c->n_pos, hipMemcpyHostToDevice, s));
+    std::vector<uint8_t> img(input_bytes(c));
+    fill_inputs(c, sp, img.data());
+    TRY_HIP(hipMemcpyAsync(c->d_letters, img.data(), img.size(), hipMemcpyHostToDevice, s));
     TRY_HIP(hipStreamSynchronize(s));
     c->loaded = true;
     return LTLF_OK;

@@ -130,5 +130,23 @@ struct Arena {
     }
 };
 
+// Start of a 256-aligned block of `need` bytes in [lo, hi) that overlaps none
+// of the intervals [first, second) in `avoid`; UINT64_MAX if there is none.
+// Candidates: the start of the range and the end of each interval (a block
+// that fits anywhere still fits after sliding down to one of them), and the
+// end of the range.
+inline uint64_t free_spot(uint64_t lo, uint64_t hi, uint64_t need,
+                          const std::vector<std::pair<uint64_t, uint64_t>>& avoid) {
+    std::vector<uint64_t> at = {align_up(lo, 256)};
+    if (hi >= need) at.push_back((hi - need) & ~255ull);
+    for (const auto& iv : avoid) at.push_back(align_up(iv.second, 256));
+    for (const uint64_t x : at) {
+        if (x < lo || x + need > hi) continue;
+        bool clear = true;
+        for (const auto& iv : avoid) clear = clear && (x + need <= iv.first || iv.second <= x);
+        if (clear) return x;
+    }
+    return UINT64_MAX;
+}
 
 }  // namespace ltlf

@@ -1,6 +1,7 @@
 // CPU checks of the driver's host-side pieces (paper_2504_18943_amd/csrc/ltlf_host.h):
-// the scheduler's region allocator against a granule-by-granule model, and
-// the workspace size model's invariants.  Prints "ok" and exits 0, or names
+// the scheduler's region allocator against a granule-by-granule model, the
+// workspace size model's invariants, and the staging-block search against
+// brute force.  Prints "ok" and exits 0, or names
 // the first failure and exits 1.
 #include <cstdio>
 #include <cstdlib>
@@ -128,10 +129,41 @@ static void size_model(uint64_t seed) {
     }
 }
 
+// Staging-block search: against every 256-aligned start in a small range,
+// free_spot finds a block exactly when one exists, and what it returns lies
+// in the range, is aligned and overlaps no interval to avoid.
+static void spot_random(uint64_t seed) {
+    std::mt19937_64 rng(seed);
+    const uint64_t G = 256;
+    for (int t = 0; t < 20000; ++t) {
+        const uint64_t lo = (rng() % 8) * 100 + (rng() % 2) * G * 4, hi = lo + (8 + rng() % 56) * G + rng() % G;
+        const uint64_t need = 1 + rng() % (24 * G);
+        std::vector<std::pair<uint64_t, uint64_t>> avoid;
+        for (uint64_t k = 0, m = rng() % 6; k < m; ++k) {
+            const uint64_t a = lo + rng() % (hi - lo + 512), b = a + 1 + rng() % (8 * G);
+            avoid.push_back({a, b});
+        }
+        auto clear = [&](uint64_t x) {
+            if (x < lo || x + need > hi) return false;
+            for (const auto& iv : avoid)
+                if (x < iv.second && iv.first < x + need) return false;
+            return true;
+        };
+        bool any = false;
+        for (uint64_t x = align_up(lo, G); x + need <= hi && !any; x += G) any = clear(x);
+        const uint64_t got = free_spot(lo, hi, need, avoid);
+        CHECK(any == (got != UINT64_MAX), "free_spot %s a block (need %llu in [%llu, %llu))",
+              any ? "missed" : "invented", (unsigned long long)need, (unsigned long long)lo,
+              (unsigned long long)hi);
+        if (got != UINT64_MAX) CHECK(got % G == 0 && clear(got), "free_spot returned a bad block");
+    }
+}
+
 int main() {
     arena_random(1);
     arena_random(2);
     size_model(3);
+    spot_random(4);
     if (fails) return 1;
     std::printf("ok\n");
     return 0;

@@ -4,7 +4,9 @@
 against a granule-by-granule model, and the workspace size model's
 invariants (the carve-up fits, capacities grow with the workspace and stay
 below the row limit, a smaller region's row store never starts after a
-larger workspace's).  Compiled with g++ from tests/host/host_check.cpp."""
+larger workspace's), and the search for a block that avoids given
+intervals (which stages a job's stored levels when it takes the whole area)
+against brute force.  Compiled with g++ from tests/host/host_check.cpp."""
 from __future__ import annotations
 
 import os

@@ -1023,19 +1023,24 @@ struct LevelRun {
 //     ltlf_run) on a worker thread with a stream of its own while the main
 //     thread keeps stepping the small jobs; several large jobs run at once
 //     when their regions fit the large area.
-// Admission is sized by forecast: a job starts with a region for the first
-// few thousand rows, and before each level its region must hold the level's
-// worst case (every candidate a new row).  Otherwise the job moves to a
-// region sized for that worst case, at least four times its stored rows: its
-// stored levels (rows, derivation records, digests) are copied to the same
-// indices there and its table is rebuilt from the records, so no level is
-// enumerated twice (a small job whose next level is large moves into the
-// large area the same way).  A job whose worst case exceeds every region
-// short of the whole large area waits until the large area is empty and
-// runs there from the start: the large area is a request's capacity, and
-// every result equals ltlf_solve's with a workspace of the large area's size
-// (status, minimal cost, levels, overflow level, counts and sets), hence
-// ltlf_solve's on the same context whenever the run does not overflow it.
+// A job starts with a region for the first few thousand rows.  Before each
+// level a small job's region must hold the level's worst case (every
+// candidate a new row), a large job's the level's forecast (the growth ratio
+// of the levels before it, with a margin).  Otherwise the job moves to a
+// larger region: its stored levels (rows, derivation records, digests) are
+// copied to the same indices there and its table is rebuilt from the records,
+// so no level is enumerated twice (a small job whose next level is large
+// moves into the large area the same way).  A large level that overflows a
+// region sized by forecast is dropped and run again in a region sized for
+// its worst case.  A job that needs more than half the large area for its
+// next level, or is expected to for the level after it, waits for the whole
+// area; the first such job that holds a region keeps it and takes the whole
+// area with its stored levels (in place where its region lines up with the
+// whole area's layout, else through a staging block), the others start over
+// there.  The large area is a request's capacity, and every result equals
+// ltlf_solve's with a workspace of the large area's size (status, minimal
+// cost, levels, overflow level, counts and sets), hence ltlf_solve's on the
+// same context whenever the run does not overflow it.
 
 struct Job {
     enum Mode : uint32_t { QUEUED, SMALL, LARGE, FINISHED };
@@ -1103,6 +1108,7 @@ struct Scheduler {
     double small_step_s = 0.0, small_wait_s = 0.0, admit_s = 0.0, plan_s = 0.0, close_s = 0.0;
     double forecast_margin = 1.5;  // LTLF_FORECAST_SCALE: margin of the large jobs' forecasts
     bool always_stage = false;     // LTLF_PROMOTE_STAGED: promote() stages even aligned regions
+    bool early_full = true;        // LTLF_EARLY_FULL=0: big_loop asks for the whole area only when due
     std::chrono::steady_clock::time_point t0;
     std::mutex mu;
     std::condition_variable cv;
@@ -1140,6 +1146,10 @@ struct Scheduler {
         // stages them even where they already sit in place
         const char* ps = std::getenv("LTLF_PROMOTE_STAGED");
         always_stage = ps && *ps && *ps != '0';
+        // a test hook: jobs ask for the whole area only for the level that
+        // needs it, not a level ahead
+        const char* ef = std::getenv("LTLF_EARLY_FULL");
+        early_full = !(ef && *ef == '0');
         t0 = std::chrono::steady_clock::now();
         TRY(ensure_workspace(c));
         c->loaded = false;  // the workspace is carved below
@@ -1357,7 +1367,8 @@ struct Scheduler {
                 // the level after this one expected to need more than half
                 // the area: the job asks for the whole area now, where it will
                 // be anyway, instead of enumerating this level here first
-                const uint64_t next = c->row_limit || lev >= j->bound ? 0 : grown(j->sub, lev, need - r.rows);
+                const uint64_t next =
+                    !early_full || c->row_limit || lev >= j->bound ? 0 : grown(j->sub, lev, need - r.rows);
                 if (next && region_for(j, need + next) > large.total() / 2) {
                     j->need_rows = need + next;
                     j->early_full = true;

@@ -203,24 +203,30 @@ def test_forecast_short_levels_redone_exactly(large_area_problems, capfd, monkey
         s.close()
 
 
-@pytest.mark.parametrize("staged", [False, True], ids=["as-placed", "staged"])
-def test_whole_area_taken_with_stored_levels(batched_222, capfd, monkeypatch, staged):
-    """Batched problem 113 (372-chunk rows) in a 100 GiB workspace: its later
-    levels are expected to need more than half the large area, so it waits
-    for the whole area keeping its region, then takes the whole area with its
-    stored levels (table rebuilt) instead of starting over, overflows at
-    level 11 and finds its minimum there by the check.  As placed, its rows
-    stay where they are when its region lines up with the whole area's layout
-    (else they are staged); staged (a test hook), rows, records and digests
-    always go through a staging block of the area first.  Results equal the
-    problem solved alone, sets included."""
+@pytest.mark.parametrize("mode", ["default", "in-place", "staged"])
+def test_whole_area_taken_with_stored_levels(batched_222, capfd, monkeypatch, mode):
+    """Batched problem 113 (372-chunk rows) in a 100 GiB workspace comes to
+    need more than half the large area, waits for the whole area keeping its
+    region, then takes the whole area with its stored levels (table rebuilt)
+    instead of starting over, overflows at level 11 and finds its minimum
+    there by the check.  default: it asks a level ahead (its level 10 is
+    expected to lead to a level that needs the whole area), from a region
+    that does not line up with the whole area's layout, so rows, records and
+    digests go through a staging block of the area.  in-place (test hook: ask
+    only for the level that needs it): its level 9 region is placed so that
+    its rows sit where the whole area's layout puts them, and they stay
+    there.  staged (test hook): staging even where they line up.  Results
+    equal the problem solved alone, sets included."""
     ps = [batched_222[113], workload.tiny(1), workload.tiny(2)]
     monkeypatch.setenv("LTLF_TRACE", "1")
-    if staged:
+    if mode == "in-place":
+        monkeypatch.setenv("LTLF_EARLY_FULL", "0")
+    if mode == "staged":
+        monkeypatch.setenv("LTLF_EARLY_FULL", "0")
         monkeypatch.setenv("LTLF_PROMOTE_STAGED", "1")
     s = m.Synthesizer(device=0, workspace_bytes=100 << 30)
     try:
-        print(f"[batch] whole area with stored levels (staged={staged})", flush=True)
+        print(f"[batch] whole area with stored levels ({mode})", flush=True)
         mix = s.solve_batch(ps, flags=m.FLAG_DIGEST)
         trace = capfd.readouterr().err
         promoted = trace.count("takes the whole area with its stored levels")
@@ -228,8 +234,7 @@ def test_whole_area_taken_with_stored_levels(batched_222, capfd, monkeypatch, st
         print(f"[batch]   promotions: {promoted} (staged {n_staged}); {mix[0].status_name} min {mix[0].min_cost} "
               f"levels {mix[0].levels_done} overflow {mix[0].overflow_level}", flush=True)
         assert promoted == 1
-        if staged:
-            assert n_staged == 1
+        assert n_staged == (0 if mode == "in-place" else 1)
         for p, r in zip(ps, mix):
             a = s.solve(p, flags=m.FLAG_DIGEST)
             assert (a.status, a.min_cost, a.levels_done, a.overflow_level, a.level_counts, a.level_digests) == \

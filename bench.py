@@ -562,7 +562,9 @@ def main() -> int:
             table = synth.autotune()
             extras["autotune"] = {"seconds": round(time.perf_counter() - a, 2),
                                   "classes": [{"chunks": e["chunks"], "kernel": e["kernel"],
-                                               "ns_per_candidate": e["ns_per_candidate"]} for e in table]}
+                                               "ns_per_candidate": e["ns_per_candidate"],
+                                               "wave_tile": e["wave_tile"],
+                                               "ns_wave_tile": e["ns_wave_tile"]} for e in table]}
             log(f"[bench] autotune {extras['autotune']}")
         if args.batched > 0:
             extras["batched"] = batched_compare(synth, args.batched)

@@ -298,7 +298,8 @@ ltlf_status ltlf_solve_batch(ltlf_ctx *ctx, uint32_t n, const ltlf_spec *specs,
  * generates fastest on this device (one candidate per lane with operands in
  * LDS, per group of lanes with one 16-byte chunk each, or per wavefront with
  * the row streamed 64 chunks at a time; each kernel has its own pair-grid
- * tile).  Results never depend on the choice, only the speed. */
+ * tile, the wave kernel's chosen per class as well).  Results never depend
+ * on the choice, only the speed. */
 #define LTLF_TUNE_CLASSES 16
 typedef struct {
     uint32_t n_classes;                    /* classes filled */
@@ -308,17 +309,26 @@ typedef struct {
     uint64_t candidates[LTLF_TUNE_CLASSES];  /* candidates of one timed run */
     double ns_per_candidate[LTLF_TUNE_CLASSES][3];  /* generation + verification time per
                                                        candidate of lane, group, wave
-                                                       (0: not applicable at this width) */
+                                                       (wave: with its chosen pair tile;
+                                                       0: not applicable at this width) */
+    uint32_t wave_tile[LTLF_TUNE_CLASSES];  /* the wave kernel's pair-grid tile at this
+                                               width: side of its square pair tiles, 8, 16
+                                               or 32 (unary tiles: twice as many operands);
+                                               0 = the built-in 16 */
+    double ns_wave_tile[LTLF_TUNE_CLASSES][3];  /* the wave kernel's time per candidate with
+                                                   tiles of side 8, 16, 32 */
 } ltlf_tuning;
 
 /* Measures every applicable generation kernel on a synthetic problem per
  * width class (3 propositions, 8 x chunks traces of length 15, letters and
  * labels from a fixed seed; cost bound raised until a run has about 2e10
  * bytes of candidate rows (5e6 .. 1e8 candidates) or reaches 12; every level
- * enumerated) and keeps, per class in the context, the fastest (the built-in
- * choice unless another kernel is more than 5% faster): later runs without an
- * LTLF_FLAG_KERNEL_* flag use
- * the class nearest to their row width (log scale).  The large region of a
+ * enumerated), the wave kernel with pair tiles of side 8, 16 and 32, and
+ * keeps, per class in the context, the fastest (the built-in choice, and the
+ * wave kernel's built-in tile, unless another is more than 5% faster): later
+ * runs use the class nearest to their row width (log scale) for the kernel,
+ * unless an LTLF_FLAG_KERNEL_* flag names one, and for the wave kernel's
+ * tile.  The large region of a
  * batch or server created on the context inherits it.  The context's loaded
  * problem is discarded.  out may be NULL.  Returns OK, EINVAL, ENOMEM,
  * EDEVICE. */
@@ -327,8 +337,9 @@ ltlf_status ltlf_autotune(ltlf_ctx *ctx, void *stream, ltlf_tuning *out);
 /* Installs a tuning table (e.g. one measured earlier on another context);
  * NULL restores the built-in choice (lane where its 256- or 128-lane tile
  * fits the LDS, up to about 67 chunks, else group up to 64 chunks, else
- * wave).  EINVAL: n_classes > LTLF_TUNE_CLASSES,
- * a chunks entry of 0 or a kernel entry that is not one of the three flags. */
+ * wave; the wave kernel's tile 16).  EINVAL: n_classes > LTLF_TUNE_CLASSES,
+ * a chunks entry of 0, a kernel entry that is not one of the three flags, or
+ * a wave_tile entry other than 0, 8, 16, 32. */
 ltlf_status ltlf_ctx_set_tuning(ltlf_ctx *ctx, const ltlf_tuning *tuning);
 
 /* Result of ltlf_solve_split.  formula is a caller buffer (host) or NULL. */

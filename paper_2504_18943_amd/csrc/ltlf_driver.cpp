@@ -65,6 +65,13 @@ inline uint64_t pow2_ceil(uint64_t x) {
     return p;
 }
 
+// One class of the kernel tuning table: rows of about `chunks` 16-byte
+// chunks generate fastest with kernel `kind` (KERNEL_*), and the wave kernel
+// there with pair tiles of side `wtile` (0: the built-in side).
+struct TuneClass {
+    uint32_t chunks, kind, wtile;
+};
+
 }  // namespace
 
 struct ltlf_ctx {
@@ -130,9 +137,9 @@ struct ltlf_ctx {
     unsigned long long* h_batch = nullptr;  // pinned, h_batch_cap counters
     uint64_t h_batch_cap = 0;
 
-    // measured kernel choice per row-width class: (chunks, KERNEL_*); empty =
-    // the built-in rule
-    std::vector<std::pair<uint32_t, uint32_t>> tune;
+    // measured kernel choice per row-width class; empty = the built-in rule
+    std::vector<TuneClass> tune;
+    uint32_t wave_tile_force = 0;  // autotune's timed runs: this wave tile (0: the table's)
 };
 
 namespace {
@@ -443,6 +450,8 @@ struct Profiler {
     }
 };
 
+uint32_t tuned_wave_tile(const ltlf_ctx* c);
+
 // Start of a run: per-level bookkeeping, store settings, and on the stream
 // (a1) encoding of the atoms and masks, counters reset, initial table.
 ltlf_status begin_run(ltlf_ctx* c, uint32_t bound, uint32_t flags, uint32_t kernel, hipStream_t s) {
@@ -452,6 +461,7 @@ ltlf_status begin_run(ltlf_ctx* c, uint32_t bound, uint32_t flags, uint32_t kern
     c->st.cap = c->plan_cap;  // the row limit is applied to live rows per level
     c->st.hmask = (flags & LTLF_FLAG_DEBUG_WEAK_HASH) ? 0x3Full : ~0ull;
     c->st.kernel = kernel;
+    c->st.wtile = tuned_wave_tile(c);  // for any wave launch of the run (the look-ahead's too)
     TRY_HIP(launch_encode(c->d_letters, c->d_lengths, c->d_pos_off, c->d_seg_off, c->d_positive,
                           c->n_traces, c->n_props, c->Wp, c->d_V, c->d_S, c->d_P0, c->d_atoms, s));
     TRY_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(c->d_ctr), C_NUM, 0, s));
@@ -634,19 +644,36 @@ constexpr uint32_t kBuiltinPref = KERNEL_LANE;
 
 // The measured kernel for the loaded row width: the tuning class nearest to
 // it on a log scale; the built-in choice without a table.
-uint32_t tuned_kernel(const ltlf_ctx* c) {
-    if (c->tune.empty()) return kBuiltinPref;
+const TuneClass* tuned_class(const ltlf_ctx* c) {
+    if (c->tune.empty()) return nullptr;
     const double w = std::log((double)std::max<uint32_t>(1, c->Wp / 4));
     double best = 1e300;
-    uint32_t kind = kBuiltinPref;
+    const TuneClass* pick = nullptr;
     for (const auto& t : c->tune) {
-        const double d = std::fabs(std::log((double)t.first) - w);
+        const double d = std::fabs(std::log((double)t.chunks) - w);
         if (d < best) {
             best = d;
-            kind = t.second;
+            pick = &t;
         }
     }
-    return kind;
+    return pick;
+}
+uint32_t tuned_kernel(const ltlf_ctx* c) {
+    const TuneClass* t = tuned_class(c);
+    return t ? t->kind : kBuiltinPref;
+}
+
+// The wave kernel's pair-tile side for the loaded row width (the tuning
+// class's, else the built-in one), and the generation kernel and tile shape
+// for preference pref with it.  Every plan and every launch of a run takes
+// the wave tile from here (the store carries it to the kernels).
+uint32_t tuned_wave_tile(const ltlf_ctx* c) {
+    if (c->wave_tile_force) return c->wave_tile_force;
+    const TuneClass* t = tuned_class(c);
+    return t && wave_tile_ok(t->wtile) ? t->wtile : kWaveTileBuiltin;
+}
+TileShape shape_of(const ltlf_ctx* c, uint32_t pref) {
+    return tile_shape(c->Wp, c->lds_limit, pref, tuned_wave_tile(c));
 }
 
 // One single-problem run, level by level: the level loop of ltlf_run, also
@@ -685,7 +712,7 @@ struct LevelRun {
                               : (flags & LTLF_FLAG_KERNEL_GROUP) ? KERNEL_GROUP
                               : (flags & LTLF_FLAG_KERNEL_LANE)  ? KERNEL_LANE
                                                                  : tuned_kernel(c);
-        shape = tile_shape(c->Wp, c->lds_limit, pref);
+        shape = shape_of(c, pref);
         rows = 0;
         candidates = 0;
         status = LTLF_NOT_FOUND;
@@ -708,8 +735,9 @@ struct LevelRun {
         profile = (flags & LTLF_FLAG_PROFILE) != 0;
         res = result;
         prof.c = c;
-        shape = tile_shape(c->Wp, c->lds_limit, tuned_kernel(c));
+        shape = shape_of(c, tuned_kernel(c));
         c->st.kernel = shape.kind;
+        c->st.wtile = tuned_wave_tile(c);
         rows = rows_now;
         candidates = cand_now;
         status = status_now;
@@ -770,7 +798,7 @@ struct LevelRun {
         for (uint32_t o = 0; o < 4; ++o)
             if (k->op_cost[o] == 1) omask |= 1u << o;
         if (omask) {
-            const LevelPlan q = plan_level(c, k, lev, tile_shape(c->Wp, c->lds_limit, KERNEL_WAVE));
+            const LevelPlan q = plan_level(c, k, lev, shape_of(c, KERNEL_WAVE));
             TRY(launch_groups(q, [&](SegTable& t, uint64_t total) -> ltlf_status {
                 for (uint64_t tile = 0; tile < total; tile += kLookaheadTiles) {
                     t.tile_begin = tile;
@@ -1573,7 +1601,7 @@ struct Scheduler {
             j->lev = 0;
             return start_large(j, to, &large, off, total, true, s);
         }
-        const uint32_t kind = tile_shape(to->Wp, to->lds_limit, tuned_kernel(to)).kind;
+        const uint32_t kind = shape_of(to, tuned_kernel(to)).kind;
         TRY(migrate(j, to, kind, s, lined_up));
         if (lined_up && digests)
             TRY_HIP(hipMemcpyAsync(to->d_digest, dig.data(), 8ull * (kMaxBound + 1), hipMemcpyHostToDevice, s));
@@ -1599,7 +1627,7 @@ struct Scheduler {
                             hipStream_t s) {
         const bool fresh = j->sub == nullptr || j->lev == 0;
         if (!fresh) {
-            const uint32_t kind = tile_shape(sub->Wp, sub->lds_limit, tuned_kernel(sub)).kind;
+            const uint32_t kind = shape_of(sub, tuned_kernel(sub)).kind;
             TRY(migrate(j, sub, kind, s));
             TRY_HIP(hipStreamSynchronize(s));  // the copies have read the old region
         }
@@ -2272,7 +2300,7 @@ struct Scheduler {
     }
 
     // Small jobs run the wave kernel's batched form (any row width).
-    static TileShape small_shape(const ltlf_ctx* sub) { return tile_shape(sub->Wp, sub->lds_limit, KERNEL_WAVE); }
+    static TileShape small_shape(const ltlf_ctx* sub) { return shape_of(sub, KERNEL_WAVE); }
 };
 
 }  // namespace
@@ -2432,7 +2460,7 @@ ltlf_status ltlf_ctx_set_tuning(ltlf_ctx* c, const ltlf_tuning* t) {
         return LTLF_OK;
     }
     if (t->n_classes > LTLF_TUNE_CLASSES) return LTLF_EINVAL;
-    std::vector<std::pair<uint32_t, uint32_t>> tune;
+    std::vector<TuneClass> tune;
     for (uint32_t i = 0; i < t->n_classes; ++i) {
         const uint32_t f = t->kernel[i];
         const uint32_t kind = f == LTLF_FLAG_KERNEL_LANE    ? KERNEL_LANE
@@ -2440,7 +2468,8 @@ ltlf_status ltlf_ctx_set_tuning(ltlf_ctx* c, const ltlf_tuning* t) {
                               : f == LTLF_FLAG_KERNEL_WAVE  ? KERNEL_WAVE
                                                             : 0u;
         if (!kind || t->chunks[i] == 0) return LTLF_EINVAL;
-        tune.emplace_back(t->chunks[i], kind);
+        if (t->wave_tile[i] != 0 && !wave_tile_ok(t->wave_tile[i])) return LTLF_EINVAL;
+        tune.push_back(TuneClass{t->chunks[i], kind, t->wave_tile[i]});
     }
     c->tune = tune;
     return LTLF_OK;
@@ -2460,8 +2489,13 @@ ltlf_status ltlf_autotune(ltlf_ctx* c, void* stream, ltlf_tuning* out) {
     const uint32_t flag_of[3] = {LTLF_FLAG_KERNEL_LANE, LTLF_FLAG_KERNEL_GROUP, LTLF_FLAG_KERNEL_WAVE};
     const uint32_t kind_of[3] = {KERNEL_LANE, KERNEL_GROUP, KERNEL_WAVE};
     ltlf_tuning t{};
-    std::vector<std::pair<uint32_t, uint32_t>> tune;
+    std::vector<TuneClass> tune;
     c->tune.clear();  // the timed runs name their kernel; the search runs use the built-in rule
+    struct Unforce {
+        ltlf_ctx* c;
+        ~Unforce() { c->wave_tile_force = 0; }
+    } unforce{c};
+    static const uint32_t kTiles[3] = {8, 16, 32};
     uint64_t rng = 0x2504189430ull;
     auto next = [&rng]() {  // splitmix64
         uint64_t z = (rng += 0x9E3779B97F4A7C15ull);
@@ -2492,14 +2526,41 @@ ltlf_status ltlf_autotune(ltlf_ctx* c, void* stream, ltlf_tuning* out) {
         uint32_t best_i = 2;
         // the lane kernel's family: 256-lane tiles, or 128-lane tiles where only those fit
         auto family = [](uint32_t kind) { return kind == KERNEL_LANE_HALF ? (uint32_t)KERNEL_LANE : kind; };
+        // the wave kernel with each pair-tile side; the built-in side stays
+        // unless another is clearly faster
+        uint32_t wtile = kWaveTileBuiltin;
+        for (uint32_t w = 0; w < 3; ++w) {
+            c->wave_tile_force = kTiles[w];
+            r = ltlf_result{};
+            const ltlf_status st =
+                ltlf_run(c, &k, bound, LTLF_FLAG_EXHAUST | LTLF_FLAG_PROFILE | LTLF_FLAG_KERNEL_WAVE, stream, &r);
+            if (st < 0) return st;
+            t.ns_wave_tile[ci][w] = 1e6 * (r.gen_ms + r.verify_ms) / (double)std::max<uint64_t>(1, r.candidates);
+        }
+        c->wave_tile_force = 0;
+        {
+            double wbest = 0;
+            for (uint32_t w = 0; w < 3; ++w)
+                if (wbest == 0 || t.ns_wave_tile[ci][w] < wbest) {
+                    wbest = t.ns_wave_tile[ci][w];
+                    wtile = kTiles[w];
+                }
+            if (t.ns_wave_tile[ci][1] <= 1.05 * wbest) wtile = kWaveTileBuiltin;
+        }
+        t.wave_tile[ci] = wtile;
         for (uint32_t i = 0; i < 3; ++i) {
             t.ns_per_candidate[ci][i] = 0;
             if (family(tile_shape(c->Wp, c->lds_limit, kind_of[i]).kind) != kind_of[i]) continue;  // does not apply
-            r = ltlf_result{};
-            const ltlf_status st =
-                ltlf_run(c, &k, bound, LTLF_FLAG_EXHAUST | LTLF_FLAG_PROFILE | flag_of[i], stream, &r);
-            if (st < 0) return st;
-            const double ns = 1e6 * (r.gen_ms + r.verify_ms) / (double)std::max<uint64_t>(1, r.candidates);
+            double ns = 0;
+            if (kind_of[i] == KERNEL_WAVE) {
+                ns = t.ns_wave_tile[ci][wtile == 8 ? 0 : wtile == 16 ? 1 : 2];
+            } else {
+                r = ltlf_result{};
+                const ltlf_status st =
+                    ltlf_run(c, &k, bound, LTLF_FLAG_EXHAUST | LTLF_FLAG_PROFILE | flag_of[i], stream, &r);
+                if (st < 0) return st;
+                ns = 1e6 * (r.gen_ms + r.verify_ms) / (double)std::max<uint64_t>(1, r.candidates);
+            }
             t.ns_per_candidate[ci][i] = ns;
             t.candidates[ci] = r.candidates;
             if (best == 0 || ns < best) {
@@ -2517,7 +2578,7 @@ ltlf_status ltlf_autotune(ltlf_ctx* c, void* stream, ltlf_tuning* out) {
         t.kernel[ci] = flag_of[best_i];
         t.bound[ci] = bound;
         t.n_classes = ci + 1;
-        tune.emplace_back(chunks, kind_of[best_i]);
+        tune.push_back(TuneClass{chunks, kind_of[best_i], wtile});
     }
     c->tune = tune;
     c->loaded = false;

@@ -118,7 +118,7 @@ struct Store {
     uint32_t Wp;            // words per row (multiple of 4)
     uint32_t n_props;
     uint32_t kernel;        // KERNEL_* generation kernel of the run
-    uint32_t pad;
+    uint32_t wtile;         // wave kernel: side of its square pair tiles (unary tiles: 2 x wtile operands)
 };
 
 // Launchers (defined in ltlf_kernels.hip).
@@ -141,7 +141,11 @@ struct TileShape {
 // the wave kernel, anything else is the default (lane kernel where its
 // 256-lane tile fits the LDS, else the group kernel for rows of 2..64 chunks,
 // else the wave kernel).
-TileShape tile_shape(uint32_t Wp, uint64_t lds_limit, uint32_t pref);
+// wave_tile: side of the wave kernel's pair tiles (8, 16 or 32; 0: the
+// built-in 16).
+constexpr uint32_t kWaveTileBuiltin = 16;
+TileShape tile_shape(uint32_t Wp, uint64_t lds_limit, uint32_t pref, uint32_t wave_tile = 0);
+inline bool wave_tile_ok(uint32_t t) { return t == 8 || t == 16 || t == 32; }
 uint64_t lds_bytes(uint32_t Wp, uint32_t lanes);
 // Grid of the generation launch: the tile count, or for the persistent group
 // kernel the resident block count (at most the tile count).

@@ -1199,15 +1199,11 @@ __global__ __launch_bounds__(kLanes) void k_generate_grp(Store s, SegTable t) {
 // the multi-word adds cross lanes by ballot carry-lookahead and steps through
 // the top lane.
 
-// Pair tile (left x right operands, square: triangular segments use square
-// tiles) and unary tile of the wave kernel; the block's four waves share a
-// tile and meet at a barrier between tiles.
-#ifndef LTLF_WAVE_TILE
-#define LTLF_WAVE_TILE 16
-#endif
-constexpr uint32_t kWA = LTLF_WAVE_TILE;       // left operands per pair tile
-constexpr uint32_t kWB = LTLF_WAVE_TILE;       // right operands per pair tile
-constexpr uint32_t kWU = 2 * LTLF_WAVE_TILE;   // operands per unary tile
+// Pair tile of the wave kernel: Store::wtile left x wtile right operands
+// (square: triangular segments use square tiles), unary tiles of 2 x wtile
+// operands; the block's four waves share a tile and meet at a barrier
+// between tiles.  The side is chosen per row width by the autotuner (8, 16
+// or 32), else kWaveTileBuiltin.
 constexpr uint32_t kWaveChunk = 8;  // rows / records a wave takes per atomic
 
 
@@ -1613,11 +1609,12 @@ __device__ __forceinline__ uint32_t wave_items(const Store& s, const Seg& g, uin
     const uint32_t NQ = s.Wp / 4;
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid / 64;
+    const uint32_t WT = s.wtile, WU = 2 * s.wtile;
     const uint4* rows4 = reinterpret_cast<const uint4*>(s.rows);
     uint32_t count = 0;
     if (g.kind == SEG_UNARY) {
-        for (uint32_t iv = wave; iv < kWU; iv += kLanes / 64) {
-            const uint64_t vl = lt * kWU + iv;
+        for (uint32_t iv = wave; iv < WU; iv += kLanes / 64) {
+            const uint64_t vl = lt * WU + iv;
             if (vl >= g.nb) break;  // uniform over the wave
             const uint32_t vi = (uint32_t)(g.b0 + vl);
             const uint32_t vop = s.meta[vi].x & 7u;
@@ -1637,14 +1634,14 @@ __device__ __forceinline__ uint32_t wave_items(const Store& s, const Seg& g, uin
             while (tb > 0 && tb * (tb + 1) / 2 > lt) --tb;
             ta = lt - tb * (tb + 1) / 2;
         } else {
-            const uint64_t tiles_b = (g.nb + kWB - 1) / kWB;
+            const uint64_t tiles_b = (g.nb + WT - 1) / WT;
             ta = lt / tiles_b;
             tb = lt % tiles_b;
         }
         const bool mA = (g.opmask & M_AND) != 0, mO = (g.opmask & M_OR) != 0;
         const bool mU = (g.opmask & M_UAB) != 0, mV = (g.opmask & M_UBA) != 0;
-        for (uint32_t it = wave; it < kWA * kWB; it += kLanes / 64) {
-            const uint64_t al = ta * kWA + it / kWB, bl = tb * kWB + it % kWB;
+        for (uint32_t it = wave; it < WT * WT; it += kLanes / 64) {
+            const uint64_t al = ta * WT + it / WT, bl = tb * WT + it % WT;
             if (al >= g.na || bl >= g.nb || (g.tri && al >= bl)) continue;  // uniform over the wave
             const uint32_t ai = (uint32_t)(g.a0 + al), bi = (uint32_t)(g.b0 + bl);
             const bool en[4] = {mA, mO, mU, mV};
@@ -2452,14 +2449,15 @@ static uint32_t group_size(uint32_t nq) {
     return g;
 }
 
-TileShape tile_shape(uint32_t Wp, uint64_t lds_limit, uint32_t pref) {
+TileShape tile_shape(uint32_t Wp, uint64_t lds_limit, uint32_t pref, uint32_t wave_tile) {
+    const uint32_t wt = wave_tile_ok(wave_tile) ? wave_tile : kWaveTileBuiltin;
     const uint32_t nq = Wp / 4;
     const bool group_fits = nq >= 2 && nq <= 64 && grp_lds_bytes(Wp) <= lds_limit;
     const bool lane_fits = lds_bytes(Wp, kLanes) <= lds_limit;
     const bool half_fits = lds_bytes(Wp, kLanes / 2) <= lds_limit;
     const TileShape group{KERNEL_GROUP, kGA, kGB, kGU, 1}, lane{KERNEL_LANE, kTileA, kLanes, kLanes, 0};
     const TileShape half{KERNEL_LANE_HALF, kTileA, kLanes / 2, kLanes / 2, 0};
-    const TileShape wave{KERNEL_WAVE, kWA, kWB, kWU, 1};
+    const TileShape wave{KERNEL_WAVE, wt, wt, 2 * wt, 1};
     if (pref == KERNEL_WAVE) return wave;
     if (pref == KERNEL_GROUP && group_fits) return group;
     if (lane_fits) return lane;
@@ -2528,7 +2526,7 @@ hipError_t launch_generate(const Store& s, const SegTable& t, uint64_t blocks, h
         default: return hipErrorInvalidValue;
         }
     } else if (s.kernel == KERNEL_WAVE) {
-        if (blocks == 0 || blocks > n) return hipErrorInvalidValue;
+        if (blocks == 0 || blocks > n || !wave_tile_ok(s.wtile)) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_generate_wave, dim3((uint32_t)blocks), block, 0, st, s, t);
     } else if (s.kernel == KERNEL_LANE) {
         const uint64_t lds = lds_bytes(s.Wp, kLanes);
@@ -2549,7 +2547,7 @@ hipError_t launch_generate(const Store& s, const SegTable& t, uint64_t blocks, h
 hipError_t launch_lookahead(const Store& s, const SegTable& t, uint32_t omask, hipStream_t st) {
     const uint64_t n = t.tile_end - t.tile_begin;
     if (n == 0) return hipSuccess;
-    if (n > 0x7FFFFFFFull || omask == 0 || omask > 15) return hipErrorInvalidValue;
+    if (n > 0x7FFFFFFFull || omask == 0 || omask > 15 || !wave_tile_ok(s.wtile)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_lookahead_wave, dim3((uint32_t)n), dim3(kLanes), 0, st, s, t, omask);
     return hipGetLastError();
 }

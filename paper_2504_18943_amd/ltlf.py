@@ -74,7 +74,9 @@ class ltlf_tuning(ctypes.Structure):
     _fields_ = [("n_classes", ctypes.c_uint32), ("chunks", ctypes.c_uint32 * TUNE_CLASSES),
                 ("kernel", ctypes.c_uint32 * TUNE_CLASSES), ("bound", ctypes.c_uint32 * TUNE_CLASSES),
                 ("candidates", ctypes.c_uint64 * TUNE_CLASSES),
-                ("ns_per_candidate", (ctypes.c_double * 3) * TUNE_CLASSES)]
+                ("ns_per_candidate", (ctypes.c_double * 3) * TUNE_CLASSES),
+                ("wave_tile", ctypes.c_uint32 * TUNE_CLASSES),
+                ("ns_wave_tile", (ctypes.c_double * 3) * TUNE_CLASSES)]
 
 
 class ltlf_split_result(ctypes.Structure):
@@ -492,7 +494,8 @@ class Synthesizer:
         fastest in the context (ltlf_autotune in include/ltlf.h).  Returns one
         entry per class: chunks, chosen kernel, cost bound and candidates of
         the timed runs, ns per candidate of lane / group / wave (None where a
-        kernel does not apply)."""
+        kernel does not apply; wave with its chosen tile), the wave kernel's
+        pair-tile side and its ns per candidate with sides 8, 16, 32."""
         t = ltlf_tuning()
         st = ltlf_autotune(self._ctx, self._stream(), t)
         if st != OK:
@@ -502,7 +505,9 @@ class Synthesizer:
         return [{"chunks": t.chunks[i], "kernel": names[t.kernel[i]], "bound": t.bound[i],
                  "candidates": t.candidates[i],
                  "ns_per_candidate": {n: (round(t.ns_per_candidate[i][j], 4) if t.ns_per_candidate[i][j] else None)
-                                      for j, n in enumerate(("lane", "group", "wave"))}}
+                                      for j, n in enumerate(("lane", "group", "wave"))},
+                 "wave_tile": t.wave_tile[i],
+                 "ns_wave_tile": {w: round(t.ns_wave_tile[i][j], 4) for j, w in enumerate((8, 16, 32))}}
                 for i in range(t.n_classes)]
 
     def set_tuning(self, tuning: Optional["ltlf_tuning"]) -> None:

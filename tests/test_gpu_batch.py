@@ -72,6 +72,26 @@ def test_batch_matches_oracle_at_full_bounds(big):
         check(r, oracle.solve(p), p)
 
 
+def test_step_graphs_equal_eager_launches(big, monkeypatch):
+    """The small pool's batched step is replayed as two graphs (uploads,
+    generation, verification, reset; gather and download), once per step with
+    the scheduler's own host work and waits between replays.  The same batch
+    with the same copies and launches issued one by one (LTLF_NO_GRAPH) gives
+    the same results, and both equal the oracle (counts and sets)."""
+    ps = workload.batched(1, max(SUBSET_FULL) + 1)
+    ps = [ps[i] for i in SUBSET_FULL] + [workload.tiny(s) for s in (1, 2, 3)]
+    out = {}
+    for mode in ("graph", "eager"):
+        if mode == "eager":
+            monkeypatch.setenv("LTLF_NO_GRAPH", "1")
+        print(f"[batch] {len(ps)} problems, {mode} steps", flush=True)
+        out[mode] = big.solve_batch(ps, flags=m.FLAG_DIGEST)
+    for p, g, e in zip(ps, out["graph"], out["eager"]):
+        assert (g.status, g.min_cost, g.levels_done, g.level_counts, g.level_digests) == \
+            (e.status, e.min_cost, e.levels_done, e.level_counts, e.level_digests), p.name
+        check(g, oracle.solve(p), p)
+
+
 def test_batch_mixed_widths_exhaustive(big):
     """One-chunk, 10-chunk and 328-chunk rows in one batch, every level."""
     ps = [workload.tiny(s) for s in (1, 2, 3, 4)] + [workload.medium(1), workload.large(1)]

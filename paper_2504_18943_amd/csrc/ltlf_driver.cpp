@@ -136,10 +136,6 @@ struct ltlf_ctx {
     std::vector<ltlf_ctx*> subs;
     unsigned long long* h_batch = nullptr;  // pinned, h_batch_cap counters
     uint64_t h_batch_cap = 0;
-    // pinned images of a batched launch: store descriptors, header + pieces
-    Store* h_stpin = nullptr;
-    uint64_t h_stpin_cap = 0;
-    uint8_t* h_ctl = nullptr;
 
     // measured kernel choice per row-width class; empty = the built-in rule
     std::vector<TuneClass> tune;
@@ -1129,14 +1125,13 @@ struct Scheduler {
     std::vector<hipStream_t> streams;  // one per large job slot, reused
     uint64_t next_ticket = 1;
     Store* d_stores = nullptr;
-    BHeader* d_hdr = nullptr;  // header, then the pieces (kBHeaderBytes on)
+    BSeg* d_segs = nullptr;
     unsigned long long* d_gather = nullptr;
     uint32_t launches = 0;
-    // the small pool's batched launch: replayed as graphs, or (LTLF_NO_GRAPH
-    // set) the same copies and launches issued one by one
+    // the small pool's batched launch: replayed as a graph, or (LTLF_NO_GRAPH
+    // set) the same launches issued one by one
     StepGraphs graphs;
     bool use_graphs = true;
-    uint32_t gen_blocks = 0;
     bool trace = false;  // LTLF_TRACE set: one line per job event on stderr
     // small-pool statistics (reported with the trace): steps with small jobs,
     // their batched launches, wall time in those steps and, within it, time
@@ -1193,7 +1188,7 @@ struct Scheduler {
         c->loaded = false;  // the workspace is carved below
         c->ran = false;
         const uint64_t off_segs = align_up(sizeof(Store) * (uint64_t)max_res, 256);
-        const uint64_t off_gather = off_segs + align_up(kBHeaderBytes + sizeof(BSeg) * kSegs, 256);
+        const uint64_t off_gather = off_segs + align_up(sizeof(BSeg) * kSegs, 256);
         base = off_gather + align_up(8ull * C_NUM * max_res, 256);
         if (base + 4 * kMinSlice > c->ws_bytes) return fail(c, LTLF_ENOMEM, "workspace too small for the scheduler");
         const uint64_t region = c->ws_bytes - base;
@@ -1204,7 +1199,7 @@ struct Scheduler {
         small.init(base, small_end);
         large.init(small_end, small_end + (c->ws_bytes - small_end) / 256 * 256);
         d_stores = reinterpret_cast<Store*>(c->ws);
-        d_hdr = reinterpret_cast<BHeader*>(c->ws + off_segs);
+        d_segs = reinterpret_cast<BSeg*>(c->ws + off_segs);
         d_gather = reinterpret_cast<unsigned long long*>(c->ws + off_gather);
         if (c->h_batch_cap < (uint64_t)C_NUM * max_res) {
             if (c->h_batch) (void)hipHostFree(c->h_batch);
@@ -1214,29 +1209,12 @@ struct Scheduler {
                                   hipHostMallocDefault));
             c->h_batch_cap = (uint64_t)C_NUM * max_res;
         }
-        if (c->h_stpin_cap < max_res) {
-            if (c->h_stpin) (void)hipHostFree(c->h_stpin);
-            c->h_stpin = nullptr;
-            c->h_stpin_cap = 0;
-            TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_stpin), sizeof(Store) * max_res,
-                                  hipHostMallocDefault));
-            c->h_stpin_cap = max_res;
-        }
-        if (!c->h_ctl)
-            TRY_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_ctl), kBHeaderBytes + sizeof(BSeg) * kSegs,
-                                  hipHostMallocDefault));
-        TRY_HIP(batch_blocks(gen_blocks));
         const char* ng = std::getenv("LTLF_NO_GRAPH");
         use_graphs = !(ng && *ng && *ng != '0');
         if (use_graphs) {
             graphs.d_stores = d_stores;
-            graphs.d_hdr = d_hdr;
-            graphs.d_gather = d_gather;
-            graphs.h_stores = c->h_stpin;
-            graphs.h_ctl = c->h_ctl;
-            graphs.h_gather = c->h_batch;
-            const hipError_t ge = make_step_graphs(graphs, max_res, gen_blocks, sizeof(Store) * max_res,
-                                                   kBHeaderBytes + sizeof(BSeg) * kSegs, 8ull * C_NUM * max_res);
+            graphs.d_segs = d_segs;
+            const hipError_t ge = make_step_graphs(graphs);
             if (ge != hipSuccess) {
                 free_step_graphs(graphs);
                 return fail(c, LTLF_EDEVICE, "building the batched step's graphs", ge);
@@ -2113,18 +2091,16 @@ struct Scheduler {
         // large-area requests raised just now are served at once if they fit
         if (!grow_queue.empty()) TRY(admit(s));
         if (!live.empty()) {
-            const uint32_t n_live = (uint32_t)live.size();
-            if (n_live > max_resident) return fail(c, LTLF_EDEVICE, "more small jobs than resident slots");
-            for (size_t i = 0; i < live.size(); ++i) c->h_stpin[i] = live[i]->sub->st;
-            BHeader* hh = reinterpret_cast<BHeader*>(c->h_ctl);
-            BSeg* hp = reinterpret_cast<BSeg*>(c->h_ctl + kBHeaderBytes);
+            std::vector<Store> h_stores(live.size());
+            for (size_t i = 0; i < live.size(); ++i) h_stores[i] = live[i]->sub->st;
+            TRY_HIP(hipMemcpyAsync(d_stores, h_stores.data(), sizeof(Store) * live.size(), hipMemcpyHostToDevice, s));
             // pieces of every job's plan, each job's share of a launch
-            // bounded by its deferral list; at least one launch (it uploads
-            // the stores and the header the gather reads)
-            for (bool first_launch = true;; first_launch = false) {
-                size_t np = 0;
+            // bounded by its deferral list
+            std::vector<BSeg> pieces;
+            for (;;) {
+                pieces.clear();
                 uint64_t first = 0;
-                for (size_t i = 0; i < live.size() && np + kMaxSegs < kSegs; ++i) {
+                for (size_t i = 0; i < live.size() && pieces.size() + kMaxSegs < kSegs; ++i) {
                     Job* j = live[i];
                     uint64_t budget = j->sub->st.def0_cap;
                     uint64_t seg_first = 0;
@@ -2141,7 +2117,7 @@ struct Scheduler {
                             b.first = first;
                             b.lt0 = j->next_tile - seg_first;
                             b.seg = sg;
-                            hp[np++] = b;
+                            pieces.push_back(b);
                             first += take;
                             j->next_tile += take;
                             budget -= take * per;
@@ -2149,36 +2125,25 @@ struct Scheduler {
                         seg_first = seg_end;
                     }
                 }
-                if (np == 0 && !first_launch) break;
-                *hh = BHeader{(uint32_t)np, n_live, first, 0};
-                const size_t ctl = kBHeaderBytes + sizeof(BSeg) * np;
-                // resident blocks, no more than there are tiles (blocks
-                // beyond them would only wait for slots to exit)
-                const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(first, gen_blocks));
+                if (pieces.empty()) break;
+                TRY_HIP(hipMemcpyAsync(d_segs, pieces.data(), sizeof(BSeg) * pieces.size(), hipMemcpyHostToDevice, s));
                 if (use_graphs) {
-                    TRY_HIP(set_step(graphs, n_live, blocks, ctl));
-                    TRY_HIP(hipGraphLaunch(graphs.iter, s));
+                    TRY_HIP(set_step(graphs, (uint32_t)pieces.size(), first, (uint32_t)live.size()));
+                    TRY_HIP(hipGraphLaunch(graphs.exec, s));
                 } else {
-                    TRY_HIP(hipMemcpyAsync(d_stores, c->h_stpin, sizeof(Store) * n_live, hipMemcpyHostToDevice, s));
-                    TRY_HIP(hipMemcpyAsync(d_hdr, c->h_ctl, ctl, hipMemcpyHostToDevice, s));
-                    TRY_HIP(launch_generate_batch(d_stores, d_hdr, blocks, s));
-                    TRY_HIP(launch_verify_batch(d_stores, d_hdr, n_live, s));
-                    TRY_HIP(launch_between_batch(d_stores, d_hdr, n_live, s));
+                    TRY_HIP(launch_generate_batch(d_stores, d_segs, (uint32_t)pieces.size(), 0, first, s));
+                    TRY_HIP(launch_verify_batch(d_stores, (uint32_t)live.size(), s));
+                    TRY_HIP(launch_between_batch(d_stores, (uint32_t)live.size(), s));
                 }
-                if (np) ++launches;
+                ++launches;
                 {
                     const auto w0 = std::chrono::steady_clock::now();
-                    TRY_HIP(hipStreamSynchronize(s));  // the pinned header and pieces are rewritten next
+                    TRY_HIP(hipStreamSynchronize(s));  // `pieces` is reused
                     small_wait_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
                 }
-                if (np == 0) break;
             }
-            if (use_graphs) {
-                TRY_HIP(hipGraphLaunch(graphs.close, s));
-            } else {
-                TRY_HIP(launch_gather_ctr(d_stores, d_hdr, n_live, d_gather, s));
-                TRY_HIP(hipMemcpyAsync(c->h_batch, d_gather, 8ull * C_NUM * n_live, hipMemcpyDeviceToHost, s));
-            }
+            TRY_HIP(launch_gather_ctr(d_stores, (uint32_t)live.size(), d_gather, s));
+            TRY_HIP(hipMemcpyAsync(c->h_batch, d_gather, 8ull * C_NUM * live.size(), hipMemcpyDeviceToHost, s));
             const auto w0 = std::chrono::steady_clock::now();
             TRY_HIP(hipStreamSynchronize(s));
             small_wait_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
@@ -2449,8 +2414,6 @@ void ltlf_ctx_destroy(ltlf_ctx* c) {
     c->subs.clear();
     (void)hipSetDevice(c->device);
     if (c->h_batch) (void)hipHostFree(c->h_batch);
-    if (c->h_stpin) (void)hipHostFree(c->h_stpin);
-    if (c->h_ctl) (void)hipHostFree(c->h_ctl);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
     if (c->h_tokens) (void)hipHostFree(c->h_tokens);

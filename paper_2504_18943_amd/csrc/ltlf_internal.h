@@ -99,16 +99,6 @@ struct BSeg {
     Seg seg;
 };
 
-// Counts of one batched launch, copied to the device ahead of its pieces
-// (the pieces start kBHeaderBytes after it): the step's kernels read them
-// there, so the same launches (a captured graph) serve every step.
-struct BHeader {
-    uint32_t nsegs;   // pieces
-    uint32_t n_live;  // problems, stores[0, n_live)
-    uint64_t tiles;   // launch tiles, [0, tiles)
-    unsigned long long cursor;  // next tile to take (uploaded as 0)
-};
-constexpr uint64_t kBHeaderBytes = 256;
 
 // Device-side view of one loaded problem and its store.
 struct Store {
@@ -169,39 +159,24 @@ hipError_t launch_verify_deferred(const Store& s, hipStream_t st);
 // operators of omask (bits: not, X, F, G) applied and checked; one block per
 // tile.
 hipError_t launch_lookahead(const Store& s, const SegTable& t, uint32_t omask, hipStream_t st);
-// The batched step's launches: counts come from the header at d_hdr (pieces
-// at d_hdr + kBHeaderBytes); the grids cover `blocks` resident generation
-// blocks (at most batch_blocks, which take tiles from the header's cursor)
-// and n problems.
-hipError_t batch_blocks(uint32_t& blocks);
-hipError_t launch_generate_batch(const Store* d_stores, BHeader* d_hdr, uint32_t blocks, hipStream_t st);
-hipError_t launch_verify_batch(const Store* d_stores, const BHeader* d_hdr, uint32_t n, hipStream_t st);
-hipError_t launch_between_batch(const Store* d_stores, const BHeader* d_hdr, uint32_t n, hipStream_t st);
-hipError_t launch_gather_ctr(const Store* d_stores, const BHeader* d_hdr, uint32_t n, unsigned long long* out,
-                             hipStream_t st);
-// The batched step as two executable graphs with the same copies and
-// launches: `iter` uploads the stores (h_stores -> d_stores) and the header
-// with its pieces (h_ctl -> d_hdr), then generation, verification and the
-// between-launch reset; `close` gathers the counters and downloads them
-// (d_gather -> h_gather).  Copy sizes and grids are set before each replay
-// (set_step).
+hipError_t launch_generate_batch(const Store* d_stores, const BSeg* d_segs, uint32_t nsegs, uint64_t tile0,
+                                 uint64_t tiles, hipStream_t st);
+hipError_t launch_verify_batch(const Store* d_stores, uint32_t n, hipStream_t st);
+hipError_t launch_between_batch(const Store* d_stores, uint32_t n, hipStream_t st);
+hipError_t launch_gather_ctr(const Store* d_stores, uint32_t n, unsigned long long* out, hipStream_t st);
+// The batched launch (generation over pieces of every problem's plan,
+// verification, between-launch reset) as an executable graph, replayed per
+// launch with its counts and grids written into it (set_step: nsegs pieces
+// at d_segs covering `tiles` launch tiles, n problems at d_stores).
 struct StepGraphs {
-    hipGraph_t g_iter = nullptr, g_close = nullptr;
-    hipGraphExec_t iter = nullptr, close = nullptr;
-    hipGraphNode_t up_stores = nullptr, up_ctl = nullptr, down = nullptr;
-    hipGraphNode_t gen = nullptr, ver = nullptr, btw = nullptr, gat = nullptr;
-    Store* d_stores = nullptr;
-    BHeader* d_hdr = nullptr;
-    unsigned long long* d_gather = nullptr;
-    const void* h_stores = nullptr;
-    const void* h_ctl = nullptr;
-    unsigned long long* h_gather = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t gen = nullptr, ver = nullptr, btw = nullptr;
+    const Store* d_stores = nullptr;
+    const BSeg* d_segs = nullptr;
 };
-hipError_t make_step_graphs(StepGraphs& g, uint32_t max_n, uint32_t blocks, size_t stores_max, size_t ctl_max,
-                            size_t gather_max);
-// Replay settings: n problems, `blocks` generation blocks, `ctl` bytes of
-// header and pieces.
-hipError_t set_step(StepGraphs& g, uint32_t n, uint32_t blocks, size_t ctl);
+hipError_t make_step_graphs(StepGraphs& g);
+hipError_t set_step(StepGraphs& g, uint32_t nsegs, uint64_t tiles, uint32_t n);
 void free_step_graphs(StepGraphs& g);
 hipError_t launch_reinsert(const Store& s, uint64_t n, hipStream_t st);
 // Sets C_DEF0 = 0 and C_SNAP = C_ROWS; must run between any launch that

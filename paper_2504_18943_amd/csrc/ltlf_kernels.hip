@@ -1725,33 +1725,22 @@ __global__ __launch_bounds__(kLanes) void k_generate_wave(Store s, SegTable t) {
 // segs[] sorted by first tile, each naming its problem's store.  Rows and
 // records are taken exactly (chunk 1: no unused tails), each problem's
 // counters being its own addresses.
-__global__ __launch_bounds__(kLanes) void k_generate_wave_batch(const Store* stores, BHeader* hdr) {
-    __shared__ unsigned long long sh_tile;
-    const BSeg* segs = reinterpret_cast<const BSeg*>(reinterpret_cast<const char*>(hdr) + kBHeaderBytes);
-    const uint32_t nsegs = hdr->nsegs;
-    const uint64_t tiles = hdr->tiles;
-    // resident blocks take tiles from the header's cursor (tiles of
-    // different problems differ in cost); a block's waves share its tile
-    for (;;) {
-        if (threadIdx.x == 0) sh_tile = atomicAdd(&hdr->cursor, 1ull);
-        __syncthreads();
-        const uint64_t tile = sh_tile;
-        __syncthreads();
-        if (tile >= tiles) break;
-        uint32_t lo = 0, hi = nsegs;  // last seg with first <= tile
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) / 2;
-            if (segs[mid].first <= tile) lo = mid;
-            else hi = mid;
-        }
-        const BSeg& b = segs[lo];
-        const Store s = stores[b.problem];
-        const uint64_t snap = s.ctr[C_SNAP];
-        const bool full_store = store_full(s);
-        WaveAlloc wa;
-        const uint32_t count = wave_tile(s, b.seg, b.lt0 + (tile - b.first), wa, snap, full_store, 1);
-        wave_count(s, C_CAND, count);
+__global__ __launch_bounds__(kLanes) void k_generate_wave_batch(const Store* stores, const BSeg* segs, uint32_t nsegs,
+                                                                uint64_t tile0) {
+    const uint64_t tile = tile0 + blockIdx.x;
+    uint32_t lo = 0, hi = nsegs;  // last seg with first <= tile
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (segs[mid].first <= tile) lo = mid;
+        else hi = mid;
     }
+    const BSeg& b = segs[lo];
+    const Store s = stores[b.problem];
+    const uint64_t snap = s.ctr[C_SNAP];
+    const bool full_store = store_full(s);
+    WaveAlloc wa;
+    const uint32_t count = wave_tile(s, b.seg, b.lt0 + (tile - b.first), wa, snap, full_store, 1);
+    wave_count(s, C_CAND, count);
 }
 
 // ----------------------------------------------------------- look-ahead --
@@ -1959,26 +1948,25 @@ __global__ __launch_bounds__(kLanes) void k_verify_wave(Store s) {
 }
 
 // Batched form: blockIdx.y is the problem.
-__global__ __launch_bounds__(kLanes) void k_verify_wave_batch(const Store* stores, const BHeader* hdr) {
-    if (blockIdx.y >= hdr->n_live) return;
+__global__ __launch_bounds__(kLanes) void k_verify_wave_batch(const Store* stores) {
     const Store s = stores[blockIdx.y];
     verify_wave_records(s, ((uint64_t)blockIdx.x * kLanes + threadIdx.x) / 64, (uint64_t)gridDim.x * (kLanes / 64));
 }
 
 // Between batched launches: every problem's deferral list is emptied and its
 // launch snapshot taken (see k_between).
-__global__ void k_between_batch(const Store* stores, const BHeader* hdr) {
+__global__ void k_between_batch(const Store* stores, uint32_t n) {
     const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= hdr->n_live) return;
+    if (p >= n) return;
     unsigned long long* ctr = stores[p].ctr;
     ctr[C_DEF0] = 0;
     ctr[C_SNAP] = ctr[C_ROWS];
 }
 
 // Copies every problem's counters to out[p * C_NUM + i] (one transfer to the host).
-__global__ void k_gather_ctr(const Store* stores, const BHeader* hdr, unsigned long long* out) {
+__global__ void k_gather_ctr(const Store* stores, uint32_t n, unsigned long long* out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= hdr->n_live * C_NUM) return;
+    if (i >= n * C_NUM) return;
     out[i] = stores[i / C_NUM].ctr[i % C_NUM];
 }
 
@@ -2564,147 +2552,102 @@ hipError_t launch_lookahead(const Store& s, const SegTable& t, uint32_t omask, h
     return hipGetLastError();
 }
 
-hipError_t batch_blocks(uint32_t& blocks) {
-    int dev = 0, cus = 0, per_cu = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_generate_wave_batch, kLanes, 0);
-    if (e != hipSuccess) return e;
-    blocks = (uint32_t)((per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1));
-    return hipSuccess;
-}
-
-hipError_t launch_generate_batch(const Store* d_stores, BHeader* d_hdr, uint32_t blocks, hipStream_t st) {
-    if (blocks == 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_generate_wave_batch, dim3(blocks), dim3(kLanes), 0, st, d_stores, d_hdr);
+hipError_t launch_generate_batch(const Store* d_stores, const BSeg* d_segs, uint32_t nsegs, uint64_t tile0,
+                                 uint64_t tiles, hipStream_t st) {
+    if (tiles == 0) return hipSuccess;
+    if (tiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_generate_wave_batch, dim3((uint32_t)tiles), dim3(kLanes), 0, st, d_stores, d_segs, nsegs,
+                       tile0);
     return hipGetLastError();
 }
 
-hipError_t launch_verify_batch(const Store* d_stores, const BHeader* d_hdr, uint32_t n, hipStream_t st) {
+hipError_t launch_verify_batch(const Store* d_stores, uint32_t n, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_verify_wave_batch, dim3(8, n), dim3(kLanes), 0, st, d_stores, d_hdr);
+    hipLaunchKernelGGL(k_verify_wave_batch, dim3(8, n), dim3(kLanes), 0, st, d_stores);
     return hipGetLastError();
 }
 
-hipError_t launch_between_batch(const Store* d_stores, const BHeader* d_hdr, uint32_t n, hipStream_t st) {
+hipError_t launch_between_batch(const Store* d_stores, uint32_t n, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_between_batch, dim3(blocks_for(n, 256)), dim3(256), 0, st, d_stores, d_hdr);
+    hipLaunchKernelGGL(k_between_batch, dim3(blocks_for(n, 256)), dim3(256), 0, st, d_stores, n);
     return hipGetLastError();
 }
 
-hipError_t launch_gather_ctr(const Store* d_stores, const BHeader* d_hdr, uint32_t n, unsigned long long* out,
-                             hipStream_t st) {
+hipError_t launch_gather_ctr(const Store* d_stores, uint32_t n, unsigned long long* out, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_ctr, dim3(blocks_for((uint64_t)n * C_NUM, 256)), dim3(256), 0, st, d_stores, d_hdr,
+    hipLaunchKernelGGL(k_gather_ctr, dim3(blocks_for((uint64_t)n * C_NUM, 256)), dim3(256), 0, st, d_stores, n,
                        out);
     return hipGetLastError();
 }
 
-// The step graphs are built node by node (no stream capture): copies
-// host -> device of the stores and of the header with its pieces, the three
-// launches of a batched launch, then (second graph) the gather and the copy
-// device -> host of the counters.  Every launch reads its counts from the
-// header, so only the copy sizes change between replays.
-hipError_t make_step_graphs(StepGraphs& g, uint32_t max_n, uint32_t blocks, size_t stores_max, size_t ctl_max,
-                            size_t gather_max) {
-    if (max_n == 0 || blocks == 0) return hipErrorInvalidValue;
-    hipError_t e = hipGraphCreate(&g.g_iter, 0);
-    if (e == hipSuccess) e = hipGraphCreate(&g.g_close, 0);
+// The batched launch as a graph (generation, verification, between-launch
+// reset), built node by node; set_step writes each replay's counts and grids
+// into the executable graph.
+static hipKernelNodeParams node_params(const void* fn, dim3 grid, dim3 block, void** args) {
+    hipKernelNodeParams p{};
+    p.func = const_cast<void*>(fn);
+    p.gridDim = grid;
+    p.blockDim = block;
+    p.sharedMemBytes = 0;
+    p.kernelParams = args;
+    p.extra = nullptr;
+    return p;
+}
+
+hipError_t make_step_graphs(StepGraphs& g) {
+    hipError_t e = hipGraphCreate(&g.graph, 0);
     if (e != hipSuccess) return e;
-    auto kernel = [](hipGraph_t graph, hipGraphNode_t* node, hipGraphNode_t dep, const void* fn, dim3 grid, dim3 block,
-                     void** args) {
-        hipKernelNodeParams p{};
-        p.func = const_cast<void*>(fn);
-        p.gridDim = grid;
-        p.blockDim = block;
-        p.sharedMemBytes = 0;
-        p.kernelParams = args;
-        p.extra = nullptr;
-        return hipGraphAddKernelNode(node, graph, &dep, 1, &p);
-    };
-    hipGraphNode_t& gen = g.gen;
-    hipGraphNode_t& ver = g.ver;
-    hipGraphNode_t& btw = g.btw;
-    hipGraphNode_t& gat = g.gat;
-    Store* stores = g.d_stores;
-    BHeader* hdr = g.d_hdr;
-    unsigned long long* out = g.d_gather;
-    void* a2[] = {&stores, &hdr};
-    void* a3[] = {&stores, &hdr, &out};
-    e = hipGraphAddMemcpyNode1D(&g.up_stores, g.g_iter, nullptr, 0, g.d_stores, g.h_stores, stores_max,
-                                hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipGraphAddMemcpyNode1D(&g.up_ctl, g.g_iter, &g.up_stores, 1, g.d_hdr, g.h_ctl, ctl_max,
-                                    hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = kernel(g.g_iter, &gen, g.up_ctl, reinterpret_cast<const void*>(k_generate_wave_batch), dim3(blocks),
-                   dim3(kLanes), a2);
-    if (e == hipSuccess)
-        e = kernel(g.g_iter, &ver, gen, reinterpret_cast<const void*>(k_verify_wave_batch), dim3(8, max_n),
-                   dim3(kLanes), a2);
-    if (e == hipSuccess)
-        e = kernel(g.g_iter, &btw, ver, reinterpret_cast<const void*>(k_between_batch),
-                   dim3((uint32_t)blocks_for(max_n, 256)), dim3(256), a2);
+    const Store* stores = g.d_stores;
+    const BSeg* segs = g.d_segs;
+    uint32_t nsegs = 1, n = 1;
+    uint64_t tile0 = 0;
+    void* ag[] = {&stores, &segs, &nsegs, &tile0};
+    void* av[] = {&stores};
+    void* ab[] = {&stores, &n};
+    hipKernelNodeParams p = node_params(reinterpret_cast<const void*>(k_generate_wave_batch), dim3(1), dim3(kLanes), ag);
+    e = hipGraphAddKernelNode(&g.gen, g.graph, nullptr, 0, &p);
     if (e == hipSuccess) {
-        hipKernelNodeParams p{};
-        p.func = reinterpret_cast<void*>(k_gather_ctr);
-        p.gridDim = dim3((uint32_t)blocks_for((uint64_t)max_n * C_NUM, 256));
-        p.blockDim = dim3(256);
-        p.kernelParams = a3;
-        e = hipGraphAddKernelNode(&gat, g.g_close, nullptr, 0, &p);
+        p = node_params(reinterpret_cast<const void*>(k_verify_wave_batch), dim3(8, 1), dim3(kLanes), av);
+        e = hipGraphAddKernelNode(&g.ver, g.graph, &g.gen, 1, &p);
     }
-    if (e == hipSuccess)
-        e = hipGraphAddMemcpyNode1D(&g.down, g.g_close, &gat, 1, g.h_gather, g.d_gather, gather_max,
-                                    hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipGraphInstantiate(&g.iter, g.g_iter, nullptr, nullptr, 0);
-    if (e == hipSuccess) e = hipGraphInstantiate(&g.close, g.g_close, nullptr, nullptr, 0);
+    if (e == hipSuccess) {
+        p = node_params(reinterpret_cast<const void*>(k_between_batch), dim3(1), dim3(256), ab);
+        e = hipGraphAddKernelNode(&g.btw, g.graph, &g.ver, 1, &p);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
     return e;
 }
 
-hipError_t set_step(StepGraphs& g, uint32_t n, uint32_t blocks, size_t ctl) {
-    if (n == 0 || blocks == 0) return hipErrorInvalidValue;
-    hipError_t e = hipGraphExecMemcpyNodeSetParams1D(g.iter, g.up_stores, g.d_stores, g.h_stores, sizeof(Store) * n,
-                                                     hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipGraphExecMemcpyNodeSetParams1D(g.iter, g.up_ctl, g.d_hdr, g.h_ctl, ctl, hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipGraphExecMemcpyNodeSetParams1D(g.close, g.down, g.h_gather, g.d_gather, 8ull * C_NUM * n,
-                                              hipMemcpyDeviceToHost);
-    // grids: the generation blocks, and one row of blocks per problem
-    Store* stores = g.d_stores;
-    BHeader* hdr = g.d_hdr;
-    unsigned long long* out = g.d_gather;
-    void* a2[] = {&stores, &hdr};
-    void* a3[] = {&stores, &hdr, &out};
-    auto grid = [&](hipGraphExec_t x, hipGraphNode_t node, const void* fn, dim3 gd, dim3 bd, void** args) {
-        hipKernelNodeParams p{};
-        p.func = const_cast<void*>(fn);
-        p.gridDim = gd;
-        p.blockDim = bd;
-        p.kernelParams = args;
-        return hipGraphExecKernelNodeSetParams(x, node, &p);
-    };
-    if (e == hipSuccess)
-        e = grid(g.iter, g.gen, reinterpret_cast<const void*>(k_generate_wave_batch), dim3(blocks), dim3(kLanes), a2);
-    if (e == hipSuccess)
-        e = grid(g.iter, g.ver, reinterpret_cast<const void*>(k_verify_wave_batch), dim3(8, n), dim3(kLanes), a2);
-    if (e == hipSuccess)
-        e = grid(g.iter, g.btw, reinterpret_cast<const void*>(k_between_batch), dim3((uint32_t)blocks_for(n, 256)),
-                 dim3(256), a2);
-    if (e == hipSuccess)
-        e = grid(g.close, g.gat, reinterpret_cast<const void*>(k_gather_ctr),
-                 dim3((uint32_t)blocks_for((uint64_t)n * C_NUM, 256)), dim3(256), a3);
+hipError_t set_step(StepGraphs& g, uint32_t nsegs, uint64_t tiles, uint32_t n) {
+    if (tiles == 0 || tiles > 0x7FFFFFFFull || n == 0) return hipErrorInvalidValue;
+    const Store* stores = g.d_stores;
+    const BSeg* segs = g.d_segs;
+    uint64_t tile0 = 0;
+    void* ag[] = {&stores, &segs, &nsegs, &tile0};
+    void* av[] = {&stores};
+    void* ab[] = {&stores, &n};
+    hipKernelNodeParams p =
+        node_params(reinterpret_cast<const void*>(k_generate_wave_batch), dim3((uint32_t)tiles), dim3(kLanes), ag);
+    hipError_t e = hipGraphExecKernelNodeSetParams(g.exec, g.gen, &p);
+    if (e == hipSuccess) {
+        p = node_params(reinterpret_cast<const void*>(k_verify_wave_batch), dim3(8, n), dim3(kLanes), av);
+        e = hipGraphExecKernelNodeSetParams(g.exec, g.ver, &p);
+    }
+    if (e == hipSuccess) {
+        p = node_params(reinterpret_cast<const void*>(k_between_batch), dim3((uint32_t)blocks_for(n, 256)), dim3(256),
+                        ab);
+        e = hipGraphExecKernelNodeSetParams(g.exec, g.btw, &p);
+    }
     return e;
 }
 
 void free_step_graphs(StepGraphs& g) {
-    if (g.iter) (void)hipGraphExecDestroy(g.iter);
-    if (g.close) (void)hipGraphExecDestroy(g.close);
-    if (g.g_iter) (void)hipGraphDestroy(g.g_iter);
-    if (g.g_close) (void)hipGraphDestroy(g.g_close);
-    g.iter = g.close = nullptr;
-    g.g_iter = g.g_close = nullptr;
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g.exec = nullptr;
+    g.graph = nullptr;
 }
+
 
 hipError_t launch_verify_deferred(const Store& s, hipStream_t st) {
     // records are the same for every generation kernel; rows of 2..64

@@ -1132,6 +1132,8 @@ struct Scheduler {
     // set) the same launches issued one by one
     StepGraphs graphs;
     bool use_graphs = true;
+    hipStream_t graph_stream = nullptr;  // where the graph was last replayed
+    bool graph_launched = false;
     bool trace = false;  // LTLF_TRACE set: one line per job event on stderr
     // small-pool statistics (reported with the trace): steps with small jobs,
     // their batched launches, wall time in those steps and, within it, time
@@ -1153,6 +1155,8 @@ struct Scheduler {
     static constexpr uint64_t kSubStaging = 4096;
 
     ~Scheduler() {
+        // a step that failed part-way may have left a replay in flight
+        if (graph_launched) (void)hipStreamSynchronize(graph_stream);
         free_step_graphs(graphs);
         for (Job* j : bigs) stop_worker(j);
         for (hipStream_t st : streams) {
@@ -2129,6 +2133,8 @@ struct Scheduler {
                 TRY_HIP(hipMemcpyAsync(d_segs, pieces.data(), sizeof(BSeg) * pieces.size(), hipMemcpyHostToDevice, s));
                 if (use_graphs) {
                     TRY_HIP(set_step(graphs, (uint32_t)pieces.size(), first, (uint32_t)live.size()));
+                    graph_stream = s;
+                    graph_launched = true;
                     TRY_HIP(hipGraphLaunch(graphs.exec, s));
                 } else {
                     TRY_HIP(launch_generate_batch(d_stores, d_segs, (uint32_t)pieces.size(), 0, first, s));

@@ -2,18 +2,21 @@
 
 Workload: the large problem of seed 1 (5 props, 512+512 traces, lengths
 16..64, 5,248-byte rows: the wave kernel) with every cost level enumerated to
-10 in the benchmark's workspace (exactly what bench.py times).  Levels 1..6
-are within the oracle's reach (about 13 s) and are compared exactly (counts,
-sorted sets and digests).  Levels 7..10 (~3.5e7 CMs) are beyond it, so for
-them the test checks properties that hold at any size on sampled rows: each
-sampled CM equals the CM of its own derivation re-evaluated from the
-definitions, that derivation costs exactly the level, the CM occurs in no
-level <= 6, and no two sampled CMs are equal.  Level counts and digests (the
+10 in the benchmark's workspace (exactly what bench.py times).  Levels 1..7
+are within the oracle's reach (about 1.5 minutes): levels 1..6 are compared
+exactly (counts, sorted sets and digests), level 7 (1.1e5 CMs of 5 KB) by
+count and by its set of 128-bit row keys (BLAKE2b of each exported row).  Levels 8..10 (~3.5e7 CMs) are beyond it, so for them the
+test checks properties that hold at any size on sampled rows: each sampled
+CM equals the CM of its own derivation re-evaluated from the definitions,
+that derivation costs exactly the level, the CM occurs in no level <= 7, and
+no two sampled CMs are equal.  Level counts and digests (the
 sets) must be identical over repeated runs, and the configuration's own solve
 (bound 16) must return a separating formula of the minimal cost the
 exhaustive run finds.
 """
 from __future__ import annotations
+
+import hashlib
 
 import numpy as np
 import pytest
@@ -29,7 +32,12 @@ from tests import digest
 pytestmark = pytest.mark.gpu
 
 BOUND = 10
-ORACLE_BOUND = 6
+ORACLE_BOUND = 7
+EXACT_BOUND = 6  # levels compared row by row; level 7 by count and row keys
+
+
+def key(row):
+    return hashlib.blake2b(np.ascontiguousarray(row).tobytes(), digest_size=16).digest()
 SAMPLES = 12
 
 
@@ -72,12 +80,15 @@ def test_counts_and_sets_repeatable_and_complete(big_run):
 def test_low_levels_equal_oracle(big_run, oracle_low):
     s, p, _, r = big_run
     o = oracle_low
-    assert o.status == oracle.NOT_FOUND and r.min_cost > ORACLE_BOUND
+    assert (o.status, o.min_cost) == (oracle.OK, r.min_cost)  # the minimum, 7, is within the oracle's reach
     assert r.level_counts[: ORACLE_BOUND + 1] == o.level_counts[: ORACLE_BOUND + 1]
     for c in range(1, ORACLE_BOUND + 1):
         want = o.export_level(c)
-        assert np.array_equal(sorted_rows(s.export_level(c)), sorted_rows(want)), c
-        assert r.level_digests[c] == digest.level_digest(want, p.lengths), c
+        if c <= EXACT_BOUND:
+            assert np.array_equal(sorted_rows(s.export_level(c)), sorted_rows(want)), c
+            assert r.level_digests[c] == digest.level_digest(want, p.lengths), c
+        else:
+            assert {key(x) for x in s.export_level(c)} == {key(x) for x in want}, c
     assert ev.separates(r.formula, p.traces, p.positive)
     assert ev.cost(r.formula) == r.min_cost
 
@@ -87,8 +98,8 @@ def test_high_levels_sampled(big_run, oracle_low):
     o = oracle_low
     low = set()
     for c in range(1, ORACLE_BOUND + 1):
-        lv = np.ascontiguousarray(o.export_level(c))
-        low.update(lv.view(np.dtype((np.void, lv.shape[1] * 8))).ravel().tolist())
+        for row in o.export_level(c):
+            low.add(key(row))
     rng = np.random.Generator(np.random.PCG64(2025))
     seen = set()
     for c in range(ORACLE_BOUND + 1, BOUND + 1):
@@ -100,7 +111,7 @@ def test_high_levels_sampled(big_run, oracle_low):
             assert ev.cost(f) == c, (c, i, f)
             want = ev.canonical_words(ev.characteristic_matrix(f, p.traces))
             assert tuple(int(x) for x in got) == tuple(want), (c, i, f)
-            assert got.tobytes() not in low, (c, i, f)
+            assert key(got) not in low, (c, i, f)
             assert got.tobytes() not in seen, (c, i, f)
             seen.add(got.tobytes())
 

@@ -1155,6 +1155,13 @@ struct Scheduler {
     static constexpr uint64_t kSubStaging = 4096;
 
     ~Scheduler() {
+        if (trace)  // the batch's or the server's small-pool summary
+            std::fprintf(stderr,
+                         "[ltlf] small pool: %llu steps, %u batched launches, %.1f ms in those steps (planning and "
+                         "moves %.1f, level close and finish %.1f), %.1f ms of it waiting for the device; admission "
+                         "%.1f ms\n",
+                         (unsigned long long)small_steps, launches, 1e3 * small_step_s, 1e3 * plan_s, 1e3 * close_s,
+                         1e3 * small_wait_s, 1e3 * admit_s);
         // a step that failed part-way may have left a replay in flight
         if (graph_launched) (void)hipStreamSynchronize(graph_stream);
         free_step_graphs(graphs);
@@ -2682,12 +2689,6 @@ ltlf_status ltlf_solve_batch(ltlf_ctx* c, uint32_t n, const ltlf_spec* specs, co
         }
         TRY(sc.step(s, nullptr));
     }
-    if (sc.trace)
-        std::fprintf(stderr,
-                     "[ltlf] small pool: %llu steps, %u batched launches, %.1f ms in those steps (planning and moves "
-                     "%.1f, level close and finish %.1f), %.1f ms of it waiting for the device; admission %.1f ms\n",
-                     (unsigned long long)sc.small_steps, sc.launches, 1e3 * sc.small_step_s, 1e3 * sc.plan_s,
-                     1e3 * sc.close_s, 1e3 * sc.small_wait_s, 1e3 * sc.admit_s);
     TRY_HIP(hipEventRecord(e1, s));
     TRY_HIP(hipEventSynchronize(e1));
     float ms = 0.f;

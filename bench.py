@@ -426,6 +426,9 @@ def main() -> int:
     ap.add_argument("--only-medium", action="store_true",
                     help="time the medium problem's steps only (profiling runs of the lane kernel); "
                          "prints that leg's figures, not the headline line")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="solve the batched configuration with ltlf_solve_batch only (a warm-up call, "
+                         "then one timed call; profiling runs); prints that call's figures")
     ap.add_argument("--cpu-bound", type=int, default=6,
                     help="oracle baseline on the headline problem to this cost (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -485,6 +488,22 @@ def main() -> int:
         return 0
     ws = int(args.workspace_gb * (1 << 30)) if args.workspace_gb > 0 else large_workspace_bytes(free)
     log(f"[bench] workspace {ws / (1 << 30):.1f} GiB of {free / (1 << 30):.1f} GiB free")
+    if args.only_batched:
+        synth = m.Synthesizer(device=dev, workspace_bytes=ws)
+        if not args.no_autotune:
+            synth.autotune()
+        ps = workload.batched(1, args.batched)
+        synth.solve_batch(ps, flags=m.FLAG_DIGEST)  # warm-up
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        rs = synth.solve_batch(ps, flags=m.FLAG_DIGEST)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - a
+        print(json.dumps({"batched_only": {"problems": len(ps), "wall_ms": round(wall * 1e3, 1),
+                                           "problems_per_s": round(len(ps) / wall, 2),
+                                           "ok": sum(r.status == m.ltlf.OK for r in rs)}}), flush=True)
+        synth.close()
+        return 0
     synth = m.Synthesizer(device=dev, workspace_bytes=ws)
     p = workload.large(1)
     synth.load(p)

@@ -2236,15 +2236,18 @@ __global__ void k_encode(const uint32_t* letters, const uint32_t* lengths, const
         if ((uint64_t)seg_off[m + 1] <= lo) a = m + 1;
         else b = m;
     }
+    // trace t's positions k = 0..n-1 sit at bits seg_off[t] + n - 1 - k (the
+    // guard at seg_off[t] + n stays clear): only the bits inside this word
+    // are visited
     uint32_t vw = 0, sw = 0, pw = 0;
     for (uint32_t t = a; t < n_traces && (uint64_t)seg_off[t] < hi; ++t) {
+        const uint64_t seg = seg_off[t];
         const uint32_t n = lengths[t];
-        for (uint32_t k = 0; k < n; ++k) {
-            const uint64_t bit = (uint64_t)seg_off[t] + (n - 1 - k);
-            if (bit < lo || bit >= hi) continue;
+        const uint64_t b0 = seg > lo ? seg : lo, b1 = seg + n < hi ? seg + n : hi;
+        for (uint64_t bit = b0; bit < b1; ++bit) {
             const uint32_t m = 1u << (uint32_t)(bit - lo);
             vw |= m;
-            if (k == 0) {
+            if (bit == seg + n - 1) {  // position 0
                 sw |= m;
                 if (positive[t]) pw |= m;
             }
@@ -2256,10 +2259,11 @@ __global__ void k_encode(const uint32_t* letters, const uint32_t* lengths, const
     for (uint32_t p = 0; p < n_props; ++p) {
         uint32_t aw = 0;
         for (uint32_t t = a; t < n_traces && (uint64_t)seg_off[t] < hi; ++t) {
+            const uint64_t seg = seg_off[t];
             const uint32_t n = lengths[t];
-            for (uint32_t k = 0; k < n; ++k) {
-                const uint64_t bit = (uint64_t)seg_off[t] + (n - 1 - k);
-                if (bit < lo || bit >= hi) continue;
+            const uint64_t b0 = seg > lo ? seg : lo, b1 = seg + n < hi ? seg + n : hi;
+            for (uint64_t bit = b0; bit < b1; ++bit) {
+                const uint32_t k = (uint32_t)(seg + n - 1 - bit);
                 if ((letters[pos_off[t] + k] >> p) & 1u) aw |= 1u << (uint32_t)(bit - lo);
             }
         }

@@ -2724,8 +2724,22 @@ hipError_t launch_digest(const uint32_t* rows, uint32_t Wp, uint64_t first, uint
                          unsigned long long* out, hipStream_t st) {
     if (n == 0) return hipSuccess;
     const uint32_t nq = Wp / 4;
+    // lanes per row: rows of up to 8 chunks one pass of the next power of
+    // two; wider rows the group of 8..64 lanes (128 B or more contiguous per
+    // pass) that leaves the fewest lanes idle on a row's last pass (ties: the
+    // larger group)
     uint32_t G = 1;
-    while (G < nq && G < 64) G <<= 1;
+    while (G < nq && G < 8) G <<= 1;
+    if (nq > 8) {
+        uint64_t best = ~0ull;
+        for (uint32_t g = 8; g <= 64; g <<= 1) {
+            const uint64_t slots = (uint64_t)g * ((nq + g - 1) / g);
+            if (slots <= best) {
+                best = slots;
+                G = g;
+            }
+        }
+    }
     const uint64_t groups = n;  // one row per group per iteration
     uint64_t blocks = (groups * G + 255) / 256;
     if (blocks > 8192) blocks = 8192;

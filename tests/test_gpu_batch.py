@@ -9,6 +9,7 @@ and costs the minimal cost.
 """
 from __future__ import annotations
 
+import gc
 import time
 
 import pytest
@@ -278,6 +279,8 @@ def test_batched_configuration_equals_one_by_one():
     import bench
 
     t0 = time.perf_counter()
+    gc.collect()
+    torch.cuda.empty_cache()  # workspaces of earlier tests, cached by torch
     free, _ = torch.cuda.mem_get_info(0)
     ws = int(min(free * 0.8, 200 * (1 << 30)))
     ps = workload.batched(1, 256)

@@ -13,6 +13,7 @@ identical over repeated runs.
 """
 from __future__ import annotations
 
+import gc
 import numpy as np
 import pytest
 import torch
@@ -36,6 +37,8 @@ def sorted_rows(a):
 
 @pytest.fixture(scope="module")
 def big_run():
+    gc.collect()
+    torch.cuda.empty_cache()  # workspaces of earlier tests, cached by torch
     free, _ = torch.cuda.mem_get_info(0)
     ws = int(min(free * 0.6, 120 << 30))  # 3.3e8 rows x (160 + 16 + 16) bytes + lists
     print(f"[fullsize] workspace {ws >> 30} GiB", flush=True)

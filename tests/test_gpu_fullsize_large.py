@@ -16,6 +16,7 @@ exhaustive run finds.
 """
 from __future__ import annotations
 
+import gc
 import hashlib
 
 import numpy as np
@@ -47,6 +48,8 @@ def sorted_rows(a):
 
 @pytest.fixture(scope="module")
 def big_run():
+    gc.collect()
+    torch.cuda.empty_cache()  # workspaces of earlier tests, cached by torch
     free, _ = torch.cuda.mem_get_info(0)
     ws = bench.large_workspace_bytes(free)
     print(f"[fullsize-large] workspace {ws >> 30} GiB", flush=True)
